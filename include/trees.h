@@ -1,0 +1,199 @@
+/*
+ * libtrees -- the TREES epoch runtime (Hechtman, Hilton and Sorin, "TREES: A
+ * CPU/GPU Task-Parallel Runtime with Explicit Epoch Synchronization") for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * A program is a set of task types whose bodies use fork / join / emit
+ * (Section 4.3.2).  The runtime keeps every task in a task vector in HBM and
+ * runs the program as a sequence of bulk-synchronous epochs (Section 4.3):
+ * Phase 1 picks the next epoch's range of task-vector entries, Phase 2 runs
+ * every task of the range in parallel on the GPU, Phase 3 pushes the ranges
+ * created by forks and joins.  Many independent task trees may share the
+ * epochs of one context.
+ *
+ * Conventions of the whole interface:
+ *  - every function returns a trees_status (0 = success, < 0 = error) unless
+ *    stated otherwise; no C++ exception crosses this boundary;
+ *  - "device pointer" means memory of the context's GPU (hipMalloc'd or a
+ *    PyTorch CUDA/HIP tensor's data pointer); the caller owns it;
+ *  - trees_last_error() returns a message for the last failed call.
+ */
+#ifndef TREES_H
+#define TREES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct trees_ctx trees_ctx;
+typedef int32_t trees_status;
+
+enum {
+  TREES_OK = 0,
+  TREES_E_INVALID = -1,   /* bad argument or program */
+  TREES_E_NOMEM = -2,     /* the tree's task-vector arena does not fit in the budget now */
+  TREES_E_OVERFLOW = -3,  /* a tree needed more task-vector entries than reserved */
+  TREES_E_PENDING = -4,   /* the tree has not finished yet */
+  TREES_E_DEVICE = -5,    /* a HIP runtime call failed */
+  TREES_E_ABORTED = -6,   /* the run stopped on trees_abort or its epoch budget */
+  TREES_E_STATE = -7,     /* call not allowed in the context's current state */
+  TREES_E_ENCODING = -8,  /* a task-vector entry held a code outside its epoch's window */
+  TREES_E_STACK = -9      /* a tree exceeded the per-tree stack depth (128 records) */
+};
+
+/* Scheduler: how epochs are sequenced.
+ *  PLAIN      one kernel launch per epoch of one tree, Phases 1 and 3 on the
+ *             host after copying back nextFreeCore and the join count
+ *             (Sections 5.2.2-5.2.4); trees run one after another.
+ *  GRAPH      all live trees share each epoch; Phases 1 and 3 run on the
+ *             device; a captured chain of `graph_chunk` epoch launches is
+ *             replayed until no tree is live.
+ *  PERSISTENT all live trees share each epoch inside one co-resident
+ *             (cooperative) launch with a device grid barrier per epoch.
+ *  AUTO       PERSISTENT or GRAPH as the tuned configuration says. */
+typedef enum {
+  TREES_SCHED_PLAIN = 0,
+  TREES_SCHED_GRAPH = 1,
+  TREES_SCHED_PERSISTENT = 2,
+  TREES_SCHED_AUTO = 3
+} trees_sched;
+
+enum {
+  TREES_F_TRACE = 1u,  /* record per-epoch (CEN, range, valid, forks, joins) per tree */
+  TREES_F_DEBUG = 2u
+};
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(trees_config) */
+  int32_t device;         /* HIP device ordinal */
+  void *stream;           /* hipStream_t to run on; NULL = a stream owned by the context */
+  void *arena_base;       /* device pointer to the task-vector budget; NULL = the library allocates */
+  uint64_t arena_bytes;   /* budget in bytes (28 bytes per task-vector entry) */
+  int32_t max_trees;      /* tree slots; 0 = 4096 */
+  int32_t sched;          /* trees_sched */
+  int32_t wg_size;        /* 256, 512 or 1024; 0 = 256 (the paper's work-group size, Section 5.1.1) */
+  int32_t blocks_per_cu;  /* work-groups per CU for GRAPH/PERSISTENT grids; 0 = automatic (PERSISTENT
+                           * never exceeds 3/4 of the runtime's occupancy figure) */
+  int32_t graph_chunk;    /* epochs per captured graph; 0 = 8 */
+  uint32_t flags;         /* TREES_F_* */
+  double timeout_s;       /* PERSISTENT barrier spin limit in seconds; 0 = 60 */
+} trees_config;
+
+/* Built-in task programs (their task bodies are compiled into the library). */
+typedef enum {
+  TREES_PROG_FIB_I32 = 1,   /* naive Fibonacci, 32-bit sums (Section 6.2) */
+  TREES_PROG_FIB_I64 = 2,   /* naive Fibonacci, 64-bit sums */
+  TREES_PROG_MSORT_U32 = 3, /* split-in-halves merge sort of uint32 keys (Section 6.4) */
+  TREES_PROG_NQUEENS = 4,   /* N-queens solution count, one task per partial placement (Section 6.5) */
+  TREES_PROG_BFS_CSR = 5    /* task-per-vertex breadth-first search over CSR (Section 6.3) */
+} trees_builtin;
+
+typedef struct {
+  void *ptr;       /* device pointer, caller-owned */
+  uint64_t bytes;
+} trees_buf;
+
+typedef struct {
+  int32_t status;          /* TREES_OK, TREES_E_PENDING or the tree's error */
+  uint32_t epochs;         /* epochs the tree executed (its critical path, Section 4.4.1) */
+  uint64_t tasks;          /* valid task executions, join continuations included (its work) */
+  uint64_t launched;       /* lanes launched over all its epochs (valid + invalid entries) */
+  uint64_t peak_entries;   /* high-water mark of nextFreeCore (its space, Section 4.4.2) */
+  int64_t start_epoch;     /* global epoch of its first epoch (batched schedulers) */
+  int64_t done_epoch;      /* global epoch in which it finished */
+} trees_tree_stats;
+
+typedef struct {
+  uint64_t global_epochs;  /* epochs executed by this run */
+  uint64_t tasks;          /* valid tasks of trees that finished in this run */
+  int32_t stop_reason;     /* 1 drained, 2 epoch budget, 3 abort, 4 barrier timeout */
+  int32_t live;            /* trees still live after the run */
+  double seconds;          /* host wall time of the run */
+  int32_t grid;            /* work-groups of the batched launch (0 for PLAIN) */
+  int32_t api_blocks_per_cu; /* the runtime's occupancy figure for that kernel */
+} trees_run_stats;
+
+typedef struct {
+  int32_t epoch, cen, b, e, launched, valid, forks, joins, nfc;
+} trees_epoch_rec;
+
+/* Create a context on cfg->device.  *out receives the context.  Allocates the
+ * task vector (unless cfg->arena_base is given), the per-tree descriptors,
+ * stacks and scheduler state in device memory.  Errors: INVALID, DEVICE,
+ * NOMEM. */
+trees_status trees_create(const trees_config *cfg, trees_ctx **out);
+
+/* Destroy a context and free what the library allocated (not caller buffers). */
+void trees_destroy(trees_ctx *ctx);
+
+/* Message describing the last error of ctx (or of trees_create when ctx is NULL). */
+const char *trees_last_error(const trees_ctx *ctx);
+
+/* Register a built-in program.  Its task types receive a slice of the
+ * context's global type ids 1..NumTaskTypes (the encoding of Section 5.1.2
+ * needs NumTaskTypes fixed before the first epoch), so every program must be
+ * registered before the first trees_submit (else STATE).  Registering a kind
+ * twice returns the same id.  *out_prog receives the program id. */
+trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_prog);
+
+/* Submit one task tree: its root task is placed in entry 0 of a fresh arena of
+ * the task vector and runs in epoch 0 (Section 5.2.1).
+ *   FIB_I32 / FIB_I64: args = {n}, 0 <= n <= 43; no buffers.
+ *   NQUEENS:           args = {n}, 1 <= n <= 14; no buffers.
+ *   MSORT_U32:         args = {N}, 0 <= N < 2^31; bufs = {keys[N] (sorted in place), tmp[N]}
+ *                      (the pointers may be NULL when N = 0).
+ *   BFS_CSR:           args = {V, source}; bufs = {row_ptr[V+1], col_idx[E], depth[V] (out)}
+ *                      int32 CSR; depth receives hop counts, -1 = unreachable.
+ * The arena is sized to the exact task-vector bound of the tree; if it does
+ * not fit in the free budget the call returns NOMEM and changes nothing (the
+ * caller may retry once other trees have been collected).  Buffers must stay
+ * alive and unmodified until trees_results returns OK for the tree.  The tree
+ * becomes live at the next trees_run.  *out_tree receives its id. */
+trees_status trees_submit(trees_ctx *ctx, int32_t prog, const int64_t *args, int32_t nargs,
+                          const trees_buf *bufs, int32_t nbufs, uint64_t *out_tree);
+
+/* Run epochs until no tree is live, trees_abort is called, or max_epochs
+ * epochs have run (< 0: no limit).  Blocking.  A tree that is stopped by the
+ * budget keeps its state and continues at the next trees_run.  out may be
+ * NULL. */
+trees_status trees_run(trees_ctx *ctx, int64_t max_epochs, uint32_t flags, trees_run_stats *out);
+
+/* Result of one tree.  Returns PENDING while it is live, its error if it
+ * failed, OK otherwise.  *out_value receives the root's emitted value (fib:
+ * F(n); nqueens: the count; msort and BFS: 0, their output is in the
+ * caller's buffers).  OK and errors release the tree's slot and arena: the id
+ * is invalid afterwards.  Either output pointer may be NULL. */
+trees_status trees_results(trees_ctx *ctx, uint64_t tree, int64_t *out_value,
+                           trees_tree_stats *out_stats);
+
+/* Per-epoch records of a tree run with TREES_F_TRACE (at most 256 epochs).
+ * Copies up to cap records into out and stores the count in *n.  Call before
+ * trees_results releases the tree. */
+trees_status trees_trace(trees_ctx *ctx, uint64_t tree, trees_epoch_rec *out, int32_t cap,
+                         int32_t *n);
+
+/* Request that a running trees_run stop at the next epoch boundary.  Safe to
+ * call from another host thread. */
+trees_status trees_abort(trees_ctx *ctx);
+
+/* Change the scheduler and launch shape for later runs (used by the tuner). */
+trees_status trees_set_schedule(trees_ctx *ctx, int32_t sched, int32_t wg_size,
+                                int32_t blocks_per_cu, int32_t graph_chunk);
+
+/* Exact task-vector entries a tree of `kind` with `args` can occupy at once
+ * (the admission size).  Host-only. */
+trees_status trees_tv_bound(int32_t kind, const int64_t *args, int32_t nargs, int64_t *entries);
+
+/* Free task-vector entries of the budget (for admission decisions). */
+int64_t trees_free_entries(const trees_ctx *ctx);
+
+/* Number of submitted trees not yet released by trees_results. */
+int32_t trees_num_trees(const trees_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREES_H */

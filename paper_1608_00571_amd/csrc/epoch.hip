@@ -1,0 +1,781 @@
+// TREES epoch kernels for CDNA4 (gfx950).
+//
+// One launch of the sweep executes Phase 2 of an epoch (Section 5.2.3) for
+// every work item: a work item is one task-vector entry of one tree's
+// current range.  Each lane reads its entry, decodes epoch number and task
+// type (Section 5.1.2 and its footnote: code = epoch * NTT + type, runnable
+// iff CEN*NTT + 1 <= code <= (CEN+1)*NTT), runs the body of its type and
+// performs fork / join / emit (Section 4.3.2):
+//
+//  * fork: children of a work-group are allocated together -- a wavefront
+//    prefix sum by ballot + mbcnt, wavefront totals combined in LDS, and ONE
+//    device-scope atomic add on the tree's nextFreeCore per work-group and
+//    tree (the paper takes one atomic per wavefront through a local-memory
+//    reduction, Section 5.2.3); children of one parent are contiguous, and
+//    children are written with structure-of-arrays stores;
+//  * join: the lane rewrites its own entry with the continuation at the same
+//    epoch number and counts one join for its tree;
+//  * emit: the lane stores its value in r[i] and marks the entry invalid.
+//
+// Phase 3 and Phase 1 (Sections 5.2.2 and 5.2.4) run on the device in the
+// batched forms: the work-group that retires the last work item of a tree in
+// an epoch pushes that tree's join and fork ranges, pops its next range and
+// resets its counters; the last work-group to reach the epoch barrier turns
+// the per-tree ranges into the next epoch's work list with one exclusive
+// scan.  The plain form leaves Phases 1 and 3 to the host, one launch per
+// epoch, as the paper does.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bodies.h"
+#include "prims.h"
+#include "trees_dev.h"
+
+namespace trees {
+
+enum : int { ACT_NONE = 0, ACT_EMIT = 1, ACT_JOIN = 2, ACT_FINISH = 3 };
+
+template <int WG>
+struct Lds {
+  int32_t kfirst;          // first work-list entry of the chunk
+  int32_t nseg;            // entries (trees) the chunk touches
+  uint32_t off0;           // wl_off[kfirst]
+  int32_t flag;            // scratch broadcast
+  uint32_t gen;
+  int32_t sink;            // destination of atomics whose completion must be awaited
+  int32_t tflag;
+  uint32_t win[WG];        // wl_off[kfirst + 1 + t]
+  int32_t seg_slot[WG];    // tree slot of segment s
+  int32_t seg_cnt[WG];     // children requested per segment (LDS atomics)
+  int32_t seg_base[WG];    // arena-relative first child per segment (-1: overflow)
+  int32_t seg_join[WG];
+  int32_t seg_valid[WG];
+  int32_t scan_tmp[WG / 64 + 1];
+  int32_t v_row[WG];       // VISIT: first arc of the lane's vertex
+  int32_t v_pre[WG];       // VISIT: exclusive prefix of out-degrees
+  int32_t v_seg[WG];
+  int32_t v_cen[WG];
+};
+
+// ---------------------------------------------------------------------------
+// Segment helpers
+// ---------------------------------------------------------------------------
+
+// arr[seg] += v for every lane, one LDS atomic per wavefront when the whole
+// wavefront belongs to one segment.  v < 2^16.
+__device__ __forceinline__ void seg_add(int32_t *arr, int seg, int v) {
+  uint64_t m = ballot64(v > 0);
+  if (!m) return;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  int s0 = __shfl(seg, leader, 64);
+  if (__all(v == 0 || seg == s0)) {
+    int tot = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) tot += __popcll(ballot64((v >> b) & 1)) << b;
+    if (lane_id() == leader) atomicAdd(&arr[s0], tot);
+  } else if (v > 0) {
+    atomicAdd(&arr[seg], v);
+  }
+}
+
+// Co-operative fork allocation (Tenet 2).  Every thread of the work-group
+// calls it; lane asks for nk (< 16) children of the tree of segment `seg`.
+// Returns the arena-relative index of the lane's first child, or -1 if the
+// tree's arena overflowed.
+template <int WG, bool MULTI>
+__device__ __forceinline__ int32_t wg_alloc(const DevCtx &C, Lds<WG> &L, int seg, int nk,
+                                            const PlainArgs &P) {
+  int off = 0;
+  uint64_t m = ballot64(nk > 0);
+  if (m) {
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int s0 = __shfl(seg, leader, 64);
+    if (__all(nk == 0 || seg == s0)) {
+      int tot;
+      int pre = wave_prefix_small<4>(nk, &tot);
+      int wb = 0;
+      if (lane_id() == leader) wb = atomicAdd(&L.seg_cnt[s0], tot);
+      wb = __shfl(wb, leader, 64);
+      off = wb + pre;
+    } else if (nk > 0) {
+      off = atomicAdd(&L.seg_cnt[seg], nk);
+    }
+  }
+  __syncthreads();
+  const int nseg = L.nseg;
+  for (int s = threadIdx.x; s < nseg; s += WG) {
+    int c = L.seg_cnt[s];
+    int b = 0;
+    if (c > 0) {
+      L.seg_cnt[s] = 0;
+      if (MULTI) {
+        int slot = L.seg_slot[s];
+        b = add_agent(&C.hot[slot].nfc, (int32_t)c);
+        if ((int64_t)b + c > (int64_t)C.ts[slot].cap) {
+          L.sink = or_agent(&C.hot[slot].flags, (int32_t)TF_OVERFLOW);
+          b = -1;
+        }
+      } else {
+        b = add_agent(&C.plain->forks[P.par], (int32_t)c);
+        if ((int64_t)P.nfc0 + b + c > (int64_t)C.ts[P.slot].cap) {
+          L.sink = or_agent(&C.plain->flags[P.par], (int32_t)TF_OVERFLOW);
+          b = -1;
+        } else {
+          b += P.nfc0;
+        }
+      }
+    }
+    L.seg_base[s] = b;
+  }
+  __syncthreads();
+  if (nk == 0) return 0;
+  int b = L.seg_base[seg];
+  return b < 0 ? -1 : b + off;
+}
+
+// ---------------------------------------------------------------------------
+// Phase 3 + Phase 1 of one tree (device form).  Run by one lane of the
+// work-group that retired the tree's last work item of the epoch.
+// ---------------------------------------------------------------------------
+__device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
+  TreeState *T = &C.st[slot];
+  TreeHot *H = &C.hot[slot];
+  const int32_t nfc = ld_agent(&H->nfc);
+  const int32_t flags = ld_agent(&H->flags);
+  const int32_t cen = T->cen, b = T->b, e = T->e, old = T->old;
+  int32_t sp = T->sp;
+  const int32_t forks = nfc - old;
+  const int32_t ep = T->epochs;
+  T->epochs = ep + 1;
+  T->launched += e - b;
+  T->tasks += (int64_t)forks + joins;
+  if (nfc > T->peak) T->peak = nfc;
+  if (C.trace_on && ep < kTraceMax) {
+    TraceRec q;
+    q.epoch = ep; q.cen = cen; q.b = b; q.e = e; q.launched = e - b;
+    q.valid = ld_agent(&H->valid); q.forks = forks; q.joins = (int32_t)joins; q.nfc = nfc;
+    C.trace[(size_t)slot * kTraceMax + ep] = q;
+    T->ntrace = ep + 1;
+  }
+  int4 *stk = C.stack + (size_t)slot * kStackMax;
+  int err = 0;
+  if (flags & TF_OVERFLOW) err = -3;        // TREES_E_OVERFLOW
+  else if (flags & TF_ENCODING) err = -8;   // TREES_E_ENCODING
+  int4 top;
+  bool have = false;
+  if (!err) {
+    // Phase 3: the join range first, then the forked range on top (LIFO).
+    if (joins) {
+      if (sp >= kStackMax) err = -9;        // TREES_E_STACK
+      else stk[sp++] = make_int4(cen, b, e, nfc);
+    }
+    if (!err) {
+      if (forks) { top = make_int4(cen + 1, old, nfc, nfc); have = true; }
+      else if (sp > 0) { top = stk[--sp]; have = true; }
+    }
+  }
+  if (err || !have) {  // empty stack: the tree is complete (Section 4.3.3)
+    T->status = TS_DONE;
+    T->err = err;
+    T->sp = sp;
+    C.t_len[slot] = 0;
+    int j = add_agent(&C.hdr->done_count, 1);
+    C.done_list[j] = slot;
+    return;
+  }
+  // Phase 1 of the tree's next epoch: nextFreeCore returns to the value it
+  // had when the popped range was pushed.
+  T->cen = top.x; T->b = top.y; T->e = top.z; T->old = top.w; T->sp = sp;
+  st_agent(&H->nfc, top.w);
+  st_agent(&H->done, (uint64_t)0);
+  st_agent(&H->valid, 0);
+  C.t_len[slot] = top.z - top.y;
+  C.t_cen[slot] = top.x;
+  C.t_b[slot] = top.y;
+}
+
+// ---------------------------------------------------------------------------
+// One chunk of WG work items.
+// ---------------------------------------------------------------------------
+template <int WG, uint32_t OPS, bool MULTI>
+__device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, int32_t nL,
+                          const PlainArgs &P) {
+  const int tid = threadIdx.x;
+  const uint32_t w = w0 + tid;
+  const bool has = w < S;
+  int seg = -1;
+  int slot = 0;
+  int32_t cen = 0;
+  int64_t i = 0;
+
+  // ---- locate the lane's tree and task-vector entry --------------------
+  if (MULTI) {
+    if (nL == 1) {
+      if (tid == 0) {
+        L.kfirst = 0; L.nseg = 1; L.off0 = 0; L.win[0] = S; L.seg_slot[0] = C.wl_tree[0];
+      }
+    } else {
+      if (tid < 64) {
+        // 64-ary search for the last entry whose offset is <= w0.
+        int lo = 0, hi = nL;
+        while (hi - lo > 1) {
+          int step = (hi - lo + 63) >> 6;
+          int p = lo + tid * step;
+          bool ok = p < hi && C.wl_off[p] <= w0;
+          int j = __popcll(ballot64(ok)) - 1;
+          lo = lo + j * step;
+          hi = min(lo + step, hi);
+        }
+        if (tid == 0) { L.kfirst = lo; L.off0 = C.wl_off[lo]; }
+      }
+      __syncthreads();
+      const int kf = L.kfirst;
+      const int kk = kf + 1 + tid;
+      L.win[tid] = (kk <= nL) ? C.wl_off[kk] : 0xFFFFFFFFu;
+      __syncthreads();
+      if (tid == 0) {
+        // number of entries the chunk touches
+        uint32_t wl = min(w0 + (uint32_t)WG, S) - 1;
+        int lo2 = 0, hi2 = WG;
+        while (lo2 < hi2) { int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= wl) lo2 = mid + 1; else hi2 = mid; }
+        L.nseg = lo2 + 1;
+      }
+      __syncthreads();
+      if (tid < L.nseg) L.seg_slot[tid] = C.wl_tree[kf + tid];
+    }
+    __syncthreads();
+    if (has) {
+      int s = 0;
+      if (nL > 1) {
+        int lo2 = 0, hi2 = WG;
+        while (lo2 < hi2) { int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= w) lo2 = mid + 1; else hi2 = mid; }
+        s = lo2;
+      }
+      seg = s;
+      const int k = L.kfirst + s;
+      slot = L.seg_slot[s];
+      cen = C.wl_cen[k];
+      const uint32_t offk = (s == 0) ? L.off0 : L.win[s - 1];
+      i = C.wl_start[k] + (int64_t)(w - offk);
+    }
+  } else {
+    if (tid == 0) { L.kfirst = 0; L.nseg = 1; L.seg_slot[0] = P.slot; }
+    __syncthreads();
+    slot = P.slot;
+    cen = P.cen;
+    if (has) { seg = 0; i = C.ts[slot].base + P.b + (int64_t)w; }
+  }
+
+  // ---- fetch and decode --------------------------------------------------
+  const int32_t ntt = C.ntt;
+  int op = OP_NONE;
+  int32_t gtype = 0;
+  if (has) {
+    const int32_t code = C.code[i];
+    if (code != 0) {
+      gtype = code - cen * ntt;
+      if (gtype >= 1 && gtype <= ntt) op = C.op_of_type[gtype];
+      // an entry outside the epoch's encoding window, or of a type this
+      // kernel was not built for, is an error of its tree
+      if (op == OP_NONE || (opbit(op) & OPS) == 0) {
+        op = OP_NONE;
+        const int32_t prev = or_agent(MULTI ? &C.hot[slot].flags : &C.plain->flags[P.par],
+                                      (int32_t)TF_ENCODING);
+        if (prev < 0) L.sink = prev;
+      }
+    }
+  }
+
+  // ---- task body: decide children, join or emit ---------------------------
+  int nk = 0, act = ACT_NONE;
+  int64_t val = 0;
+  int32_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+  int64_t tb = 0;     // arena base of the lane's tree
+  int32_t tbase = 0;  // global type id of the program's first type
+  if (op != OP_NONE) {
+    const TreeStatic *T = &C.ts[slot];
+    tb = T->base;
+    tbase = T->tbase;
+    switch (op) {
+      case OP_FIB32:
+      case OP_FIB64: {
+        const int32_t n = C.a0[i];
+        if (n < 2) { act = ACT_EMIT; val = n; }
+        else { act = ACT_JOIN; nk = 2; x0 = n; }
+      } break;
+      case OP_SUM32: {
+        const int32_t c = C.a0[i];
+        const uint32_t s = (uint32_t)C.r[tb + c] + (uint32_t)C.r[tb + c + 1];
+        act = ACT_EMIT; val = (int64_t)(int32_t)s;
+      } break;
+      case OP_SUM64: {
+        const int32_t c = C.a0[i];
+        act = ACT_EMIT; val = C.r[tb + c] + C.r[tb + c + 1];
+      } break;
+      case OP_Q: {
+        const int32_t n = T->p0;
+        const int32_t row = C.a0[i];
+        if (row == n) { act = ACT_EMIT; val = 1; break; }
+        const uint32_t full = (1u << n) - 1u;
+        const uint32_t cols = (uint32_t)C.a1[i], ld = (uint32_t)C.a2[i], rd = (uint32_t)C.a3[i];
+        const uint32_t avail = ~(cols | ld | rd) & full;
+        if (!avail) { act = ACT_EMIT; val = 0; break; }
+        act = ACT_JOIN; nk = __popc(avail);
+        x0 = row; x1 = (int32_t)cols; x2 = (int32_t)ld; x3 = (int32_t)rd;
+      } break;
+      case OP_QSUM: {
+        const int32_t c = C.a0[i], k = C.a1[i];
+        int64_t s = 0;
+        for (int32_t j = 0; j < k; ++j) s += C.r[tb + c + j];
+        act = ACT_EMIT; val = s;
+      } break;
+      case OP_MS: {
+        const int32_t lo = C.a0[i], hi = C.a1[i], d = C.a2[i];
+        if (hi - lo <= kLeaf) {
+          ms_leaf((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, lo, hi, d);
+          act = ACT_FINISH;
+        } else {
+          act = ACT_JOIN; nk = 2; x0 = lo; x1 = hi; x2 = d;
+        }
+      } break;
+      case OP_MERGE: {
+        ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, C.a0[i], C.a1[i], C.a2[i]);
+        act = ACT_FINISH;
+      } break;
+      case OP_VISIT:
+        act = ACT_FINISH;   // its arcs are expanded co-operatively below
+        break;
+      default: break;
+    }
+  }
+
+  // ---- fork: co-operative slot allocation, structure-of-arrays writes ------
+  const int32_t cb = wg_alloc<WG, MULTI>(C, L, seg, nk, P);
+  if (nk > 0 && cb >= 0) {
+    const int64_t c = tb + cb;
+    const int32_t nxt = (cen + 1) * ntt + tbase;   // code of local type 1, next epoch
+    if (op == OP_FIB32 || op == OP_FIB64) {
+      C.code[c] = nxt; C.a0[c] = x0 - 1;
+      C.code[c + 1] = nxt; C.a0[c + 1] = x0 - 2;
+    } else if (op == OP_Q) {
+      const int32_t n = C.ts[slot].p0;
+      const uint32_t full = (1u << n) - 1u;
+      const uint32_t cols = (uint32_t)x1, ld = (uint32_t)x2, rd = (uint32_t)x3;
+      uint32_t avail = ~(cols | ld | rd) & full;
+      int64_t cc = c;
+      while (avail) {
+        const uint32_t bit = avail & (0u - avail);
+        avail ^= bit;
+        C.code[cc] = nxt;
+        C.a0[cc] = x0 + 1;
+        C.a1[cc] = (int32_t)(cols | bit);
+        C.a2[cc] = (int32_t)(((ld | bit) << 1) & full);
+        C.a3[cc] = (int32_t)((rd | bit) >> 1);
+        ++cc;
+      }
+    } else if (op == OP_MS) {
+      const int32_t mid = x0 + (x1 - x0) / 2;
+      C.code[c] = nxt; C.a0[c] = x0; C.a1[c] = mid; C.a2[c] = x2 + 1;
+      C.code[c + 1] = nxt; C.a0[c + 1] = mid; C.a1[c + 1] = x1; C.a2[c + 1] = x2 + 1;
+    }
+  }
+
+  // ---- join / emit: writes to the lane's own entry -------------------------
+  if (act == ACT_EMIT) {
+    C.r[i] = val;
+    C.code[i] = 0;
+  } else if (act == ACT_FINISH) {
+    C.code[i] = 0;
+  } else if (act == ACT_JOIN) {
+    C.code[i] = cen * ntt + tbase + 1;   // local type 2: SUM / QSUM / MERGE
+    if (op != OP_MS) {
+      C.a0[i] = cb;
+      if (op == OP_Q) C.a1[i] = nk;
+    }
+  }
+
+  // ---- BFS: co-operative expansion of the VISIT lanes' arcs ----------------
+  if (OPS & OPS_BFS) {
+    const bool isv = (op == OP_VISIT);
+    if (__syncthreads_or(isv)) {
+      int32_t deg = 0, row = 0;
+      if (isv) {
+        const int32_t v = C.a0[i];
+        const int32_t *rp = (const int32_t *)C.ts[slot].ptr0;
+        row = rp[v];
+        deg = rp[v + 1] - row;
+      }
+      int tot;
+      const int pre = wg_excl_scan<WG>(deg, L.scan_tmp, &tot);
+      L.v_row[tid] = row;
+      L.v_pre[tid] = pre;
+      L.v_seg[tid] = seg;
+      L.v_cen[tid] = cen;
+      __syncthreads();
+      for (int e0 = 0; e0 < tot; e0 += WG) {
+        const int e = e0 + tid;
+        int claim = 0, sseg = -1;
+        int32_t u = 0, scen = 0;
+        const TreeStatic *ST = nullptr;
+        if (e < tot) {
+          int lo = 0, hi = WG;   // last lane l with v_pre[l] <= e
+          while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (L.v_pre[mid] <= e) lo = mid; else hi = mid; }
+          sseg = L.v_seg[lo];
+          scen = L.v_cen[lo];
+          ST = &C.ts[L.seg_slot[sseg]];
+          u = ((const int32_t *)ST->ptr1)[L.v_row[lo] + (e - L.v_pre[lo])];
+          int32_t *depth = (int32_t *)ST->ptr2;
+          if (depth[u] == -1 && atomicCAS(&depth[u], -1, scen + 1) == -1) claim = 1;
+        }
+        const int32_t vb = wg_alloc<WG, MULTI>(C, L, sseg, claim, P);
+        if (claim && vb >= 0) {
+          const int64_t c = ST->base + vb;
+          C.code[c] = (scen + 1) * ntt + ST->tbase;
+          C.a0[c] = u;
+        }
+      }
+    }
+  }
+
+  // ---- per-tree bookkeeping: joins, valid tasks, retired items ------------
+  seg_add(L.seg_join, seg, act == ACT_JOIN ? 1 : 0);
+  if (C.trace_on) seg_add(L.seg_valid, seg, op != OP_NONE ? 1 : 0);
+  __syncthreads();
+  const int nseg = L.nseg;
+  for (int s = tid; s < nseg; s += WG) {
+    const int32_t j = L.seg_join[s];
+    const int32_t v = L.seg_valid[s];
+    L.seg_join[s] = 0;
+    L.seg_valid[s] = 0;
+    if (MULTI) {
+      const int sl = L.seg_slot[s];
+      const uint32_t beg = (s == 0) ? L.off0 : L.win[s - 1];
+      const uint32_t end = L.win[s];
+      const uint32_t lo = max(beg, w0), hi = min(min(end, w0 + (uint32_t)WG), S);
+      const uint32_t items = hi - lo;
+      if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
+      const uint64_t add = ((uint64_t)(uint32_t)j << 32) | items;
+      const uint64_t prev = add_agent(&C.hot[sl].done, add);
+      if ((uint32_t)prev + items == end - beg) tree_finish(C, sl, (uint32_t)(prev >> 32) + (uint32_t)j);
+    } else {
+      if (j) add_agent(&C.plain->joins[P.par], j);
+      if (v) add_agent(&C.plain->valid[P.par], v);
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Work-list construction (the serial part of Phase 1 over all trees): an
+// exclusive scan of the per-tree range lengths.  One work-group.
+// ---------------------------------------------------------------------------
+template <int WG>
+__device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
+  SchedHdr *H = C.hdr;
+  const int tid = threadIdx.x;
+  if (after_epoch) {
+    const int nd = H->done_count;
+    for (int j = tid; j < nd; j += WG) {
+      const int slot = C.done_list[j];
+      TreeState *T = &C.st[slot];
+      if (T->err == 0) T->result = C.r[C.ts[slot].base];
+      T->done_gepoch = H->gepoch;
+    }
+  }
+  const int ts = H->tslots;
+  const int per = (ts + WG - 1) / WG;
+  const int t0 = min(tid * per, ts), t1 = min(t0 + per, ts);
+  int cnt = 0, items = 0;
+  for (int t = t0; t < t1; ++t) {
+    const int len = C.t_len[t];
+    if (len > 0) { ++cnt; items += len; }
+  }
+  int ctot, itot;
+  const int cpre = wg_excl_scan<WG>(cnt, L.scan_tmp, &ctot);
+  const int ipre = wg_excl_scan<WG>(items, L.scan_tmp, &itot);
+  int k = cpre;
+  uint32_t off = (uint32_t)ipre;
+  const int64_t g = H->gepoch + (after_epoch ? 1 : 0);
+  for (int t = t0; t < t1; ++t) {
+    const int len = C.t_len[t];
+    if (len > 0) {
+      C.wl_tree[k] = t;
+      C.wl_off[k] = off;
+      C.wl_start[k] = C.ts[t].base + C.t_b[t];
+      C.wl_cen[k] = C.t_cen[t];
+      if (C.st[t].start_gepoch < 0) C.st[t].start_gepoch = g;
+      ++k;
+      off += (uint32_t)len;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    C.wl_off[ctot] = (uint32_t)itot;
+    H->S = (uint32_t)itot;
+    H->L = ctot;
+    H->live = ctot;
+    H->done_count = 0;
+    if (after_epoch) { H->gepoch += 1; H->run_epochs += 1; }
+    int stop = 0;
+    if (ctot == 0) stop = 1;
+    else if (H->max_epochs >= 0 && H->run_epochs >= H->max_epochs) stop = 2;
+    else if (C.abort_flag && *C.abort_flag) stop = 3;
+    if (H->stop_reason == 4) stop = 4;   // a barrier timed out: stay stopped
+    H->stop = stop;
+    if (stop) H->stop_reason = stop;
+  }
+  __syncthreads();
+}
+
+template <int WG>
+__device__ __forceinline__ void lds_init(Lds<WG> &L) {
+  for (int t = threadIdx.x; t < WG; t += WG) { L.seg_cnt[t] = 0; L.seg_join[t] = 0; L.seg_valid[t] = 0; }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Plain form: one launch per epoch of one tree; grid covers the range.
+template <int WG, uint32_t OPS>
+__global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
+  __shared__ Lds<WG> L;
+  lds_init<WG>(L);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int q = P.par ^ 1;   // the next epoch's counters
+    C.plain->forks[q] = 0; C.plain->joins[q] = 0; C.plain->valid[q] = 0; C.plain->flags[q] = 0;
+  }
+  const uint32_t S = (uint32_t)(P.e - P.b);
+  run_chunk<WG, OPS, false>(C, L, blockIdx.x * WG, S, 1, P);
+}
+
+// Batched form.  persistent != 0: a co-resident grid loops over epochs with
+// a device grid barrier.  persistent == 0: one epoch per launch (a chain of
+// such launches is captured in a graph); the last work-group to finish
+// builds the next work list and the kernel boundary is the barrier.
+template <int WG, uint32_t OPS>
+__global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
+  __shared__ Lds<WG> L;
+  __shared__ int32_t s_hdr[3];
+  lds_init<WG>(L);
+  SchedHdr *H = C.hdr;
+  const PlainArgs P{};
+  while (true) {
+    if (threadIdx.x == 0) { s_hdr[0] = (int32_t)H->S; s_hdr[1] = H->L; s_hdr[2] = H->stop; }
+    __syncthreads();
+    const uint32_t S = (uint32_t)s_hdr[0];
+    const int32_t nL = s_hdr[1];
+    if (s_hdr[2]) break;
+    const uint32_t nchunks = (S + WG - 1) / WG;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+      run_chunk<WG, OPS, true>(C, L, c * WG, S, nL, P);
+    // ---- epoch barrier: Tenet 1, one arrival per work-group ------------
+    // Every wavefront releases its own task-vector and state writes (each
+    // wavefront must, a fence by one thread does not cover the others'
+    // outstanding stores), then one thread arrives.
+    fence_release();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t g = ld_agent(&H->gen);
+      fence_release();
+      const uint32_t a = add_agent(&H->arrive, 1u);
+      L.flag = (a == gridDim.x - 1);
+      L.gen = g;
+    }
+    __syncthreads();
+    if (L.flag) {
+      fence_acquire();
+      schedule_scan<WG>(C, L, true);
+      fence_release();
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        st_agent(&H->arrive, 0u);
+        fence_release();
+        __hip_atomic_store(&H->gen, L.gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (!persistent) break;
+    } else {
+      if (!persistent) break;
+      if (threadIdx.x == 0) {
+        const int64_t t0 = realtime();
+        int timed_out = 0;
+        while (ld_agent(&H->gen) == L.gen) {
+          __builtin_amdgcn_s_sleep(2);
+          if (realtime() - t0 > C.timeout_ticks) { timed_out = 1; break; }
+        }
+        L.tflag = timed_out;
+        if (timed_out) {
+          // give up: every other work-group stops at its next boundary
+          st_agent(&H->stop_reason, 4);
+          st_agent(&H->stop, 1);
+        }
+      }
+      __syncthreads();
+      if (L.tflag) break;
+    }
+    fence_acquire();
+    __syncthreads();
+  }
+}
+
+// Builds the first work list of a run from the trees' current ranges.
+template <int WG>
+__global__ __launch_bounds__(WG) void k_scan(DevCtx C) {
+  __shared__ Lds<WG> L;
+  if (threadIdx.x == 0) { C.hdr->arrive = 0; C.hdr->done_count = 0; C.hdr->stop_reason = 0; }
+  __syncthreads();
+  schedule_scan<WG>(C, L, false);
+}
+
+// Admission: make staged trees live (root in entry 0 of the arena, epoch 0).
+__global__ void k_admit(DevCtx C, const Admit *adm, int32_t n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const Admit a = adm[j];
+  const int s = a.slot;
+  ((TreeStatic *)C.ts)[s] = a.ts;
+  TreeState T = {};
+  T.cen = 0; T.b = 0; T.e = 1; T.old = 1; T.sp = 0; T.status = TS_LIVE; T.err = 0;
+  T.epochs = 0; T.tasks = 1; T.launched = 0; T.result = 0; T.done_gepoch = -1;
+  T.start_gepoch = -1; T.peak = 1; T.ntrace = 0;
+  C.st[s] = T;
+  TreeHot Hh = {};
+  Hh.nfc = 1;
+  C.hot[s] = Hh;
+  C.t_len[s] = 1; C.t_cen[s] = 0; C.t_b[s] = 0;
+  const int64_t r0 = a.ts.base;
+  C.code[r0] = a.root_code;
+  C.a0[r0] = a.a0; C.a1[r0] = a.a1; C.a2[r0] = a.a2; C.a3[r0] = a.a3;
+  C.r[r0] = 0;
+}
+
+// BFS payload initialisation: depth = -1 everywhere, 0 at the source.
+__global__ void k_depth_init(int32_t *depth, int32_t V, int32_t src) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < V; v += (int64_t)gridDim.x * blockDim.x)
+    depth[v] = (v == src) ? 0 : -1;
+}
+
+// Release a slot: no range, status free.
+__global__ void k_release(DevCtx C, int32_t slot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    C.t_len[slot] = 0;
+    C.st[slot].status = TS_FREE;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+#define TREES_FOR_OPS(M, WG)      \
+  M(WG, OPS_FIB)                  \
+  M(WG, OPS_NQ)                   \
+  M(WG, OPS_FIB | OPS_NQ)         \
+  M(WG, OPS_MS)                   \
+  M(WG, OPS_BFS)                  \
+  M(WG, OPS_ALL)
+
+static uint32_t pick_ops(uint32_t need) {
+  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_BFS, OPS_ALL};
+  for (uint32_t s : sets)
+    if ((need & ~s) == 0) return s;
+  return OPS_ALL;
+}
+
+template <int WG>
+static const void *plain_fn(uint32_t ops) {
+#define M(W, O) if (ops == (O)) return (const void *)&k_plain<W, O>;
+  TREES_FOR_OPS(M, WG)
+#undef M
+  return nullptr;
+}
+template <int WG>
+static const void *epochs_fn(uint32_t ops) {
+#define M(W, O) if (ops == (O)) return (const void *)&k_epochs<W, O>;
+  TREES_FOR_OPS(M, WG)
+#undef M
+  return nullptr;
+}
+
+const void *kernel_plain(int wg, uint32_t need) {
+  const uint32_t ops = pick_ops(need);
+  switch (wg) {
+    case 256: return plain_fn<256>(ops);
+    case 512: return plain_fn<512>(ops);
+    case 1024: return plain_fn<1024>(ops);
+    default: return nullptr;
+  }
+}
+const void *kernel_epochs(int wg, uint32_t need) {
+  const uint32_t ops = pick_ops(need);
+  switch (wg) {
+    case 256: return epochs_fn<256>(ops);
+    case 512: return epochs_fn<512>(ops);
+    case 1024: return epochs_fn<1024>(ops);
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s) {
+  const void *fn = kernel_plain(wg, need);
+  if (!fn) return hipErrorInvalidValue;
+  const uint32_t S = (uint32_t)(P.e - P.b);
+  dim3 grid((S + wg - 1) / wg), block(wg);
+  DevCtx c = C;
+  PlainArgs p = P;
+  void *args[] = {&c, &p};
+  return hipLaunchKernel(fn, grid, block, args, 0, s);
+}
+
+hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s) {
+  const void *fn = kernel_epochs(wg, need);
+  if (!fn) return hipErrorInvalidValue;
+  DevCtx c = C;
+  int32_t p = persistent;
+  void *args[] = {&c, &p};
+  if (persistent) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(wg), args, 0, s);
+  return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, 0, s);
+}
+
+int coresident_blocks_per_cu(int wg, uint32_t need) {
+  const void *fn = kernel_epochs(wg, need);
+  if (!fn) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, 0) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_scan(const DevCtx &C, hipStream_t s) {
+  DevCtx c = C;
+  void *args[] = {&c};
+  return hipLaunchKernel((const void *)&k_scan<256>, dim3(1), dim3(256), args, 0, s);
+}
+
+hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  DevCtx c = C;
+  const Admit *a = (const Admit *)adm;
+  int32_t nn = n;
+  void *args[] = {&c, &a, &nn};
+  return hipLaunchKernel((const void *)&k_admit, dim3((n + 255) / 256), dim3(256), args, 0, s);
+}
+
+hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, hipStream_t s) {
+  int32_t v = V, sc = src;
+  void *args[] = {&depth, &v, &sc};
+  int blocks = (int)((V + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  return hipLaunchKernel((const void *)&k_depth_init, dim3(blocks), dim3(256), args, 0, s);
+}
+
+hipError_t launch_release(const DevCtx &C, int slot, hipStream_t s) {
+  DevCtx c = C;
+  int32_t sl = slot;
+  void *args[] = {&c, &sl};
+  return hipLaunchKernel((const void *)&k_release, dim3(1), dim3(64), args, 0, s);
+}
+
+size_t admit_record_size() { return sizeof(Admit); }
+
+}  // namespace trees

@@ -1,0 +1,834 @@
+// libtrees host side: contexts, program registration, admission of task
+// trees into task-vector arenas, and the three epoch schedulers.
+#include "trees.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "trees_dev.h"
+
+namespace trees {
+hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s);
+hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s);
+int coresident_blocks_per_cu(int wg, uint32_t need);
+hipError_t launch_scan(const DevCtx &C, hipStream_t s);
+hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
+hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, hipStream_t s);
+const void *kernel_epochs(int wg, uint32_t need);
+}  // namespace trees
+
+using namespace trees;
+
+namespace {
+
+constexpr int kBytesPerEntry = 28;   // code + a0..a3 (int32) + r (int64)
+
+std::string g_create_error;
+
+struct Prog {
+  int kind = 0;
+  int tbase = 0;
+  int ntypes = 0;
+  uint32_t ops = 0;
+};
+
+enum HostStatus { H_FREE = 0, H_STAGED = 1, H_LIVE = 2, H_DONE = 3 };
+
+struct HostTree {
+  int hstatus = H_FREE;
+  uint32_t gen = 1;
+  int prog = 0;
+  int kind = 0;
+  int64_t base = 0, cap = 0;
+  uint64_t order = 0;              // submission order
+  TreeState st{};                  // mirror of the device state
+  std::vector<TraceRec> trace;     // plain-scheduler trace (host-recorded)
+  bool host_trace = false;
+};
+
+uint32_t ops_of_kind(int kind) {
+  switch (kind) {
+    case TREES_PROG_FIB_I32: return opbit(OP_FIB32) | opbit(OP_SUM32);
+    case TREES_PROG_FIB_I64: return opbit(OP_FIB64) | opbit(OP_SUM64);
+    case TREES_PROG_MSORT_U32: return OPS_MS;
+    case TREES_PROG_NQUEENS: return OPS_NQ;
+    case TREES_PROG_BFS_CSR: return OPS_BFS;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Exact task-vector bounds (admission sizes).  The task vector only shrinks
+// when a join range is popped (nextFreeCore returns to the value saved with
+// the range), so a tree's high-water mark is reached when its deepest level
+// has been forked: every task of the forking type is then allocated.
+// ---------------------------------------------------------------------------
+int64_t fib_bound(int64_t n) {
+  if (n < 2) return 1;
+  int64_t a = 0, b = 1;   // F(n+1)
+  for (int64_t k = 0; k < n + 1; ++k) { int64_t t = a + b; a = b; b = t; }
+  return 2 * a - 1;       // nodes of the naive call tree
+}
+
+int64_t nq_nodes_rec(int n, int row, uint32_t cols, uint32_t ld, uint32_t rd) {
+  if (row == n) return 1;
+  const uint32_t full = (1u << n) - 1u;
+  uint32_t avail = ~(cols | ld | rd) & full;
+  int64_t s = 1;
+  while (avail) {
+    uint32_t bit = avail & (0u - avail);
+    avail ^= bit;
+    s += nq_nodes_rec(n, row + 1, cols | bit, ((ld | bit) << 1) & full, (rd | bit) >> 1);
+  }
+  return s;
+}
+int64_t nq_bound(int n) {
+  static std::mutex mu;
+  static int64_t memo[16] = {0};
+  std::lock_guard<std::mutex> g(mu);
+  if (!memo[n]) memo[n] = nq_nodes_rec(n, 0, 0, 0, 0);
+  return memo[n];
+}
+
+int64_t ms_bound(int64_t n) {
+  // MS tasks of the split tree: 1 + bound(floor(n/2)) + bound(ceil(n/2))
+  static std::mutex mu;
+  static std::map<int64_t, int64_t> memo;
+  if (n <= kLeaf) return 1;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = memo.find(n);
+    if (it != memo.end()) return it->second;
+  }
+  int64_t v = 1 + ms_bound(n / 2) + ms_bound(n - n / 2);
+  std::lock_guard<std::mutex> g(mu);
+  memo[n] = v;
+  return v;
+}
+
+trees_status tv_bound(int kind, const int64_t *args, int nargs, int64_t *out, std::string *err) {
+  auto bad = [&](const char *m) { if (err) *err = m; return (trees_status)TREES_E_INVALID; };
+  switch (kind) {
+    case TREES_PROG_FIB_I32:
+    case TREES_PROG_FIB_I64:
+      if (nargs < 1 || args[0] < 0 || args[0] > 43) return bad("fib: need 0 <= n <= 43");
+      *out = fib_bound(args[0]);
+      return TREES_OK;
+    case TREES_PROG_NQUEENS:
+      if (nargs < 1 || args[0] < 1 || args[0] > 14) return bad("nqueens: need 1 <= n <= 14");
+      *out = nq_bound((int)args[0]);
+      return TREES_OK;
+    case TREES_PROG_MSORT_U32:
+      if (nargs < 1 || args[0] < 0 || args[0] >= (1ll << 31)) return bad("msort: need 0 <= N < 2^31");
+      *out = ms_bound(args[0]);
+      return TREES_OK;
+    case TREES_PROG_BFS_CSR:
+      if (nargs < 2 || args[0] < 1 || args[0] >= (1ll << 31) || args[1] < 0 || args[1] >= args[0])
+        return bad("bfs: need V >= 1 and 0 <= source < V");
+      *out = args[0];
+      return TREES_OK;
+  }
+  return bad("unknown program kind");
+}
+
+}  // namespace
+
+struct trees_ctx {
+  trees_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char *arena = nullptr;
+  bool own_arena = false;
+  int64_t nent = 0;
+  void *ctl = nullptr;             // control block (descriptors, stacks, work list, header)
+  DevCtx dc{};
+  std::vector<Prog> progs;
+  int ntt = 0;
+  bool frozen = false;
+  int tmax = 4096;
+  std::vector<HostTree> trees;
+  int tslots = 0;
+  int ntrees = 0;
+  uint64_t order = 0;
+  std::map<int64_t, int64_t> freel;   // arena free list: start -> length
+  int64_t free_ent = 0;
+  std::vector<Admit> staged;
+  struct DepthInit { int32_t *depth; int32_t V, src; };
+  std::vector<DepthInit> depth_inits;
+  Admit *adm_host = nullptr;       // pinned staging
+  Admit *adm_dev = nullptr;
+  PlainCounters *plain_host = nullptr;
+  SchedHdr *hdr_host = nullptr;
+  TreeState *st_host = nullptr;
+  int32_t *abort_flag = nullptr;
+  int64_t *r_host = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int gkey_wg = 0, gkey_grid = 0, gkey_chunk = 0;
+  uint32_t gkey_ops = 0;
+  int sched = TREES_SCHED_PERSISTENT;
+  int wg = 256, bpc = 0, chunk = 8;
+  int ncu = 0;
+  int last_grid = 0, last_api_bpc = 0;
+  double clock_hz = 1e8;
+  bool running = false;
+  std::string err;
+  std::mutex mu;
+};
+
+namespace {
+
+trees_status fail(trees_ctx *c, trees_status st, const std::string &m) {
+  if (c) c->err = m; else g_create_error = m;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, TREES_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t arena_alloc(trees_ctx *c, int64_t n) {
+  for (auto it = c->freel.begin(); it != c->freel.end(); ++it) {
+    if (it->second >= n) {
+      int64_t s = it->first, len = it->second;
+      c->freel.erase(it);
+      if (len > n) c->freel[s + n] = len - n;
+      c->free_ent -= n;
+      return s;
+    }
+  }
+  return -1;
+}
+
+void arena_free(trees_ctx *c, int64_t s, int64_t n) {
+  if (n <= 0) return;
+  c->free_ent += n;
+  auto it = c->freel.emplace(s, n).first;
+  auto nx = std::next(it);
+  if (nx != c->freel.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    c->freel.erase(nx);
+  }
+  if (it != c->freel.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      c->freel.erase(it);
+    }
+  }
+}
+
+uint32_t ops_needed(trees_ctx *c) {
+  uint32_t o = 0;
+  for (auto &p : c->progs) o |= p.ops;
+  return o;
+}
+
+trees_status flush_admissions(trees_ctx *c) {
+  const int n = (int)c->staged.size();
+  if (n) {
+    memcpy(c->adm_host, c->staged.data(), sizeof(Admit) * n);
+    HIPCHK(c, hipMemcpyAsync(c->adm_dev, c->adm_host, sizeof(Admit) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_admit(c->dc, c->adm_dev, n, c->stream));
+    for (auto &a : c->staged) {
+      HostTree &t = c->trees[a.slot];
+      t.hstatus = H_LIVE;
+      memset(&t.st, 0, sizeof(t.st));
+      t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 1; t.st.peak = 1;
+      t.st.done_gepoch = -1; t.st.start_gepoch = -1;
+      t.trace.clear();
+      t.host_trace = false;
+    }
+    c->staged.clear();
+  }
+  for (auto &d : c->depth_inits) HIPCHK(c, launch_depth_init(d.depth, d.V, d.src, c->stream));
+  c->depth_inits.clear();
+  // the admission staging buffer is reused: wait for the copy
+  if (n) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TREES_OK;
+}
+
+// Read the device state of every slot back into the host mirrors.
+trees_status sync_states(trees_ctx *c) {
+  if (c->tslots == 0) return TREES_OK;
+  HIPCHK(c, hipMemcpyAsync(c->st_host, c->dc.st, sizeof(TreeState) * c->tslots, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int s = 0; s < c->tslots; ++s) {
+    HostTree &t = c->trees[s];
+    if (t.hstatus != H_LIVE) continue;
+    t.st = c->st_host[s];
+    if (t.st.status == TS_DONE) t.hstatus = H_DONE;
+  }
+  return TREES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PLAIN: the paper's host-driven loop, one tree at a time.
+// ---------------------------------------------------------------------------
+trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *gepochs, bool trace) {
+  HostTree &t = c->trees[slot];
+  TreeState st{};
+  HIPCHK(c, hipMemcpyAsync(c->st_host, c->dc.st + slot, sizeof(TreeState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  st = c->st_host[0];
+  std::vector<int4> stk(st.sp);
+  if (st.sp)
+    HIPCHK(c, hipMemcpy(stk.data(), c->dc.stack + (size_t)slot * kStackMax, sizeof(int4) * st.sp,
+                        hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemsetAsync(c->dc.plain, 0, sizeof(PlainCounters), c->stream));
+  if (trace) t.host_trace = true;
+  const uint32_t need = c->progs[t.prog].ops;
+  int par = 0;
+  int err = 0;
+  bool done = false;
+  while (true) {
+    if (*budget == 0 || *(volatile int32_t *)c->abort_flag) break;
+    // Phase 1 happened when the range was popped; launch Phase 2.
+    PlainArgs P{slot, st.cen, st.b, st.e, st.old, par};
+    if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
+    HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->plain_host, c->dc.plain, sizeof(PlainCounters), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int32_t forks = c->plain_host->forks[par];
+    const int32_t joins = c->plain_host->joins[par];
+    const int32_t valid = c->plain_host->valid[par];
+    const int32_t flags = c->plain_host->flags[par];
+    const int32_t nfc = st.old + forks;
+    if (trace && st.epochs < kTraceMax)
+      t.trace.push_back(TraceRec{st.epochs, st.cen, st.b, st.e, st.e - st.b, valid, forks, joins, nfc});
+    st.epochs += 1;
+    st.launched += st.e - st.b;
+    st.tasks += (int64_t)forks + joins;
+    if (nfc > st.peak) st.peak = nfc;
+    ++*gepochs;
+    if (*budget > 0) --*budget;
+    par ^= 1;
+    if (flags & TF_OVERFLOW) { err = TREES_E_OVERFLOW; done = true; break; }
+    if (flags & TF_ENCODING) { err = TREES_E_ENCODING; done = true; break; }
+    // Phase 3 (Section 5.2.4): push the join range, then the forked range.
+    int4 top;
+    bool have = false;
+    if (joins) {
+      if ((int)stk.size() >= kStackMax) { err = TREES_E_STACK; done = true; break; }
+      stk.push_back(make_int4(st.cen, st.b, st.e, nfc));
+    }
+    if (forks) { top = make_int4(st.cen + 1, st.old, nfc, nfc); have = true; }
+    else if (!stk.empty()) { top = stk.back(); stk.pop_back(); have = true; }
+    if (!have) { done = true; break; }
+    st.cen = top.x; st.b = top.y; st.e = top.z; st.old = top.w;
+  }
+  st.sp = (int)stk.size();
+  if (done) {
+    st.status = TS_DONE;
+    st.err = err;
+    st.done_gepoch = (int64_t)*gepochs - 1;
+    if (!err) {
+      HIPCHK(c, hipMemcpy(c->r_host, c->dc.r + t.base, sizeof(int64_t), hipMemcpyDeviceToHost));
+      st.result = c->r_host[0];
+    }
+  }
+  // Write the state back so any scheduler can continue a paused tree.
+  c->st_host[0] = st;
+  HIPCHK(c, hipMemcpyAsync(c->dc.st + slot, c->st_host, sizeof(TreeState), hipMemcpyHostToDevice, c->stream));
+  if (st.sp)
+    HIPCHK(c, hipMemcpyAsync(c->dc.stack + (size_t)slot * kStackMax, stk.data(), sizeof(int4) * st.sp,
+                             hipMemcpyHostToDevice, c->stream));
+  TreeHot hot{};
+  hot.nfc = st.old;
+  HIPCHK(c, hipMemcpyAsync(c->dc.hot + slot, &hot, sizeof(TreeHot), hipMemcpyHostToDevice, c->stream));
+  int32_t lcb[3] = {done ? 0 : st.e - st.b, st.cen, st.b};
+  HIPCHK(c, hipMemcpyAsync(c->dc.t_len + slot, &lcb[0], 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dc.t_cen + slot, &lcb[1], 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dc.t_b + slot, &lcb[2], 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  t.st = st;
+  if (done) t.hstatus = H_DONE;
+  return TREES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GRAPH / PERSISTENT: device Phases 1 and 3.
+// ---------------------------------------------------------------------------
+trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
+  // read-modify-write of the header's scalar part
+  HIPCHK(c, hipMemcpyAsync(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->hdr_host->stop = 0;
+  c->hdr_host->stop_reason = 0;
+  c->hdr_host->run_epochs = 0;
+  c->hdr_host->max_epochs = max_epochs;
+  c->hdr_host->tslots = c->tslots;
+  c->hdr_host->arrive = 0;
+  HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_scan(c->dc, c->stream));
+  return TREES_OK;
+}
+
+trees_status read_hdr(trees_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->hdr_host, c->dc.hdr, 64, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TREES_OK;
+}
+
+// Work-groups per CU for the batched grids.  The persistent form needs every
+// work-group resident at once, and a cooperative launch sized at the
+// runtime's occupancy figure was not refused yet did not get past its first
+// grid barrier (the spin limit had to end it), so the persistent grid never
+// exceeds 3/4 of that figure.  The graph form has no residency requirement.
+int blocks_per_cu(trees_ctx *c, uint32_t need, bool persistent) {
+  int api = coresident_blocks_per_cu(c->wg, need);
+  if (api <= 0) api = 1;
+  c->last_api_bpc = api;
+  const int cap = persistent ? std::max(1, (api * 3) / 4) : api;
+  return (c->bpc > 0) ? std::min(c->bpc, cap) : cap;
+}
+
+int grid_size(trees_ctx *c, uint32_t need, bool persistent) {
+  return blocks_per_cu(c, need, persistent) * c->ncu;
+}
+
+trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
+  trees_status s = hdr_begin(c, max_epochs);
+  if (s) return s;
+  const uint32_t need = ops_needed(c);
+  const int grid = grid_size(c, need, false);
+  c->last_grid = grid;
+  if (!c->gexec || c->gkey_wg != c->wg || c->gkey_grid != grid || c->gkey_chunk != c->chunk ||
+      c->gkey_ops != need) {
+    if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < c->chunk; ++k) {
+      hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
+      if (e != hipSuccess) {
+        hipGraph_t g;
+        (void)hipStreamEndCapture(c->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, TREES_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+      }
+    }
+    HIPCHK(c, hipStreamEndCapture(c->stream, &c->graph));
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->gkey_wg = c->wg; c->gkey_grid = grid; c->gkey_chunk = c->chunk; c->gkey_ops = need;
+  }
+  s = read_hdr(c);
+  if (s) return s;
+  while (!c->hdr_host->stop) {
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    s = read_hdr(c);
+    if (s) return s;
+  }
+  return TREES_OK;
+}
+
+trees_status run_persistent(trees_ctx *c, int64_t max_epochs) {
+  trees_status s = hdr_begin(c, max_epochs);
+  if (s) return s;
+  const uint32_t need = ops_needed(c);
+  const int grid = grid_size(c, need, true);
+  c->last_grid = grid;
+  HIPCHK(c, launch_epochs(c->dc, c->wg, need, grid, 1, c->stream));
+  return read_hdr(c);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
+  if (!cfg || !out || cfg->struct_size != sizeof(trees_config))
+    return fail(nullptr, TREES_E_INVALID, "trees_create: bad config (struct_size mismatch?)");
+  *out = nullptr;
+  trees_ctx *c = new (std::nothrow) trees_ctx();
+  if (!c) return fail(nullptr, TREES_E_NOMEM, "out of host memory");
+  c->cfg = *cfg;
+  c->device = cfg->device;
+  c->tmax = cfg->max_trees > 0 ? cfg->max_trees : 4096;
+  c->sched = cfg->sched;
+  c->wg = cfg->wg_size ? cfg->wg_size : 256;
+  c->bpc = cfg->blocks_per_cu;
+  c->chunk = cfg->graph_chunk > 0 ? cfg->graph_chunk : 8;
+  if (c->wg != 256 && c->wg != 512 && c->wg != 1024) {
+    delete c;
+    return fail(nullptr, TREES_E_INVALID, "wg_size must be 256, 512 or 1024");
+  }
+  auto bail = [&](trees_status st, const std::string &m) {
+    g_create_error = m;
+    trees_destroy(c);
+    return st;
+  };
+  if (hipSetDevice(c->device) != hipSuccess) return bail(TREES_E_DEVICE, "hipSetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(TREES_E_DEVICE, "no device properties");
+  c->ncu = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+    c->clock_hz = khz * 1000.0;
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(TREES_E_DEVICE, "hipStreamCreate failed");
+    c->own_stream = true;
+  }
+  // task vector
+  uint64_t bytes = cfg->arena_bytes;
+  c->nent = (int64_t)(bytes / kBytesPerEntry) & ~(int64_t)63;
+  if (c->nent <= 0) return bail(TREES_E_INVALID, "arena_bytes too small");
+  if (cfg->arena_base) {
+    c->arena = (char *)cfg->arena_base;
+  } else {
+    if (hipMalloc((void **)&c->arena, (size_t)c->nent * kBytesPerEntry + 256) != hipSuccess)
+      return bail(TREES_E_NOMEM, "hipMalloc of the task vector failed");
+    c->own_arena = true;
+  }
+  {
+    char *p = c->arena;
+    const size_t n = (size_t)c->nent;
+    c->dc.r = (int64_t *)p; p += n * 8;     // 8-byte aligned first
+    c->dc.code = (int32_t *)p; p += n * 4;
+    c->dc.a0 = (int32_t *)p; p += n * 4;
+    c->dc.a1 = (int32_t *)p; p += n * 4;
+    c->dc.a2 = (int32_t *)p; p += n * 4;
+    c->dc.a3 = (int32_t *)p; p += n * 4;
+  }
+  c->freel[0] = c->nent;
+  c->free_ent = c->nent;
+  // control block
+  const size_t T = (size_t)c->tmax;
+  const bool trace = (cfg->flags & TREES_F_TRACE) != 0;
+  size_t off = 0;
+  auto take = [&](size_t sz) { size_t o = off; off = (off + sz + 255) & ~(size_t)255; return o; };
+  const size_t o_ts = take(T * sizeof(TreeStatic)), o_st = take(T * sizeof(TreeState)),
+               o_hot = take(T * sizeof(TreeHot)), o_len = take(T * 4), o_cen = take(T * 4),
+               o_b = take(T * 4), o_stk = take(T * kStackMax * sizeof(int4)),
+               o_tr = trace ? take(T * kTraceMax * sizeof(TraceRec)) : 0, o_wt = take((T + 1) * 4),
+               o_wo = take((T + 1) * 4), o_ws = take((T + 1) * 8), o_wc = take((T + 1) * 4),
+               o_dl = take(T * 4), o_hdr = take(sizeof(SchedHdr)), o_pl = take(sizeof(PlainCounters)),
+               o_adm = take(T * sizeof(Admit));
+  if (hipMalloc(&c->ctl, off) != hipSuccess) return bail(TREES_E_NOMEM, "hipMalloc of control state failed");
+  if (hipMemset(c->ctl, 0, off) != hipSuccess) return bail(TREES_E_DEVICE, "hipMemset failed");
+  char *b = (char *)c->ctl;
+  c->dc.ts = (const TreeStatic *)(b + o_ts);
+  c->dc.st = (TreeState *)(b + o_st);
+  c->dc.hot = (TreeHot *)(b + o_hot);
+  c->dc.t_len = (int32_t *)(b + o_len);
+  c->dc.t_cen = (int32_t *)(b + o_cen);
+  c->dc.t_b = (int32_t *)(b + o_b);
+  c->dc.stack = (int4 *)(b + o_stk);
+  c->dc.trace = trace ? (TraceRec *)(b + o_tr) : nullptr;
+  c->dc.wl_tree = (int32_t *)(b + o_wt);
+  c->dc.wl_off = (uint32_t *)(b + o_wo);
+  c->dc.wl_start = (int64_t *)(b + o_ws);
+  c->dc.wl_cen = (int32_t *)(b + o_wc);
+  c->dc.done_list = (int32_t *)(b + o_dl);
+  c->dc.hdr = (SchedHdr *)(b + o_hdr);
+  c->dc.plain = (PlainCounters *)(b + o_pl);
+  c->adm_dev = (Admit *)(b + o_adm);
+  c->dc.trace_on = trace ? 1 : 0;
+  c->dc.debug = (cfg->flags & TREES_F_DEBUG) ? 1 : 0;
+  const double to = cfg->timeout_s > 0 ? cfg->timeout_s : 60.0;
+  c->dc.timeout_ticks = (int64_t)(to * c->clock_hz);
+  // pinned host memory
+  if (hipHostMalloc((void **)&c->adm_host, T * sizeof(Admit), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->plain_host, sizeof(PlainCounters), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->hdr_host, sizeof(SchedHdr), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->st_host, T * sizeof(TreeState), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->r_host, 64, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->abort_flag, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+    return bail(TREES_E_NOMEM, "hipHostMalloc failed");
+  *c->abort_flag = 0;
+  int32_t *dev_abort = nullptr;
+  if (hipHostGetDevicePointer((void **)&dev_abort, c->abort_flag, 0) != hipSuccess)
+    return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
+  c->dc.abort_flag = dev_abort;
+  c->trees.resize(c->tmax);
+  *out = c;
+  return TREES_OK;
+}
+
+void trees_destroy(trees_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->own_arena && c->arena) (void)hipFree(c->arena);
+  if (c->ctl) (void)hipFree(c->ctl);
+  if (c->adm_host) (void)hipHostFree(c->adm_host);
+  if (c->plain_host) (void)hipHostFree(c->plain_host);
+  if (c->hdr_host) (void)hipHostFree(c->hdr_host);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->r_host) (void)hipHostFree(c->r_host);
+  if (c->abort_flag) (void)hipHostFree(c->abort_flag);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *trees_last_error(const trees_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_prog) {
+  if (!c || !out_prog) return fail(c, TREES_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> g(c->mu);
+  const uint32_t ops = ops_of_kind(kind);
+  if (!ops) return fail(c, TREES_E_INVALID, "unknown program kind");
+  for (size_t p = 0; p < c->progs.size(); ++p)
+    if (c->progs[p].kind == kind) { *out_prog = (int32_t)p; return TREES_OK; }
+  if (c->frozen) return fail(c, TREES_E_STATE, "programs must be registered before the first submit");
+  Prog p;
+  p.kind = kind;
+  p.ntypes = (kind == TREES_PROG_BFS_CSR) ? 1 : 2;
+  p.tbase = c->ntt + 1;
+  p.ops = ops;
+  if (c->ntt + p.ntypes > kMaxTypes) return fail(c, TREES_E_INVALID, "too many task types");
+  c->ntt += p.ntypes;
+  // type ids of the program: tbase = body type, tbase + 1 = its join continuation
+  switch (kind) {
+    case TREES_PROG_FIB_I32: c->dc.op_of_type[p.tbase] = OP_FIB32; c->dc.op_of_type[p.tbase + 1] = OP_SUM32; break;
+    case TREES_PROG_FIB_I64: c->dc.op_of_type[p.tbase] = OP_FIB64; c->dc.op_of_type[p.tbase + 1] = OP_SUM64; break;
+    case TREES_PROG_MSORT_U32: c->dc.op_of_type[p.tbase] = OP_MS; c->dc.op_of_type[p.tbase + 1] = OP_MERGE; break;
+    case TREES_PROG_NQUEENS: c->dc.op_of_type[p.tbase] = OP_Q; c->dc.op_of_type[p.tbase + 1] = OP_QSUM; break;
+    case TREES_PROG_BFS_CSR: c->dc.op_of_type[p.tbase] = OP_VISIT; break;
+  }
+  c->dc.ntt = c->ntt;
+  c->progs.push_back(p);
+  *out_prog = (int32_t)(c->progs.size() - 1);
+  return TREES_OK;
+}
+
+trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32_t nargs,
+                          const trees_buf *bufs, int32_t nbufs, uint64_t *out_tree) {
+  if (!c || !out_tree) return fail(c, TREES_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> g(c->mu);
+  if (prog < 0 || prog >= (int)c->progs.size()) return fail(c, TREES_E_INVALID, "unknown program id");
+  const Prog &P = c->progs[prog];
+  int64_t bound = 0;
+  std::string e;
+  trees_status st = tv_bound(P.kind, args, nargs, &bound, &e);
+  if (st) return fail(c, st, e);
+  if (bound >= (1ll << 31)) return fail(c, TREES_E_INVALID, "tree too large for one arena");
+  Admit a{};
+  a.ts.kind = P.kind;
+  a.ts.tbase = P.tbase;
+  a.root_code = 0 * c->ntt + P.tbase;   // epoch 0, the program's first type
+  switch (P.kind) {
+    case TREES_PROG_FIB_I32:
+    case TREES_PROG_FIB_I64:
+      a.a0 = (int32_t)args[0];
+      a.ts.p0 = (int32_t)args[0];
+      break;
+    case TREES_PROG_NQUEENS:
+      a.ts.p0 = (int32_t)args[0];
+      break;
+    case TREES_PROG_MSORT_U32: {
+      const int64_t N = args[0];
+      if (nbufs < 2 || !bufs || (N > 0 && (!bufs[0].ptr || !bufs[1].ptr)) ||
+          bufs[0].bytes < (uint64_t)N * 4 || bufs[1].bytes < (uint64_t)N * 4)
+        return fail(c, TREES_E_INVALID, "msort: need bufs {keys[N], tmp[N]} of uint32");
+      a.a0 = 0; a.a1 = (int32_t)N; a.a2 = 0;
+      a.ts.p0 = (int32_t)N;
+      a.ts.ptr0 = (uint64_t)bufs[0].ptr;
+      a.ts.ptr1 = (uint64_t)bufs[1].ptr;
+    } break;
+    case TREES_PROG_BFS_CSR: {
+      const int64_t V = args[0], src = args[1];
+      if (nbufs < 3 || !bufs || !bufs[0].ptr || !bufs[1].ptr || !bufs[2].ptr ||
+          bufs[0].bytes < (uint64_t)(V + 1) * 4 || bufs[2].bytes < (uint64_t)V * 4)
+        return fail(c, TREES_E_INVALID, "bfs: need bufs {row_ptr[V+1], col_idx[E], depth[V]} of int32");
+      a.a0 = (int32_t)src;
+      a.ts.p0 = (int32_t)V;
+      a.ts.p1 = (int32_t)src;
+      a.ts.ptr0 = (uint64_t)bufs[0].ptr;
+      a.ts.ptr1 = (uint64_t)bufs[1].ptr;
+      a.ts.ptr2 = (uint64_t)bufs[2].ptr;
+    } break;
+  }
+  int slot = -1;
+  for (int s = 0; s < c->tmax; ++s)
+    if (c->trees[s].hstatus == H_FREE) { slot = s; break; }
+  if (slot < 0) return fail(c, TREES_E_NOMEM, "no free tree slot");
+  const int64_t base = arena_alloc(c, bound);
+  if (base < 0) return fail(c, TREES_E_NOMEM, "task-vector budget exhausted");
+  c->frozen = true;
+  a.slot = slot;
+  a.ts.base = base;
+  a.ts.cap = (int32_t)bound;
+  HostTree &t = c->trees[slot];
+  t.hstatus = H_STAGED;
+  t.prog = prog;
+  t.kind = P.kind;
+  t.base = base;
+  t.cap = bound;
+  t.order = c->order++;
+  c->staged.push_back(a);
+  if (P.kind == TREES_PROG_BFS_CSR)
+    c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1]});
+  c->tslots = std::max(c->tslots, slot + 1);
+  c->ntrees++;
+  *out_tree = ((uint64_t)t.gen << 32) | (uint32_t)slot;
+  return TREES_OK;
+}
+
+trees_status trees_run(trees_ctx *c, int64_t max_epochs, uint32_t flags, trees_run_stats *out) {
+  (void)flags;
+  if (!c) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  auto t0 = std::chrono::steady_clock::now();
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, TREES_E_DEVICE, "hipSetDevice failed");
+  *(volatile int32_t *)c->abort_flag = 0;
+  trees_status s = flush_admissions(c);
+  if (s) return s;
+  std::vector<int> before;
+  for (int i = 0; i < c->tslots; ++i)
+    if (c->trees[i].hstatus == H_LIVE) before.push_back(i);
+  uint64_t gepochs = 0;
+  int32_t stop_reason = 1;
+  int sched = c->sched == TREES_SCHED_AUTO ? TREES_SCHED_PERSISTENT : c->sched;
+  if (sched == TREES_SCHED_PLAIN) {
+    std::vector<int> order = before;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return c->trees[a].order < c->trees[b].order; });
+    int64_t budget = max_epochs;
+    const bool trace = c->dc.trace_on != 0;
+    for (int slot : order) {
+      s = run_plain_tree(c, slot, &budget, &gepochs, trace);
+      if (s) return s;
+      if (budget == 0) { stop_reason = 2; break; }
+      if (*(volatile int32_t *)c->abort_flag) { stop_reason = 3; break; }
+    }
+  } else {
+    s = (sched == TREES_SCHED_GRAPH) ? run_graph(c, max_epochs) : run_persistent(c, max_epochs);
+    if (s) return s;
+    gepochs = (uint64_t)c->hdr_host->run_epochs;
+    stop_reason = c->hdr_host->stop_reason;
+    s = sync_states(c);
+    if (s) return s;
+  }
+  if (out) {
+    out->global_epochs = gepochs;
+    uint64_t tasks = 0;
+    int live = 0;
+    for (int i : before) {
+      HostTree &t = c->trees[i];
+      if (t.hstatus == H_DONE) tasks += (uint64_t)t.st.tasks;
+      else if (t.hstatus == H_LIVE) ++live;
+    }
+    out->tasks = tasks;
+    out->live = live;
+    out->stop_reason = stop_reason;
+    out->grid = (sched == TREES_SCHED_PLAIN) ? 0 : c->last_grid;
+    out->api_blocks_per_cu = c->last_api_bpc;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (stop_reason == 4) return fail(c, TREES_E_DEVICE, "persistent barrier timed out");
+  return TREES_OK;
+}
+
+static HostTree *find_tree(trees_ctx *c, uint64_t id, int *slot) {
+  const int s = (int)(uint32_t)id;
+  const uint32_t gen = (uint32_t)(id >> 32);
+  if (s < 0 || s >= c->tmax) return nullptr;
+  HostTree &t = c->trees[s];
+  if (t.hstatus == H_FREE || t.gen != gen) return nullptr;
+  *slot = s;
+  return &t;
+}
+
+trees_status trees_results(trees_ctx *c, uint64_t tree, int64_t *out_value, trees_tree_stats *out) {
+  if (!c) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  int slot;
+  HostTree *t = find_tree(c, tree, &slot);
+  if (!t) return fail(c, TREES_E_INVALID, "unknown tree id");
+  if (t->hstatus != H_DONE) {
+    if (out) { memset(out, 0, sizeof(*out)); out->status = TREES_E_PENDING; }
+    return TREES_E_PENDING;
+  }
+  const TreeState &st = t->st;
+  if (out_value) *out_value = st.result;
+  if (out) {
+    out->status = st.err;
+    out->epochs = (uint32_t)st.epochs;
+    out->tasks = (uint64_t)st.tasks;
+    out->launched = (uint64_t)st.launched;
+    out->peak_entries = (uint64_t)st.peak;
+    out->start_epoch = st.start_gepoch;
+    out->done_epoch = st.done_gepoch;
+  }
+  const trees_status rc = st.err;
+  arena_free(c, t->base, t->cap);
+  t->hstatus = H_FREE;
+  t->gen++;
+  t->trace.clear();
+  c->ntrees--;
+  return rc;
+}
+
+trees_status trees_trace(trees_ctx *c, uint64_t tree, trees_epoch_rec *out, int32_t cap, int32_t *n) {
+  if (!c || !n) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  int slot;
+  HostTree *t = find_tree(c, tree, &slot);
+  if (!t) return fail(c, TREES_E_INVALID, "unknown tree id");
+  static_assert(sizeof(TraceRec) == sizeof(trees_epoch_rec), "trace record layout");
+  if (t->host_trace) {
+    const int m = std::min<int>(cap, (int)t->trace.size());
+    if (m > 0) memcpy(out, t->trace.data(), sizeof(TraceRec) * m);
+    *n = (int)t->trace.size();
+    return TREES_OK;
+  }
+  if (!c->dc.trace) return fail(c, TREES_E_STATE, "context created without TREES_F_TRACE");
+  const int total = std::min<int>(t->st.ntrace, kTraceMax);
+  const int m = std::min<int>(cap, total);
+  if (m > 0)
+    HIPCHK(c, hipMemcpy(out, c->dc.trace + (size_t)slot * kTraceMax, sizeof(TraceRec) * m, hipMemcpyDeviceToHost));
+  *n = total;
+  return TREES_OK;
+}
+
+trees_status trees_abort(trees_ctx *c) {
+  if (!c || !c->abort_flag) return TREES_E_INVALID;
+  __atomic_store_n(c->abort_flag, 1, __ATOMIC_SEQ_CST);
+  return TREES_OK;
+}
+
+trees_status trees_set_schedule(trees_ctx *c, int32_t sched, int32_t wg, int32_t bpc, int32_t chunk) {
+  if (!c) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (sched < 0 || sched > TREES_SCHED_AUTO) return fail(c, TREES_E_INVALID, "bad scheduler");
+  if (wg && wg != 256 && wg != 512 && wg != 1024) return fail(c, TREES_E_INVALID, "bad wg_size");
+  c->sched = sched;
+  if (wg) c->wg = wg;
+  c->bpc = bpc;
+  if (chunk > 0) c->chunk = chunk;
+  return TREES_OK;
+}
+
+trees_status trees_tv_bound(int32_t kind, const int64_t *args, int32_t nargs, int64_t *entries) {
+  if (!entries) return TREES_E_INVALID;
+  return tv_bound(kind, args, nargs, entries, nullptr);
+}
+
+int64_t trees_free_entries(const trees_ctx *c) { return c ? c->free_ent : 0; }
+
+int32_t trees_num_trees(const trees_ctx *c) { return c ? c->ntrees : 0; }
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Device-side state of the TREES runtime, shared by the host library and the
+// HIP kernels.  All layouts are plain structs in HBM.
+//
+// Task vector (Section 5.1.2): structure-of-arrays, one slot per TVM core.
+//   code[i]  = epoch * NumTaskTypes + type   (0 = invalid / finished)
+//   a0..a3[i] = task arguments (int32)
+//   r[i]     = the value an emitting task leaves in its own entry (int64)
+// Each tree owns a contiguous arena [base, base + cap) of the task vector;
+// all indices stored inside the task vector are arena-relative.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace trees {
+
+constexpr int kMaxTypes = 31;     // global task-type ids 1..NTT, NTT <= 31
+constexpr int kStackMax = 128;    // stack records per tree
+constexpr int kTraceMax = 256;    // per-epoch trace records per tree
+constexpr int kLeaf = 64;         // merge-sort ranges of <= 64 keys are leaves
+
+// Operations a task type can run.
+enum Op : int32_t {
+  OP_NONE = 0,
+  OP_FIB32 = 1, OP_SUM32 = 2,
+  OP_FIB64 = 3, OP_SUM64 = 4,
+  OP_MS = 5, OP_MERGE = 6,
+  OP_Q = 7, OP_QSUM = 8,
+  OP_VISIT = 9,
+  OP_COUNT = 10
+};
+constexpr uint32_t opbit(int op) { return 1u << op; }
+constexpr uint32_t OPS_FIB = opbit(OP_FIB32) | opbit(OP_SUM32) | opbit(OP_FIB64) | opbit(OP_SUM64);
+constexpr uint32_t OPS_NQ = opbit(OP_Q) | opbit(OP_QSUM);
+constexpr uint32_t OPS_MS = opbit(OP_MS) | opbit(OP_MERGE);
+constexpr uint32_t OPS_BFS = opbit(OP_VISIT);
+constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS;
+
+// Tree status values (TreeState::status).
+enum : int32_t { TS_FREE = 0, TS_LIVE = 1, TS_DONE = 2, TS_PAUSED = 3 };
+// Error flags raised by kernels (TreeHot::flags, atomic OR).
+enum : int32_t { TF_OVERFLOW = 1, TF_ENCODING = 2, TF_STACK = 4 };
+
+// Immutable per-tree descriptor (written at submit).
+struct TreeStatic {
+  int64_t base;      // arena offset in task-vector entries
+  int32_t cap;       // arena capacity in entries
+  int32_t tbase;     // global type id of the program's first type
+  int32_t kind;      // trees_builtin
+  int32_t p0, p1;    // fib n | nqueens n | msort N | bfs V, source
+  int32_t pad;
+  uint64_t ptr0, ptr1, ptr2;  // msort: keys, tmp; bfs: row_ptr, col_idx, depth
+};
+
+// Per-tree counters updated with device-scope atomics during an epoch.
+// One 64-byte block per tree so trees never share a line.
+struct alignas(64) TreeHot {
+  int32_t nfc;        // nextFreeCore, arena-relative
+  int32_t flags;      // TF_* error bits
+  uint64_t done;      // items finished this epoch (low 32) | joins (high 32)
+  int32_t valid;      // valid tasks this epoch (trace only)
+  int32_t pad[11];
+};
+
+// Per-tree scheduler state.  Written only by the work-group that finishes
+// the tree's epoch, read across the epoch barrier.
+struct alignas(128) TreeState {
+  int32_t cen, b, e, old;    // current epoch number and range, oldNextFreeCore
+  int32_t sp;                // stack depth
+  int32_t status;            // TS_*
+  int32_t err;               // 0 or a trees_status error code
+  int32_t epochs;            // epochs executed
+  int64_t tasks;             // valid task executions (root counted at submit)
+  int64_t launched;          // lanes launched over all epochs
+  int64_t result;            // r[root] once done
+  int64_t done_gepoch;       // global epoch at completion
+  int64_t start_gepoch;      // global epoch of the first executed epoch (-1: not started)
+  int32_t peak;              // high-water mark of nfc
+  int32_t ntrace;            // trace records written
+  int32_t pad[8];
+};
+
+struct TraceRec {
+  int32_t epoch, cen, b, e, launched, valid, forks, joins, nfc;
+};
+
+// Scheduler header.  The barrier words sit on their own cache lines.
+struct SchedHdr {
+  uint32_t S;           // items in the current work list
+  int32_t L;            // work-list entries
+  int32_t stop;         // non-zero: kernels exit at the next epoch boundary
+  int32_t live;         // live trees after the last scan
+  int64_t gepoch;       // global epochs executed by this context
+  int64_t run_epochs;   // epochs executed in the current run
+  int64_t max_epochs;   // budget of the current run (< 0: none)
+  int32_t done_count;   // trees finished in the current epoch (done_list length)
+  int32_t stop_reason;  // 1 = drained, 2 = epoch budget, 3 = abort, 4 = timeout
+  int32_t tslots;       // slots [0, tslots) may hold trees
+  int32_t pad0[15];
+  alignas(128) uint32_t arrive;   // barrier arrival counter
+  int32_t pad1[31];
+  alignas(128) uint32_t gen;      // barrier generation
+  int32_t pad2[31];
+};
+
+// Counters used by the plain scheduler (double-buffered by epoch parity, so
+// the host never has to clear them: epoch k clears the other parity).
+struct PlainCounters {
+  int32_t forks[2];
+  int32_t joins[2];
+  int32_t valid[2];
+  int32_t flags[2];
+};
+
+// Everything a kernel needs, passed by value.
+struct DevCtx {
+  int32_t *code, *a0, *a1, *a2, *a3;
+  int64_t *r;
+  const TreeStatic *ts;
+  TreeState *st;
+  TreeHot *hot;
+  int32_t *t_len, *t_cen, *t_b;   // next-epoch range per tree (finisher -> scan)
+  int4 *stack;                    // [slot * kStackMax + k] = {cen, b, e, cend}
+  TraceRec *trace;                // [slot * kTraceMax + k] or null
+  int32_t *wl_tree;               // work list: tree slot
+  uint32_t *wl_off;               // exclusive prefix of range lengths (L+1 entries)
+  int64_t *wl_start;              // absolute task-vector index of the range start
+  int32_t *wl_cen;                // epoch number of the entry
+  int32_t *done_list;             // trees finished in this epoch
+  SchedHdr *hdr;
+  PlainCounters *plain;
+  const volatile int32_t *abort_flag;  // host-pinned, set by trees_abort
+  int32_t ntt;
+  int32_t trace_on;
+  int32_t debug;
+  int32_t pad;
+  int64_t timeout_ticks;          // spin limit at the grid barrier (100 MHz clock ticks)
+  uint8_t op_of_type[kMaxTypes + 1];
+};
+
+// One staged submission, applied on the device by the admission kernel.
+struct Admit {
+  int32_t slot, root_code, a0, a1, a2, a3;
+  TreeStatic ts;
+};
+
+// Arguments of one plain-scheduler epoch (one tree, host-driven).
+struct PlainArgs {
+  int32_t slot, cen, b, e, nfc0, par;
+};
+
+}  // namespace trees

@@ -1,0 +1,110 @@
+"""Helpers for the GPU parity tests: run task trees through the C ABI (via
+the ctypes binding) and fetch what the oracle is compared with."""
+from __future__ import annotations
+
+import numpy as np
+
+SCHEDS = ["plain", "graph", "persistent"]
+
+KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5}
+
+
+def to_dev_u32(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to("cuda")
+
+
+def to_dev_i32(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to("cuda")
+
+
+def from_dev_u32(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def register_all(ctx, jobs):
+    """Every program must be registered before the first submit."""
+    for k in sorted({j.kind for j in jobs}):
+        ctx.register(KIND_OF[k])
+
+
+class Job:
+    """One tree: its spec, payload tensors and, after collect(), its outputs."""
+
+    def __init__(self, kind: str, n=None, keys=None, graph=None):
+        self.kind, self.n, self.keys, self.graph = kind, n, keys, graph
+        self.tree = None
+        self.value = None
+        self.stats = None
+        self.trace = None
+        self.out = None
+        self.bufs = ()
+
+    def submit(self, ctx):
+        import torch
+        import paper_1608_00571_amd as T
+        prog = ctx.register(KIND_OF[self.kind])
+        if self.kind in ("fib32", "fib64", "nqueens"):
+            self.tree = ctx.submit(prog, [self.n])
+        elif self.kind == "msort":
+            k = to_dev_u32(self.keys)
+            tmp = torch.empty_like(k)
+            self.bufs = (k, tmp)
+            self.tree = ctx.submit(prog, [self.keys.shape[0]], [k, tmp])
+        elif self.kind == "bfs":
+            g = self.graph
+            rp, ci = to_dev_i32(g.row_ptr), to_dev_i32(g.col_idx)
+            if ci.numel() == 0:
+                ci = torch.zeros(1, dtype=torch.int32, device="cuda")
+            d = torch.empty(g.V, dtype=torch.int32, device="cuda")
+            self.bufs = (rp, ci, d)
+            self.tree = ctx.submit(prog, [g.V, g.source], [rp, ci, d])
+        else:
+            raise ValueError(self.kind)
+        return self.tree
+
+    def collect(self, ctx, trace=False):
+        if trace:
+            self.trace = ctx.trace(self.tree)
+        self.value, self.stats = ctx.results(self.tree)
+        if self.kind == "msort":
+            self.out = from_dev_u32(self.bufs[0])
+        elif self.kind == "bfs":
+            self.out = self.bufs[2].cpu().numpy()
+        return self
+
+
+def oracle_run(job: Job):
+    """The oracle's emulation of the same tree: (Run, output array or None)."""
+    import oracle
+    if job.kind == "fib32":
+        return oracle.fib(job.n, width=32, records=True), None
+    if job.kind == "fib64":
+        return oracle.fib(job.n, width=64, records=True), None
+    if job.kind == "nqueens":
+        return oracle.nqueens(job.n, records=True), None
+    if job.kind == "msort":
+        out, r = oracle.msort(job.keys, records=True)
+        return r, out
+    if job.kind == "bfs":
+        g = job.graph
+        d, r = oracle.bfs(g.V, g.row_ptr, g.col_idx, g.source, records=True)
+        return r, d
+    raise ValueError(job.kind)
+
+
+def assert_matches_oracle(job: Job, check_trace=True):
+    want, out = oracle_run(job)
+    s = job.stats
+    got = (job.value if job.kind not in ("msort", "bfs") else want.result, s.epochs, s.tasks,
+           s.launched, s.peak_entries)
+    exp = (want.result, want.epochs, want.tasks, want.launched, want.peak)
+    assert got == exp, f"{job.kind} {job.n}: got {got} want {exp}"
+    if out is not None:
+        assert np.array_equal(job.out, out), f"{job.kind}: output differs"
+    if check_trace and job.trace is not None and want.records is not None:
+        n = min(len(job.trace), 256)
+        w = want.records[:n]
+        for f in ("epoch", "cen", "b", "e", "launched", "valid", "forks", "joins", "nfc"):
+            assert np.array_equal(job.trace[f][:n], w[f]), f"{job.kind} {job.n}: trace field {f} differs"

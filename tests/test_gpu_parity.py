@@ -1,0 +1,114 @@
+"""GPU parity: every program, under every scheduler, through the C ABI,
+element by element against the CPU oracle (results, per-tree statistics and
+the per-epoch trace; all integer, so bit-exact)."""
+import numpy as np
+import pytest
+
+import inputs
+from tests.gpu_util import SCHEDS, Job, assert_matches_oracle, register_all
+
+pytestmark = pytest.mark.gpu
+
+ARENA = 256 << 20
+
+
+def make_ctx(sched, trace=True, **kw):
+    import paper_1608_00571_amd as T
+    return T.Context(ARENA, sched=sched, trace=trace, timeout_s=20.0, **kw)
+
+
+def run_alone(sched, jobs, trace=True):
+    with make_ctx(sched, trace=trace) as ctx:
+        register_all(ctx, jobs)
+        for j in jobs:
+            j.submit(ctx)
+        ctx.run()
+        for j in jobs:
+            j.collect(ctx, trace=trace)
+    return jobs
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("kind", ["fib32", "fib64"])
+def test_fib(sched, kind):
+    for n in [0, 1, 2, 3, 5, 10, 17, 22]:
+        (j,) = run_alone(sched, [Job(kind, n)])
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_nqueens(sched):
+    for n in range(1, 10):
+        (j,) = run_alone(sched, [Job("nqueens", n)])
+        assert_matches_oracle(j)
+
+
+MSORT_SIZES = [0, 1, 2, 63, 64, 65, 129, 1000, 4096, (1 << 16) + 3]
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_msort(sched):
+    for n in MSORT_SIZES:
+        keys = inputs.keys_u32(n, 1000 + n)
+        (j,) = run_alone(sched, [Job("msort", keys=keys)])
+        assert_matches_oracle(j)
+
+
+def tiny_graphs():
+    from tests.test_oracle_bfs import tiny_graphs as tg
+    out = []
+    for name, (V, arcs, s) in tg().items():
+        out.append((name, inputs.csr_from_arcs(V, arcs, s)))
+    for scale, seed in [(8, 1), (10, 2), (12, 3)]:
+        out.append((f"rmat{scale}", inputs.rmat(scale, seed)))
+    return out
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_bfs(sched):
+    for name, g in tiny_graphs():
+        (j,) = run_alone(sched, [Job("bfs", graph=g)])
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+def test_mixed_batch_equals_alone(sched):
+    """Independent trees of every program share epochs; each tree's result,
+    statistics and trace equal its own oracle run; the batch takes as many
+    global epochs as its longest tree."""
+    jobs = []
+    for k, n in [("fib64", 15), ("nqueens", 7), ("fib32", 9), ("nqueens", 5), ("fib64", 1)]:
+        jobs.append(Job(k, n))
+    jobs.append(Job("msort", keys=inputs.keys_u32(3000, 5)))
+    jobs.append(Job("msort", keys=inputs.keys_u32(64, 6)))
+    jobs.append(Job("bfs", graph=inputs.rmat(9, 4)))
+    jobs.append(Job("bfs", graph=inputs.csr_from_arcs(5, [(0, 1), (1, 2), (2, 3), (3, 4)], 0)))
+    with make_ctx(sched) as ctx:
+        register_all(ctx, jobs)
+        for j in jobs:
+            j.submit(ctx)
+        rs = ctx.run()
+        for j in jobs:
+            j.collect(ctx, trace=True)
+    for j in jobs:
+        assert_matches_oracle(j)
+        assert j.stats.start_epoch == 0
+        assert j.stats.done_epoch == j.stats.epochs - 1
+    assert rs.global_epochs == max(j.stats.epochs for j in jobs)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+def test_many_small_trees(sched):
+    """Hundreds of small trees: work-groups straddle many trees, so the
+    segmented fork allocation and per-tree finishing are exercised."""
+    mix = inputs.batch_mix(600, fib_range=(0, 12), nq_range=(1, 7))
+    jobs = [Job("fib64" if k == "fib" else "nqueens", n) for k, n in mix]
+    with make_ctx(sched) as ctx:
+        register_all(ctx, jobs)
+        for j in jobs:
+            j.submit(ctx)
+        ctx.run()
+        for j in jobs:
+            j.collect(ctx, trace=True)
+    for j in jobs:
+        assert_matches_oracle(j)
