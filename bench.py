@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the TREES epoch path on one MI355X.
+
+Default workload (one "step"): the two programs of the plain-scheduler
+configuration, run back to back through the C ABI --
+  * naive fib(32) with 64-bit sums: 10,573,732 tasks in 63 epochs;
+  * merge sort of 2^24 uint32 keys drawn uniformly from a seed (split in
+    halves, runs of <= 64 keys insertion sorted, merge continuation):
+    786,430 tasks in 37 epochs;
+under the plain scheduler (one launch per epoch, Phases 1 and 3 on the host).
+Inputs are resident in HBM before the timed region; every step sorts its own
+fresh copy of the keys.
+
+Prints one JSON line: tasks/s over the whole step (the metric), epochs/s,
+the roofline of the dominant epoch kernel (algorithmic bytes / HIP-event
+kernel time, against 8 TB/s HBM), and the CPU oracle timed on this host.
+
+    python bench.py [--steps K] [--warmup W] [--config 2|1|3|4] [--sched plain|graph|persistent]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic bytes (task-vector fields each task type must touch, reads +
+# writes, plus payload bytes), per program.
+# ---------------------------------------------------------------------------
+def fib_counts(n: int):
+    F = [0, 1]
+    for _ in range(n + 2):
+        F.append(F[-1] + F[-2])
+    if n < 2:
+        return dict(leaves=1, internal=0, sums=0)
+    return dict(leaves=F[n + 1], internal=F[n + 1] - 1, sums=F[n + 1] - 1)
+
+
+def fib_bytes(n: int, launched: int, tasks: int, rbytes: int = 8) -> dict:
+    c = fib_counts(n)
+    idle = launched - tasks
+    # FIB leaf: read code, a0; write r, code.  FIB internal: read code, a0;
+    # write 2 children (code, a0) and own (code, a0).  SUM: read code, a0,
+    # two child r; write r, code.  Idle lane: read code.
+    tv = c["leaves"] * (8 + rbytes + 4) + c["internal"] * 32 + c["sums"] * (8 + 2 * rbytes + rbytes + 4) \
+        + idle * 4
+    return dict(tv=tv, payload=0)
+
+
+def msort_counts(N: int):
+    """(MS internal, leaves, merged keys over all merges, leaf keys)."""
+    memo = {}
+
+    def rec(n):
+        if n in memo:
+            return memo[n]
+        if n <= 64:
+            r = (0, 1, 0)
+        else:
+            a, b = rec(n // 2), rec(n - n // 2)
+            r = (1 + a[0] + b[0], a[1] + b[1], n + a[2] + b[2])
+        memo[n] = r
+        return r
+
+    internal, leaves, merged = rec(N)
+    return internal, leaves, merged
+
+
+def msort_bytes(N: int, launched: int, tasks: int) -> dict:
+    internal, leaves, merged = msort_counts(N)
+    merges = internal
+    idle = launched - tasks
+    # MS internal: read code, a0..a2; write 2 children (code, a0..a2), own code.
+    # MS leaf / MERGE: read code, a0..a2; write code.  Idle: read code.
+    tv = internal * 52 + leaves * 20 + merges * 20 + idle * 4
+    payload = 8 * N + 8 * merged   # every key read + written once per leaf sort and per merge level
+    return dict(tv=tv, payload=payload)
+
+
+# ---------------------------------------------------------------------------
+def cpu_baseline_cfg2(sample_keys_log2: int = 24):
+    """The oracle's epoch emulator on this host's cores: fib(32) and a merge
+    sort of 2^k keys (single-threaded C)."""
+    import inputs
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.fib(32)
+    keys = inputs.keys_u32(1 << sample_keys_log2, inputs.item_seed(2, 0))
+    _, m = oracle.msort(keys)
+    dt = time.perf_counter() - t0
+    tasks = r.tasks + m.tasks
+    return {"value": tasks / dt, "unit": "tasks/s", "cores": 1, "kind": "oracle",
+            "sample": f"epoch emulator: fib(32) + msort 2^{sample_keys_log2} (full step, {dt:.1f} s)"}
+
+
+def run_cfg2(args, sched, steps, warmup, nomap=False, key_bufs=None, keys_np=None):
+    """Time `steps` steps of fib(32) + msort under one scheduler."""
+    import numpy as np
+    import torch
+
+    import paper_1608_00571_amd as T
+
+    N = 1 << args.log2n
+    tmp = torch.empty_like(key_bufs[0])
+    arena = (T.tv_bound(T.FIB_I64, [32]) + T.tv_bound(T.MSORT_U32, [N]) + 1024) * T.BYTES_PER_ENTRY
+    ctx = T.Context(arena, sched=sched, wg=args.wg, profile=True, nomap=nomap, max_trees=8)
+    pf = ctx.register(T.FIB_I64)
+    pm = ctx.register(T.MSORT_U32)
+    base = key_bufs[-1]
+
+    def step(k):
+        tf = ctx.submit(pf, [32])
+        tm = ctx.submit(pm, [N], [key_bufs[k], tmp])
+        rs = ctx.run()
+        vf, sf = ctx.results(tf)
+        _, sm = ctx.results(tm)
+        return vf, sf, sm, rs
+
+    for k in range(warmup):
+        key_bufs[k].copy_(base)
+        step(k)
+    for k in range(steps):
+        key_bufs[k].copy_(base)
+    kt0 = ctx.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [step(k) for k in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt1 = ctx.kernel_times()
+    ref = np.sort(keys_np)
+    for k, (vf, sf, sm, rs) in enumerate(outs):
+        assert vf == 2178309 and sf.tasks == 10573732 and sf.epochs == 63, (vf, sf)
+        got = key_bufs[k].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ref), "sorted keys differ from np.sort"
+    ctx.close()
+    kt = {k: (kt1[k][0] - kt0[k][0], kt1[k][1] - kt0[k][1]) for k in kt1}
+    return dict(dt=dt, outs=outs, kt=kt)
+
+
+def bench_cfg2(args):
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1608_00571_amd as T
+
+    N = 1 << args.log2n
+    keys_np = inputs.msort_keys(N)
+    nbuf = max(args.steps, args.warmup, 1)
+    base = torch.from_numpy(keys_np.view(np.int32)).to("cuda")
+    key_bufs = [base.clone() for _ in range(nbuf)] + [base]
+    torch.cuda.synchronize()
+
+    r = run_cfg2(args, args.sched, args.steps, args.warmup, key_bufs=key_bufs, keys_np=keys_np)
+    dt, outs, kt = r["dt"], r["outs"], r["kt"]
+    vf, sf, sm, rs = outs[-1]
+    tasks = sf.tasks + sm.tasks
+    epochs = sf.epochs + sm.epochs
+    ms_step = dt * 1e3 / args.steps
+
+    # roofline of the dominant kernel (HIP-event time of its launches)
+    bf = fib_bytes(32, sf.launched, sf.tasks)
+    bm = msort_bytes(N, sm.launched, sm.tasks)
+    internal, leaves, merged = msort_counts(N)
+    per = {
+        "k_plain<FIB>": dict(ms=kt[T.FIB_I64][0], launches=kt[T.FIB_I64][1],
+                             bytes=bf["tv"] * args.steps, tv=bf["tv"] * args.steps),
+        # the msort epoch kernel: task-vector traffic + leaf sorts (8 B per key)
+        "k_plain<MS>": dict(ms=kt[T.MSORT_U32][0], launches=kt[T.MSORT_U32][1],
+                            bytes=(bm["tv"] + 8 * N) * args.steps, tv=bm["tv"] * args.steps),
+        # the map launches: every merge level reads and writes each key once
+        "k_map": dict(ms=kt[6][0], launches=kt[6][1], bytes=8 * merged * args.steps, tv=0),
+    }
+    dom = max(per, key=lambda k: per[k]["ms"])
+    d = per[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+            "kernel": dom, "launches": d["launches"],
+            "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 3),
+            "algorithmic_bytes_per_launch": int(d["bytes"] / max(1, d["launches"]))}
+    kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 3),
+                   "launches_per_step": v["launches"] // args.steps,
+                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2) if v["ms"] else None,
+                   "tv_GBps": round(v["tv"] / (v["ms"] * 1e-3) / 1e9, 2) if v["ms"] else None}
+               for k, v in per.items()}
+    line = {
+        "metric": "tasks/s", "value": tasks / (dt / args.steps), "unit": "tasks/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+u32",
+        "data": "synthetic",
+        "config": {"workload": f"fib(32) int64 + msort 2^{args.log2n} uint32, {args.sched} scheduler",
+                   "sched": args.sched, "wg": args.wg, "tasks_per_step": tasks, "epochs_per_step": epochs},
+        "epochs_per_s": epochs / (dt / args.steps),
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    if args.compare:
+        alt = {}
+        for sched in ("graph", "persistent"):
+            if sched == args.sched:
+                continue
+            rr = run_cfg2(args, sched, 2, 1, key_bufs=key_bufs, keys_np=keys_np)
+            alt[sched] = {"tasks_per_s": tasks / (rr["dt"] / 2), "ms_per_step": round(rr["dt"] * 1e3 / 2, 3)}
+        rr = run_cfg2(args, "plain", 1, 0, nomap=True, key_bufs=key_bufs, keys_np=keys_np)
+        alt["plain_naive_merge"] = {"tasks_per_s": tasks / rr["dt"], "ms_per_step": round(rr["dt"] * 1e3, 3),
+                                    "note": "merges serial in one lane (no map)"}
+        line["same_workload"] = alt
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--sched", default="plain")
+    ap.add_argument("--wg", type=int, default=256)
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="skip the graph / persistent / naive-merge runs of the same workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)
+        sys.exit(2)
+    if args.config != 2:
+        print("bench.py: only --config 2 is wired in this version", file=sys.stderr)
+        sys.exit(2)
+    line = bench_cfg2(args)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_cfg2()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

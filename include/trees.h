@@ -61,8 +61,13 @@ typedef enum {
 } trees_sched;
 
 enum {
-  TREES_F_TRACE = 1u,  /* record per-epoch (CEN, range, valid, forks, joins) per tree */
-  TREES_F_DEBUG = 2u
+  TREES_F_TRACE = 1u,   /* record per-epoch (CEN, range, valid, forks, joins) per tree */
+  TREES_F_DEBUG = 2u,
+  TREES_F_PROFILE = 4u, /* time every epoch launch with HIP events (trees_kernel_times) */
+  TREES_F_NOMAP = 8u    /* merge continuations merge serially in their own lane (the paper's
+                         * naive mergesort) instead of registering a data-parallel map job
+                         * (Section 4.2) that a co-operative merge-path launch runs before
+                         * the next epoch */
 };
 
 typedef struct {
@@ -173,6 +178,18 @@ trees_status trees_results(trees_ctx *ctx, uint64_t tree, int64_t *out_value,
  * trees_results releases the tree. */
 trees_status trees_trace(trees_ctx *ctx, uint64_t tree, trees_epoch_rec *out, int32_t cap,
                          int32_t *n);
+
+/* Device time of epoch launches measured with HIP events recorded on the
+ * context's stream around each launch (needs TREES_F_PROFILE).  out[k] for
+ * k = 1..5 accumulates the plain scheduler's per-epoch launches of program
+ * kind k (trees_builtin); out[0] accumulates batched launches (one graph
+ * replay or one persistent launch each); out[6] the plain scheduler's map
+ * launches.  Copies min(n, 7) entries. */
+typedef struct {
+  double ms;           /* summed launch durations */
+  uint64_t launches;   /* number of timed launches */
+} trees_ktime;
+trees_status trees_kernel_times(trees_ctx *ctx, trees_ktime *out, int32_t n);
 
 /* Request that a running trees_run stop at the next epoch boundary.  Safe to
  * call from another host thread. */

@@ -33,7 +33,7 @@ SCHEDS = {"plain": PLAIN, "graph": GRAPH, "persistent": PERSISTENT, "auto": AUTO
 FIB_I32, FIB_I64, MSORT_U32, NQUEENS, BFS_CSR = 1, 2, 3, 4, 5
 PROGRAMS = {"fib32": FIB_I32, "fib64": FIB_I64, "msort": MSORT_U32, "nqueens": NQUEENS, "bfs": BFS_CSR}
 
-F_TRACE, F_DEBUG = 1, 2
+F_TRACE, F_DEBUG, F_PROFILE, F_NOMAP = 1, 2, 4, 8
 BYTES_PER_ENTRY = 28
 
 
@@ -66,6 +66,10 @@ class _RunStats(ctypes.Structure):
     _fields_ = [("global_epochs", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
                 ("stop_reason", ctypes.c_int32), ("live", ctypes.c_int32), ("seconds", ctypes.c_double),
                 ("grid", ctypes.c_int32), ("api_blocks_per_cu", ctypes.c_int32)]
+
+
+class _KTime(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_uint64)]
 
 
 REC_DTYPE = np.dtype([(n, np.int32) for n in
@@ -104,6 +108,8 @@ def lib():
         L.trees_set_schedule.argtypes = [vp, i32, i32, i32, i32]
         L.trees_tv_bound.restype = i32
         L.trees_tv_bound.argtypes = [i32, ctypes.POINTER(i64), i32, ctypes.POINTER(i64)]
+        L.trees_kernel_times.restype = i32
+        L.trees_kernel_times.argtypes = [vp, ctypes.POINTER(_KTime), i32]
         L.trees_free_entries.restype = i64
         L.trees_free_entries.argtypes = [vp]
         L.trees_num_trees.restype = i32
@@ -114,7 +120,8 @@ def lib():
 
 EXPORTED = ("trees_create", "trees_destroy", "trees_last_error", "trees_register_program",
             "trees_submit", "trees_run", "trees_results", "trees_trace", "trees_abort",
-            "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees")
+            "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees",
+            "trees_kernel_times")
 
 
 @dataclass
@@ -163,7 +170,7 @@ class Context:
 
     def __init__(self, arena_bytes: int = 1 << 30, *, max_trees: int = 4096, sched="persistent",
                  wg: int = 256, blocks_per_cu: int = 0, graph_chunk: int = 8, trace: bool = False,
-                 device: int = 0, timeout_s: float = 0.0):
+                 profile: bool = False, nomap: bool = False, device: int = 0, timeout_s: float = 0.0):
         import torch
         self._torch = torch
         L = lib()
@@ -182,7 +189,7 @@ class Context:
         cfg.wg_size = wg
         cfg.blocks_per_cu = blocks_per_cu
         cfg.graph_chunk = graph_chunk
-        cfg.flags = F_TRACE if trace else 0
+        cfg.flags = (F_TRACE if trace else 0) | (F_PROFILE if profile else 0) | (F_NOMAP if nomap else 0)
         cfg.timeout_s = timeout_s
         h = ctypes.c_void_p(0)
         rc = L.trees_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -282,6 +289,13 @@ class Context:
         n = ctypes.c_int32(0)
         self._check(lib().trees_trace(self.h, tree, out.ctypes.data, 256, ctypes.byref(n)), "trace")
         return out[: min(n.value, 256)].copy()
+
+    def kernel_times(self):
+        """{kind: (ms, launches)}: HIP-event timed epoch launches; kind 0 =
+        batched launches, kind 6 = the plain scheduler's map launches."""
+        arr = (_KTime * 7)()
+        self._check(lib().trees_kernel_times(self.h, arr, 7), "kernel_times")
+        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(7)}
 
     def abort(self):
         self._check(lib().trees_abort(self.h), "abort")

@@ -52,4 +52,38 @@ __device__ __forceinline__ void ms_merge(uint32_t *keys, uint32_t *tmp, int32_t 
   while (j < hi) dst[k++] = src[j++];
 }
 
+// Co-operative leaf sort (Tenet 2): the whole wavefront sorts one run of at
+// most 64 keys, one key per lane, with a bitonic network of lane exchanges.
+// Lanes beyond the run hold the largest key, so the first n lanes end up with
+// the run's keys in order.  Must be called by all 64 lanes.
+__device__ __forceinline__ void wave_sort64(const uint32_t *src, uint32_t *dst, int32_t n) {
+  const int lane = (int)__lane_id();
+  uint32_t v = lane < n ? src[lane] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t w = (uint32_t)__shfl_xor((int)v, j, 64);
+      const bool up = (lane & k) == 0;          // this k-block sorts ascending
+      const bool low = (lane & j) == 0;         // lower partner keeps the smaller key
+      v = (low == up) ? min(v, w) : max(v, w);
+    }
+  }
+  if (lane < n) dst[lane] = v;
+}
+
+// Merge path: how many of the first q outputs of merging A (na keys) and B
+// (nb keys) come from A, when equal keys are taken from A first.
+__device__ __forceinline__ int64_t merge_path(const uint32_t *A, int64_t na, const uint32_t *B,
+                                              int64_t nb, int64_t q) {
+  int64_t lo = q > nb ? q - nb : 0;
+  int64_t hi = q < na ? q : na;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (A[mid] <= B[q - mid - 1]) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 }  // namespace trees

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "bodies.h"
 #include "prims.h"
 #include "trees_dev.h"
@@ -51,6 +53,10 @@ struct Lds {
   int32_t seg_join[WG];
   int32_t seg_valid[WG];
   int32_t scan_tmp[WG / 64 + 1];
+  int64_t scan_tmp64[WG / 64 + 1];
+  uint32_t jbase;          // first map job reserved by this work-group
+  uint64_t ubase;          // first map unit reserved by this work-group
+  uint64_t mwin[WG];       // map job offsets after the tile's first job
   int32_t v_row[WG];       // VISIT: first arc of the lane's vertex
   int32_t v_pre[WG];       // VISIT: exclusive prefix of out-degrees
   int32_t v_seg[WG];
@@ -84,7 +90,7 @@ __device__ __forceinline__ void seg_add(int32_t *arr, int seg, int v) {
 // tree's arena overflowed.
 template <int WG, bool MULTI>
 __device__ __forceinline__ int32_t wg_alloc(const DevCtx &C, Lds<WG> &L, int seg, int nk,
-                                            const PlainArgs &P) {
+                                            const PlainArgs &P, bool with_joins = false) {
   int off = 0;
   uint64_t m = ballot64(nk > 0);
   if (m) {
@@ -106,17 +112,24 @@ __device__ __forceinline__ int32_t wg_alloc(const DevCtx &C, Lds<WG> &L, int seg
   for (int s = threadIdx.x; s < nseg; s += WG) {
     int c = L.seg_cnt[s];
     int b = 0;
-    if (c > 0) {
-      L.seg_cnt[s] = 0;
-      if (MULTI) {
+    if (MULTI) {
+      if (c > 0) {
+        L.seg_cnt[s] = 0;
         int slot = L.seg_slot[s];
         b = add_agent(&C.hot[slot].nfc, (int32_t)c);
         if ((int64_t)b + c > (int64_t)C.ts[slot].cap) {
           L.sink = or_agent(&C.hot[slot].flags, (int32_t)TF_OVERFLOW);
           b = -1;
         }
-      } else {
-        b = add_agent(&C.plain->forks[P.par], (int32_t)c);
+      }
+    } else {
+      // plain form: the work-group's forks and joins in one atomic add
+      const int j = with_joins ? L.seg_join[s] : 0;
+      if (with_joins) L.seg_join[s] = 0;
+      if (c > 0 || j > 0) {
+        L.seg_cnt[s] = 0;
+        const uint64_t prev = add_agent(&C.plain->fj[P.par], ((uint64_t)(uint32_t)j << 32) | (uint32_t)c);
+        b = (int32_t)(uint32_t)prev;
         if ((int64_t)P.nfc0 + b + c > (int64_t)C.ts[P.slot].cap) {
           L.sink = or_agent(&C.plain->flags[P.par], (int32_t)TF_OVERFLOW);
           b = -1;
@@ -290,6 +303,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
   int nk = 0, act = ACT_NONE;
   int64_t val = 0;
   int32_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+  bool want_map = false;
+  bool leaf = false;
   int64_t tb = 0;     // arena base of the lane's tree
   int32_t tbase = 0;  // global type id of the program's first type
   if (op != OP_NONE) {
@@ -332,15 +347,18 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
       case OP_MS: {
         const int32_t lo = C.a0[i], hi = C.a1[i], d = C.a2[i];
         if (hi - lo <= kLeaf) {
-          ms_leaf((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, lo, hi, d);
-          act = ACT_FINISH;
+          act = ACT_FINISH;   // sorted co-operatively below
+          leaf = true;
+          x0 = lo; x1 = hi; x2 = d;
         } else {
           act = ACT_JOIN; nk = 2; x0 = lo; x1 = hi; x2 = d;
         }
       } break;
       case OP_MERGE: {
-        ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, C.a0[i], C.a1[i], C.a2[i]);
         act = ACT_FINISH;
+        x0 = C.a0[i]; x1 = C.a1[i]; x2 = C.a2[i];
+        if (C.mj_cap > 0) want_map = true;   // the merge runs in the map phase
+        else ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0, x1, x2);
       } break;
       case OP_VISIT:
         act = ACT_FINISH;   // its arcs are expanded co-operatively below
@@ -349,8 +367,58 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
     }
   }
 
+  // ---- merge-sort leaves: each wavefront sorts its lanes' runs one after
+  // another, all 64 lanes on each run (the leaf body is "sort these <= 64
+  // keys"; the keys it leaves behind are those of an insertion sort)
+  if (OPS & opbit(OP_MS)) {
+    uint64_t lm = ballot64(leaf);
+    while (lm) {
+      const int l = __ffsll((unsigned long long)lm) - 1;
+      lm &= lm - 1;
+      const int32_t lo = __shfl(x0, l, 64), hi = __shfl(x1, l, 64), d = __shfl(x2, l, 64);
+      const int sl = __shfl(slot, l, 64);
+      const TreeStatic *T = &C.ts[sl];
+      uint32_t *keys = (uint32_t *)T->ptr0;
+      uint32_t *dst = (d & 1) ? (uint32_t *)T->ptr1 : keys;
+      wave_sort64(keys + lo, dst + lo, hi - lo);
+    }
+  }
+
+  // ---- map (Section 4.2): a MERGE continuation hands its merge to the
+  // data-parallel map phase that runs before the next epoch.  One atomic per
+  // work-group reserves job slots and output units together.
+  if (OPS & opbit(OP_MERGE)) {
+    if (__syncthreads_or(want_map)) {
+      int jtot;
+      const int jpre = wg_excl_scan<WG>(want_map ? 1 : 0, L.scan_tmp, &jtot);
+      int64_t utot;
+      const int64_t upre = wg_excl_scan64<WG>(want_map ? (int64_t)(x1 - x0) : 0, L.scan_tmp64, &utot);
+      if (threadIdx.x == 0) {
+        uint64_t *ctr = MULTI ? &C.hdr->map_ctr : &C.plain->map[P.par];
+        const uint64_t prev = add_agent(ctr, ((uint64_t)jtot << kMapShift) | (uint64_t)utot);
+        L.jbase = (uint32_t)(prev >> kMapShift);
+        L.ubase = prev & kMapUnitMask;
+      }
+      __syncthreads();
+      if (want_map) {
+        const uint32_t j = L.jbase + (uint32_t)jpre;
+        if (j < (uint32_t)C.mj_cap) {
+          const TreeStatic *T = &C.ts[slot];
+          C.mj_lo[j] = x0; C.mj_hi[j] = x1;
+          C.mj_src[j] = ((x2 + 1) & 1) ? (const uint32_t *)T->ptr1 : (const uint32_t *)T->ptr0;
+          C.mj_dst[j] = (x2 & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
+          C.mj_off[j] = L.ubase + (uint64_t)upre;
+        } else {   // job list full: this lane merges by itself
+          const TreeStatic *T = &C.ts[slot];
+          ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0, x1, x2);
+        }
+      }
+    }
+  }
+
   // ---- fork: co-operative slot allocation, structure-of-arrays writes ------
-  const int32_t cb = wg_alloc<WG, MULTI>(C, L, seg, nk, P);
+  seg_add(L.seg_join, seg, act == ACT_JOIN ? 1 : 0);   // joins counted per tree segment
+  const int32_t cb = wg_alloc<WG, MULTI>(C, L, seg, nk, P, true);
   if (nk > 0 && cb >= 0) {
     const int64_t c = tb + cb;
     const int32_t nxt = (cen + 1) * ntt + tbase;   // code of local type 1, next epoch
@@ -437,8 +505,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
     }
   }
 
-  // ---- per-tree bookkeeping: joins, valid tasks, retired items ------------
-  seg_add(L.seg_join, seg, act == ACT_JOIN ? 1 : 0);
+  // ---- per-tree bookkeeping: valid tasks, retired items --------------------
   if (C.trace_on) seg_add(L.seg_valid, seg, op != OP_NONE ? 1 : 0);
   __syncthreads();
   const int nseg = L.nseg;
@@ -458,11 +525,181 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
       const uint64_t prev = add_agent(&C.hot[sl].done, add);
       if ((uint32_t)prev + items == end - beg) tree_finish(C, sl, (uint32_t)(prev >> 32) + (uint32_t)j);
     } else {
-      if (j) add_agent(&C.plain->joins[P.par], j);
       if (v) add_agent(&C.plain->valid[P.par], v);
     }
   }
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Map phase: the merges registered in the last epoch, co-operatively, in two
+// passes.  The jobs' outputs are laid end to end (a job of m keys owns m
+// consecutive units) and cut into tiles of kMapTile units.
+//  * partition: one wavefront per tile boundary finds the job holding the
+//    boundary unit (64-ary search over the job offsets) and the merge-path
+//    split there (64-ary search along the diagonal);
+//  * merge: a work-group per tile stages the input runs of every job
+//    portion the tile covers in LDS with coalesced loads, each lane merges
+//    its share out of LDS, and the tile is stored with coalesced writes.
+// ---------------------------------------------------------------------------
+constexpr int kMapTile = 2048;
+constexpr int kMaxPortions = 64;   // merge jobs exceed 64 keys, so a tile meets at most 33
+
+struct MapLds {
+  uint32_t in[kMapTile];
+  uint32_t out[kMapTile];
+  int32_t pbase[kMaxPortions + 1];   // tile-relative first output of each portion
+  int32_t pna[kMaxPortions];         // keys the portion takes from the job's first half
+  int64_t pas[kMaxPortions], pbs[kMaxPortions];   // first key taken from each half
+  int64_t pqs[kMaxPortions];         // job-relative first output of the portion
+  int64_t plo[kMaxPortions], pmid[kMaxPortions];
+  const uint32_t *psrc[kMaxPortions];
+  uint32_t *pdst[kMaxPortions];
+  int32_t P;
+  uint32_t J;
+  uint64_t U;
+};
+
+// 64-ary merge-path search by one wavefront (all 64 lanes): the number of the
+// first q outputs that come from A, equal keys taken from A first.
+__device__ __forceinline__ int64_t wave_merge_path(const uint32_t *A, int64_t na, const uint32_t *B,
+                                                   int64_t nb, int64_t q) {
+  const int lane = lane_id();
+  int64_t lo = q > nb ? q - nb : 0;
+  int64_t hi = q < na ? q : na;
+  while (lo < hi) {
+    const int64_t step = (hi - lo + 63) >> 6;
+    const int64_t pos = lo + (int64_t)lane * step;
+    const bool t = pos < hi && A[pos] <= B[q - pos - 1];
+    const int c = __popcll(ballot64(t));
+    if (c == 0) {
+      hi = lo;
+    } else {
+      const int64_t nlo = lo + (int64_t)(c - 1) * step + 1;
+      hi = min(lo + (int64_t)c * step, hi);
+      lo = nlo;
+    }
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int portion_of(const MapLds &M, int e) {
+  int lo = 0, hi = M.P;   // last portion whose base is <= e
+  while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (M.pbase[mid] <= e) lo = mid; else hi = mid; }
+  return lo;
+}
+
+// Number of usable jobs and the unit count they cover.
+__device__ __forceinline__ void map_extent(const DevCtx &C, uint32_t Jraw, uint32_t *J, uint64_t *U) {
+  *J = min(Jraw, (uint32_t)C.mj_cap);
+  *U = *J ? C.mj_off[*J - 1] + (uint64_t)(C.mj_hi[*J - 1] - C.mj_lo[*J - 1]) : 0;
+  const uint64_t maxU = (uint64_t)(C.part_cap - 1) * kMapTile;
+  if (*U > maxU) *U = maxU;   // (never for the sizes the arena admits)
+}
+
+// Pass 1: the split at every tile boundary.  `wid` / `nwaves` enumerate the
+// wavefronts taking part.
+__device__ void map_partition(const DevCtx &C, uint32_t J, uint64_t U, int64_t wid, int64_t nwaves) {
+  const uint64_t nb = (U + kMapTile - 1) / kMapTile + 1;   // boundaries 0 .. ntiles
+  const int lane = lane_id();
+  for (uint64_t t = (uint64_t)wid; t < nb; t += (uint64_t)nwaves) {
+    const uint64_t u = min(t * kMapTile, U);
+    uint32_t lo = 0, hi = J;   // last job whose offset is <= u (u = U: the last job)
+    while (hi - lo > 1) {
+      const uint32_t step = (hi - lo + 63) >> 6;
+      const uint32_t p = lo + (uint32_t)lane * step;
+      const bool ok = p < hi && C.mj_off[p] <= u;
+      const int j = __popcll(ballot64(ok)) - 1;
+      lo = lo + (uint32_t)j * step;
+      hi = min(lo + step, hi);
+    }
+    const int64_t jlo = C.mj_lo[lo], jhi = C.mj_hi[lo];
+    const int64_t mid = jlo + (jhi - jlo) / 2;
+    const uint32_t *src = C.mj_src[lo];
+    const int64_t q = (int64_t)(u - C.mj_off[lo]);
+    const int64_t ia = wave_merge_path(src + jlo, mid - jlo, src + mid, jhi - mid, q);
+    if (lane == 0) { C.part_job[t] = lo; C.part_ia[t] = ia; }
+  }
+}
+
+// Pass 2: merge tiles.  Every thread of the work-group takes part.
+template <int WG>
+__device__ void map_merge(const DevCtx &C, MapLds &M, uint32_t J, uint64_t U) {
+  constexpr int K = kMapTile / WG;
+  const uint64_t ntiles = (U + kMapTile - 1) / kMapTile;
+  const int tid = threadIdx.x;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t u0 = tile * kMapTile;
+    const uint64_t u1 = min(u0 + (uint64_t)kMapTile, U);
+    const int tl = (int)(u1 - u0);
+    const uint32_t j0 = C.part_job[tile], j1 = C.part_job[tile + 1];
+    const int64_t ia0 = C.part_ia[tile], ia1 = C.part_ia[tile + 1];
+    const int n = (int)(j1 - j0) + 1;   // jobs j0 .. j1 (j1 may start exactly at u1)
+    if (tid < n && tid < kMaxPortions) {
+      const uint32_t j = j0 + tid;
+      const uint64_t off = C.mj_off[j];
+      const int64_t lo = C.mj_lo[j], hi = C.mj_hi[j];
+      const int64_t mid = lo + (hi - lo) / 2;
+      const uint64_t ts0 = max(u0, off);
+      const uint64_t te0 = min(u1, off + (uint64_t)(hi - lo));
+      const int64_t qs = (int64_t)(ts0 - off), qe = (int64_t)(te0 - off);
+      const int64_t as = (j == j0) ? ia0 : 0;
+      const int64_t ae = (j == j1 && te0 == u1 && u1 - off == (uint64_t)qe) ? ia1 : (mid - lo);
+      M.pbase[tid] = (int32_t)(ts0 - u0);
+      M.pqs[tid] = qs;
+      M.plo[tid] = lo;
+      M.pmid[tid] = mid;
+      M.pas[tid] = as;
+      M.pbs[tid] = qs - as;
+      M.pna[tid] = (int32_t)(ae - as);
+      M.psrc[tid] = C.mj_src[j];
+      M.pdst[tid] = C.mj_dst[j];
+    }
+    if (tid == 0) {
+      // the job starting exactly at the tile's end contributes nothing
+      const int P = (n > 1 && C.mj_off[j1] >= u1) ? n - 1 : n;
+      M.P = min(P, kMaxPortions);
+      M.pbase[M.P] = tl;
+    }
+    __syncthreads();
+    // stage the inputs: portion k's first-half keys then its second-half keys
+    for (int e = tid; e < tl; e += WG) {
+      const int k = portion_of(M, e);
+      const int r = e - M.pbase[k];
+      const uint32_t *src = M.psrc[k];
+      M.in[e] = (r < M.pna[k]) ? src[M.plo[k] + M.pas[k] + r] : src[M.pmid[k] + M.pbs[k] + (r - M.pna[k])];
+    }
+    __syncthreads();
+    // every lane merges K consecutive outputs out of LDS
+    {
+      int e = tid * K;
+      const int e1 = min(e + K, tl);
+      while (e < e1) {
+        const int k = portion_of(M, e);
+        const int base = M.pbase[k];
+        const int len = M.pbase[k + 1] - base;
+        const int na = M.pna[k], nb = len - na;
+        const uint32_t *A = M.in + base;
+        const uint32_t *B = A + na;
+        const int o = e - base;
+        int lo = o > nb ? o - nb : 0, hi = o < na ? o : na;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (A[mid] <= B[o - mid - 1]) lo = mid + 1; else hi = mid; }
+        int ia = lo, ib = o - lo;
+        const int cnt = min(e1 - e, len - o);
+        for (int t = 0; t < cnt; ++t) {
+          const bool takeA = ib >= nb || (ia < na && A[ia] <= B[ib]);
+          M.out[e + t] = takeA ? A[ia++] : B[ib++];
+        }
+        e += cnt;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < tl; e += WG) {
+      const int k = portion_of(M, e);
+      M.pdst[k][M.plo[k] + M.pqs[k] + (e - M.pbase[k])] = M.out[e];
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -510,6 +747,11 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
   }
   __syncthreads();
   if (tid == 0) {
+    if (after_epoch) {   // the map jobs of this epoch run before the next one
+      const uint64_t mc = ld_agent(&H->map_ctr);
+      H->mapJ = (uint32_t)(mc >> kMapShift);
+      st_agent(&H->map_ctr, (uint64_t)0);
+    }
     C.wl_off[ctot] = (uint32_t)itot;
     H->S = (uint32_t)itot;
     H->L = ctot;
@@ -544,78 +786,143 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   lds_init<WG>(L);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int q = P.par ^ 1;   // the next epoch's counters
-    C.plain->forks[q] = 0; C.plain->joins[q] = 0; C.plain->valid[q] = 0; C.plain->flags[q] = 0;
+    C.plain->fj[q] = 0; C.plain->valid[q] = 0; C.plain->flags[q] = 0;
+    C.plain->map[q] = 0;
   }
   const uint32_t S = (uint32_t)(P.e - P.b);
   run_chunk<WG, OPS, false>(C, L, blockIdx.x * WG, S, 1, P);
 }
 
-// Batched form.  persistent != 0: a co-resident grid loops over epochs with
-// a device grid barrier.  persistent == 0: one epoch per launch (a chain of
-// such launches is captured in a graph); the last work-group to finish
-// builds the next work list and the kernel boundary is the barrier.
-template <int WG, uint32_t OPS>
-__global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
-  __shared__ Lds<WG> L;
-  __shared__ int32_t s_hdr[3];
-  lds_init<WG>(L);
+// Grid barrier between epochs (Tenet 1: one arrival per work-group).  Every
+// wavefront releases its own task-vector and state writes (a fence by one
+// thread does not cover the other wavefronts' outstanding stores), then one
+// thread arrives.  The last arriver optionally runs the work-list scan and
+// opens the barrier.  wait = false (graph form): the others return at once,
+// the kernel boundary is their barrier.  Returns false if this work-group
+// gave up waiting after the spin limit.
+template <int WG>
+__device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool wait) {
   SchedHdr *H = C.hdr;
-  const PlainArgs P{};
-  while (true) {
-    if (threadIdx.x == 0) { s_hdr[0] = (int32_t)H->S; s_hdr[1] = H->L; s_hdr[2] = H->stop; }
-    __syncthreads();
-    const uint32_t S = (uint32_t)s_hdr[0];
-    const int32_t nL = s_hdr[1];
-    if (s_hdr[2]) break;
-    const uint32_t nchunks = (S + WG - 1) / WG;
-    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
-      run_chunk<WG, OPS, true>(C, L, c * WG, S, nL, P);
-    // ---- epoch barrier: Tenet 1, one arrival per work-group ------------
-    // Every wavefront releases its own task-vector and state writes (each
-    // wavefront must, a fence by one thread does not cover the others'
-    // outstanding stores), then one thread arrives.
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t g = ld_agent(&H->gen);
+    fence_release();
+    const uint32_t a = add_agent(&H->arrive, 1u);
+    L.flag = (a == gridDim.x - 1);
+    L.gen = g;
+  }
+  __syncthreads();
+  if (L.flag) {
+    fence_acquire();
+    if (with_scan) schedule_scan<WG>(C, L, true);
     fence_release();
     __syncthreads();
     if (threadIdx.x == 0) {
-      const uint32_t g = ld_agent(&H->gen);
+      st_agent(&H->arrive, 0u);
       fence_release();
-      const uint32_t a = add_agent(&H->arrive, 1u);
-      L.flag = (a == gridDim.x - 1);
-      L.gen = g;
+      __hip_atomic_store(&H->gen, L.gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (wait) {
+    if (threadIdx.x == 0) {
+      const int64_t t0 = realtime();
+      int timed_out = 0;
+      while (ld_agent(&H->gen) == L.gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (realtime() - t0 > C.timeout_ticks) { timed_out = 1; break; }
+      }
+      L.tflag = timed_out;
+      if (timed_out) {   // give up: every other work-group stops at its next boundary
+        st_agent(&H->stop_reason, 4);
+        st_agent(&H->stop, 1);
+      }
     }
     __syncthreads();
-    if (L.flag) {
-      fence_acquire();
-      schedule_scan<WG>(C, L, true);
-      fence_release();
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        st_agent(&H->arrive, 0u);
-        fence_release();
-        __hip_atomic_store(&H->gen, L.gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (!persistent) break;
-    } else {
-      if (!persistent) break;
-      if (threadIdx.x == 0) {
-        const int64_t t0 = realtime();
-        int timed_out = 0;
-        while (ld_agent(&H->gen) == L.gen) {
-          __builtin_amdgcn_s_sleep(2);
-          if (realtime() - t0 > C.timeout_ticks) { timed_out = 1; break; }
-        }
-        L.tflag = timed_out;
-        if (timed_out) {
-          // give up: every other work-group stops at its next boundary
-          st_agent(&H->stop_reason, 4);
-          st_agent(&H->stop, 1);
-        }
-      }
-      __syncthreads();
-      if (L.tflag) break;
-    }
-    fence_acquire();
+    if (L.tflag) return false;
+  }
+  fence_acquire();
+  __syncthreads();
+  return true;
+}
+
+// Batched form.  persistent != 0: a co-resident grid loops over epochs with
+// device grid barriers; an epoch that registered map jobs is followed by the
+// map phase and one more barrier.  persistent == 0: one epoch per launch (a
+// chain of such launches, each followed by a map launch, is captured in a
+// graph); the last work-group to finish builds the next work list and the
+// kernel boundary is the barrier.
+struct NoMapLds {};
+
+template <int WG, uint32_t OPS>
+__global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
+  constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
+  using MapL = typename std::conditional<kMap, MapLds, NoMapLds>::type;
+  __shared__ Lds<WG> L;
+  __shared__ MapL M;
+  __shared__ uint32_t s_hdr[4];
+  lds_init<WG>(L);
+  if (threadIdx.x == 0) L.tflag = 0;
+  SchedHdr *H = C.hdr;
+  const PlainArgs P{};
+  while (true) {
+    if (threadIdx.x == 0) { s_hdr[0] = H->S; s_hdr[1] = (uint32_t)H->L; s_hdr[2] = (uint32_t)H->stop; s_hdr[3] = H->mapJ; }
     __syncthreads();
+    const uint32_t S = s_hdr[0];
+    const int32_t nL = (int32_t)s_hdr[1];
+    const bool stop = s_hdr[2] != 0;
+    const uint32_t mapJ = persistent ? s_hdr[3] : 0u;
+    if constexpr (kMap) {
+      if (mapJ) {   // merges registered by the previous epoch: partition, barrier, merge
+        uint32_t J;
+        uint64_t U;
+        map_extent(C, mapJ, &J, &U);
+        map_partition(C, J, U, (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6),
+                      (int64_t)gridDim.x * (WG / 64));
+        if (!grid_barrier<WG>(C, L, false, true)) break;
+        map_merge<WG>(C, M, J, U);
+      }
+    }
+    if (stop) break;
+    if (mapJ && !grid_barrier<WG>(C, L, false, true)) break;
+    const uint32_t nchunks = (S + WG - 1) / WG;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+      run_chunk<WG, OPS, true>(C, L, c * WG, S, nL, P);
+    const bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
+    if (!persistent || !ok) break;
+  }
+}
+
+// Map launches (plain and graph forms).  from_hdr: take the job count the
+// last scan recorded; the merge launch clears it when done so that a later
+// launch in a captured chain does not repeat it.
+template <int WG>
+__global__ __launch_bounds__(WG) void k_map_part(DevCtx C, uint32_t Jarg, int32_t from_hdr) {
+  const uint32_t Jraw = from_hdr ? C.hdr->mapJ : Jarg;
+  if (!Jraw) return;
+  uint32_t J;
+  uint64_t U;
+  map_extent(C, Jraw, &J, &U);
+  map_partition(C, J, U, (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6), (int64_t)gridDim.x * (WG / 64));
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_map_merge(DevCtx C, uint32_t Jarg, int32_t from_hdr) {
+  __shared__ MapLds M;
+  const uint32_t Jraw = from_hdr ? C.hdr->mapJ : Jarg;
+  if (!Jraw) return;
+  uint32_t J;
+  uint64_t U;
+  map_extent(C, Jraw, &J, &U);
+  map_merge<WG>(C, M, J, U);
+  if (from_hdr) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t a = add_agent(&C.hdr->map_arrive, 1u);
+      if (a == gridDim.x - 1) {
+        st_agent(&C.hdr->map_arrive, 0u);
+        st_agent(&C.hdr->mapJ, 0u);
+      }
+    }
   }
 }
 
@@ -725,6 +1032,26 @@ hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t ne
   PlainArgs p = P;
   void *args[] = {&c, &p};
   return hipLaunchKernel(fn, grid, block, args, 0, s);
+}
+
+// Map launches: the partition pass then the merge pass.  grid_part and
+// grid_merge are work-group counts (both passes loop over their work).
+hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
+                      hipStream_t s) {
+  const void *fp = nullptr, *fm = nullptr;
+  switch (wg) {
+    case 256: fp = (const void *)&k_map_part<256>; fm = (const void *)&k_map_merge<256>; break;
+    case 512: fp = (const void *)&k_map_part<512>; fm = (const void *)&k_map_merge<512>; break;
+    case 1024: fp = (const void *)&k_map_part<1024>; fm = (const void *)&k_map_merge<1024>; break;
+    default: return hipErrorInvalidValue;
+  }
+  DevCtx c = C;
+  uint32_t j = jobs;
+  int32_t f = from_hdr;
+  void *args[] = {&c, &j, &f};
+  hipError_t e = hipLaunchKernel(fp, dim3(grid_part), dim3(wg), args, 0, s);
+  if (e != hipSuccess) return e;
+  return hipLaunchKernel(fm, dim3(grid_merge), dim3(wg), args, 0, s);
 }
 
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s) {

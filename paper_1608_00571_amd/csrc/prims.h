@@ -70,6 +70,37 @@ __device__ __forceinline__ int wg_excl_scan(int v, int *tmp, int *total) {
   return r;
 }
 
+// 64-bit variant of wg_excl_scan (`tmp` holds WG/64 + 1 int64 of LDS).
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+template <int WG>
+__device__ __forceinline__ int64_t wg_excl_scan64(int64_t v, int64_t *tmp, int64_t *total) {
+  constexpr int NW = WG / 64;
+  const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  int64_t inc = wave_incl_scan64(v);
+  if (lane == 63) tmp[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) { int64_t t = tmp[w]; tmp[w] = s; s += t; }
+    tmp[NW] = s;
+  }
+  __syncthreads();
+  int64_t r = tmp[wave] + inc - v;
+  *total = tmp[NW];
+  __syncthreads();
+  return r;
+}
+
 // Device-scope loads/stores of words that other work-groups update with
 // atomics (they bypass the non-coherent per-XCD L2).
 template <typename T>

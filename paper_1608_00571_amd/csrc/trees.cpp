@@ -19,6 +19,8 @@
 namespace trees {
 hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s);
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s);
+hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
+                      hipStream_t s);
 int coresident_blocks_per_cu(int wg, uint32_t need);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
@@ -31,6 +33,9 @@ using namespace trees;
 namespace {
 
 constexpr int kBytesPerEntry = 28;   // code + a0..a3 (int32) + r (int64)
+constexpr int kMapJobs = 1 << 20;    // map jobs per epoch; merges beyond it run serially
+constexpr uint64_t kMapTileUnits = 2048;   // map tile (kMapTile in the kernels)
+constexpr int kPartCap = 1 << 21;    // tile boundaries: 2^32 merged keys per epoch
 
 std::string g_create_error;
 
@@ -180,6 +185,10 @@ struct trees_ctx {
   int wg = 256, bpc = 0, chunk = 8;
   int ncu = 0;
   int last_grid = 0, last_api_bpc = 0;
+  bool profile = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  trees_ktime ktime[6] = {};
+  trees_ktime mtime = {};     // map launches
   double clock_hz = 1e8;
   bool running = false;
   std::string err;
@@ -300,15 +309,42 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     // Phase 1 happened when the range was popped; launch Phase 2.
     PlainArgs P{slot, st.cen, st.b, st.e, st.old, par};
     if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
+    if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream));
+    if (c->profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->plain_host, c->dc.plain, sizeof(PlainCounters), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const int32_t forks = c->plain_host->forks[par];
-    const int32_t joins = c->plain_host->joins[par];
+    if (c->profile) {
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      c->ktime[t.kind].ms += ms;
+      c->ktime[t.kind].launches += 1;
+    }
+    const int32_t forks = (int32_t)(uint32_t)c->plain_host->fj[par];
+    const int32_t joins = (int32_t)(c->plain_host->fj[par] >> 32);
     const int32_t valid = c->plain_host->valid[par];
     const int32_t flags = c->plain_host->flags[par];
+    const uint64_t mc = c->plain_host->map[par];
     const int32_t nfc = st.old + forks;
+    if (mc >> kMapShift) {
+      // map phase: the merges registered by this epoch, before the next one
+      const uint64_t units = mc & kMapUnitMask;
+      const uint64_t tiles = (units + kMapTileUnits - 1) / kMapTileUnits;
+      const uint64_t cap = (uint64_t)c->ncu * 16;
+      const int gm = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
+      const int gp = (int)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 1 + c->wg / 64 - 1) / (c->wg / 64), cap));
+      if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+      HIPCHK(c, launch_map(c->dc, c->wg, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream));
+      if (c->profile) {
+        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        c->mtime.ms += ms;
+        c->mtime.launches += 1;
+      }
+    }
     if (trace && st.epochs < kTraceMax)
       t.trace.push_back(TraceRec{st.epochs, st.cen, st.b, st.e, st.e - st.b, valid, forks, joins, nfc});
     st.epochs += 1;
@@ -374,6 +410,9 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
   c->hdr_host->max_epochs = max_epochs;
   c->hdr_host->tslots = c->tslots;
   c->hdr_host->arrive = 0;
+  c->hdr_host->mapJ = 0;
+  c->hdr_host->map_ctr = 0;
+  c->hdr_host->map_arrive = 0;
   HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_scan(c->dc, c->stream));
   return TREES_OK;
@@ -415,6 +454,8 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < c->chunk; ++k) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
+      if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
+        e = launch_map(c->dc, c->wg, 0, 1, grid, grid, c->stream);
       if (e != hipSuccess) {
         hipGraph_t g;
         (void)hipStreamEndCapture(c->stream, &g);
@@ -429,9 +470,17 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
   s = read_hdr(c);
   if (s) return s;
   while (!c->hdr_host->stop) {
+    if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    if (c->profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     s = read_hdr(c);
     if (s) return s;
+    if (c->profile) {
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      c->ktime[0].ms += ms;
+      c->ktime[0].launches += 1;
+    }
   }
   return TREES_OK;
 }
@@ -442,8 +491,18 @@ trees_status run_persistent(trees_ctx *c, int64_t max_epochs) {
   const uint32_t need = ops_needed(c);
   const int grid = grid_size(c, need, true);
   c->last_grid = grid;
+  if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   HIPCHK(c, launch_epochs(c->dc, c->wg, need, grid, 1, c->stream));
-  return read_hdr(c);
+  if (c->profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  s = read_hdr(c);
+  if (s) return s;
+  if (c->profile) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->ktime[0].ms += ms;
+    c->ktime[0].launches += 1;
+  }
+  return TREES_OK;
 }
 
 }  // namespace
@@ -524,6 +583,11 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
                o_wo = take((T + 1) * 4), o_ws = take((T + 1) * 8), o_wc = take((T + 1) * 4),
                o_dl = take(T * 4), o_hdr = take(sizeof(SchedHdr)), o_pl = take(sizeof(PlainCounters)),
                o_adm = take(T * sizeof(Admit));
+  const bool nomap = (cfg->flags & TREES_F_NOMAP) != 0;
+  const size_t MJ = nomap ? 0 : (size_t)kMapJobs;
+  const size_t PC = nomap ? 0 : (size_t)kPartCap;
+  const size_t o_mjl = take(MJ * 4), o_mjh = take(MJ * 4), o_mjs = take(MJ * 8), o_mjd = take(MJ * 8),
+               o_mjo = take(MJ * 8), o_pj = take(PC * 4), o_pi = take(PC * 8);
   if (hipMalloc(&c->ctl, off) != hipSuccess) return bail(TREES_E_NOMEM, "hipMalloc of control state failed");
   if (hipMemset(c->ctl, 0, off) != hipSuccess) return bail(TREES_E_DEVICE, "hipMemset failed");
   char *b = (char *)c->ctl;
@@ -543,6 +607,15 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.hdr = (SchedHdr *)(b + o_hdr);
   c->dc.plain = (PlainCounters *)(b + o_pl);
   c->adm_dev = (Admit *)(b + o_adm);
+  c->dc.mj_lo = (int32_t *)(b + o_mjl);
+  c->dc.mj_hi = (int32_t *)(b + o_mjh);
+  c->dc.mj_src = (const uint32_t **)(b + o_mjs);
+  c->dc.mj_dst = (uint32_t **)(b + o_mjd);
+  c->dc.mj_off = (uint64_t *)(b + o_mjo);
+  c->dc.part_job = (uint32_t *)(b + o_pj);
+  c->dc.part_ia = (int64_t *)(b + o_pi);
+  c->dc.mj_cap = (int32_t)MJ;
+  c->dc.part_cap = (int32_t)PC;
   c->dc.trace_on = trace ? 1 : 0;
   c->dc.debug = (cfg->flags & TREES_F_DEBUG) ? 1 : 0;
   const double to = cfg->timeout_s > 0 ? cfg->timeout_s : 60.0;
@@ -560,6 +633,9 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   if (hipHostGetDevicePointer((void **)&dev_abort, c->abort_flag, 0) != hipSuccess)
     return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   c->dc.abort_flag = dev_abort;
+  c->profile = (cfg->flags & TREES_F_PROFILE) != 0;
+  if (c->profile && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess))
+    return bail(TREES_E_DEVICE, "hipEventCreate failed");
   c->trees.resize(c->tmax);
   *out = c;
   return TREES_OK;
@@ -578,6 +654,8 @@ void trees_destroy(trees_ctx *c) {
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->r_host) (void)hipHostFree(c->r_host);
   if (c->abort_flag) (void)hipHostFree(c->abort_flag);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -825,6 +903,15 @@ trees_status trees_set_schedule(trees_ctx *c, int32_t sched, int32_t wg, int32_t
 trees_status trees_tv_bound(int32_t kind, const int64_t *args, int32_t nargs, int64_t *entries) {
   if (!entries) return TREES_E_INVALID;
   return tv_bound(kind, args, nargs, entries, nullptr);
+}
+
+trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
+  if (!c || !out) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
+  for (int k = 0; k < n && k < 6; ++k) out[k] = c->ktime[k];
+  if (n > 6) out[6] = c->mtime;
+  return TREES_OK;
 }
 
 int64_t trees_free_entries(const trees_ctx *c) { return c ? c->free_ent : 0; }

@@ -95,20 +95,30 @@ struct SchedHdr {
   int32_t done_count;   // trees finished in the current epoch (done_list length)
   int32_t stop_reason;  // 1 = drained, 2 = epoch budget, 3 = abort, 4 = timeout
   int32_t tslots;       // slots [0, tslots) may hold trees
-  int32_t pad0[15];
+  uint32_t mapJ;        // map jobs registered by the last epoch (raw count)
+  int32_t pad0[14];
   alignas(128) uint32_t arrive;   // barrier arrival counter
   int32_t pad1[31];
   alignas(128) uint32_t gen;      // barrier generation
   int32_t pad2[31];
+  alignas(128) uint64_t map_ctr;  // (jobs << 38) | units, appended during an epoch
+  uint32_t map_arrive;            // work-groups done with the map launch
+  int32_t pad3[29];
 };
+
+// A map counter packs the job count (high 26 bits) and the job units (low
+// 38 bits) so one atomic add per work-group reserves both, and job indices
+// and unit offsets grow in the same order.
+constexpr int kMapShift = 38;
+constexpr uint64_t kMapUnitMask = (1ull << kMapShift) - 1;
 
 // Counters used by the plain scheduler (double-buffered by epoch parity, so
 // the host never has to clear them: epoch k clears the other parity).
 struct PlainCounters {
-  int32_t forks[2];
-  int32_t joins[2];
+  uint64_t fj[2];      // forks (low 32 bits) | joins (high 32 bits): one atomic per work-group
   int32_t valid[2];
   int32_t flags[2];
+  uint64_t map[2];
 };
 
 // Everything a kernel needs, passed by value.
@@ -134,6 +144,15 @@ struct DevCtx {
   int32_t debug;
   int32_t pad;
   int64_t timeout_ticks;          // spin limit at the grid barrier (100 MHz clock ticks)
+  // map jobs (data-parallel merges registered by MERGE continuations)
+  int32_t *mj_lo, *mj_hi;         // key range [lo, hi); the halves split at lo + (hi - lo) / 2
+  const uint32_t **mj_src;        // buffer holding the two sorted halves
+  uint32_t **mj_dst;              // buffer receiving the merged range
+  uint64_t *mj_off;               // first unit (output key) of the job
+  uint32_t *part_job;             // per tile boundary: job containing the boundary unit
+  int64_t *part_ia;               // per tile boundary: first-half keys before it (merge path)
+  int32_t mj_cap;                 // 0: map disabled, merges run serially in their lane
+  int32_t part_cap;               // tile boundaries the partition arrays hold
   uint8_t op_of_type[kMaxTypes + 1];
 };
 

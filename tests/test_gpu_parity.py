@@ -17,8 +17,8 @@ def make_ctx(sched, trace=True, **kw):
     return T.Context(ARENA, sched=sched, trace=trace, timeout_s=20.0, **kw)
 
 
-def run_alone(sched, jobs, trace=True):
-    with make_ctx(sched, trace=trace) as ctx:
+def run_alone(sched, jobs, trace=True, **kw):
+    with make_ctx(sched, trace=trace, **kw) as ctx:
         register_all(ctx, jobs)
         for j in jobs:
             j.submit(ctx)
@@ -47,10 +47,25 @@ MSORT_SIZES = [0, 1, 2, 63, 64, 65, 129, 1000, 4096, (1 << 16) + 3]
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
-def test_msort(sched):
+@pytest.mark.parametrize("nomap", [False, True])
+def test_msort(sched, nomap):
+    """Merges as data-parallel map jobs (default) and serially in their lane
+    (the naive form): same output, same task statistics."""
     for n in MSORT_SIZES:
         keys = inputs.keys_u32(n, 1000 + n)
-        (j,) = run_alone(sched, [Job("msort", keys=keys)])
+        (j,) = run_alone(sched, [Job("msort", keys=keys)], nomap=nomap)
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_msort_large_map(sched):
+    """2^20 + 5 keys (ragged halves): map jobs span many tiles at the top and
+    many jobs share a tile at the bottom; also heavy duplicates."""
+    for n, mod in [((1 << 20) + 5, None), (300000, 7)]:
+        keys = inputs.keys_u32(n, 77 + n)
+        if mod:
+            keys = keys % np.uint32(mod)
+        (j,) = run_alone(sched, [Job("msort", keys=keys)], trace=False)
         assert_matches_oracle(j)
 
 
