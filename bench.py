@@ -85,6 +85,34 @@ def msort_bytes(N: int, launched: int, tasks: int) -> dict:
     return dict(tv=tv, payload=payload)
 
 
+def nqueens_shape(n: int):
+    """(Q tasks, QSUM tasks, task-vector bytes excluding idle lanes) of the
+    one-task-per-partial-placement N-queens tree, by enumeration."""
+    full = (1 << n) - 1
+    q = qs = tv = 0
+    stack = [(0, 0, 0, 0)]
+    while stack:
+        row, cols, ld, rd = stack.pop()
+        q += 1
+        if row == n:
+            tv += 32
+            continue
+        avail = ~(cols | ld | rd) & full
+        k = bin(avail).count("1")
+        if k == 0:
+            tv += 32
+            continue
+        # Q internal: read code, a0..a3; write k children (code, a0..a3) and own code, a0, a1
+        # QSUM: read code, a0, a1, k child r; write r, code
+        tv += 32 + 20 * k + 24 + 8 * k
+        qs += 1
+        while avail:
+            bit = avail & -avail
+            avail ^= bit
+            stack.append((row + 1, cols | bit, ((ld | bit) << 1) & full, (rd | bit) >> 1))
+    return q, qs, tv
+
+
 # ---------------------------------------------------------------------------
 def cpu_baseline_cfg2(sample_keys_log2: int = 24):
     """The oracle's epoch emulator on this host's cores: fib(32) and a merge
@@ -218,6 +246,92 @@ def bench_cfg2(args):
     return line
 
 
+def bench_cfg3(args):
+    """4096 independent trees (half fib(10..28), half N-queens(6..11)) in
+    shared epochs: persistent and graph forms, and the same trees one at a
+    time under the plain scheduler."""
+    import oracle
+    import torch
+
+    import inputs
+    import paper_1608_00571_amd as T
+
+    mix = inputs.batch_mix(args.trees)
+    kinds = [(T.FIB_I64 if k == "fib" else T.NQUEENS, n) for k, n in mix]
+    # expected per-tree results and statistics (oracle emulation per distinct tree)
+    expect = {}
+    for kind, n in set(kinds):
+        r = oracle.fib(n) if kind == T.FIB_I64 else oracle.nqueens(n)
+        expect[(kind, n)] = (r.result, r.tasks, r.epochs, r.peak, r.launched)
+    nq = {n: nqueens_shape(n) for kind, n in set(kinds) if kind == T.NQUEENS}
+    tv_bytes = 0
+    for kind, n in kinds:
+        res, tasks, epochs, peak, launched = expect[(kind, n)]
+        if kind == T.FIB_I64:
+            tv_bytes += fib_bytes(n, launched, tasks)["tv"]
+        else:
+            tv_bytes += nq[n][2] + 4 * (launched - tasks)
+    total_tasks = sum(expect[k][1] for k in kinds)
+    arena = (sum(T.tv_bound(k, [n]) for k, n in kinds) + 4096) * T.BYTES_PER_ENTRY
+
+    def run(sched, wg, bpc=0, chunk=8, steps=1, warmup=1, subset=None):
+        ks = kinds if subset is None else kinds[:subset]
+        ctx = T.Context(arena, sched=sched, wg=wg, blocks_per_cu=bpc, graph_chunk=chunk, profile=True,
+                        max_trees=len(ks))
+        pf, pq = ctx.register(T.FIB_I64), ctx.register(T.NQUEENS)
+        times, gep = [], 0
+        for it in range(warmup + steps):
+            ids = [ctx.submit(pf if k == T.FIB_I64 else pq, [n]) for k, n in ks]
+            torch.cuda.synchronize()
+            kt0 = ctx.kernel_times()
+            t0 = time.perf_counter()
+            rs = ctx.run()
+            dt = time.perf_counter() - t0
+            kt1 = ctx.kernel_times()
+            for (k, n), t in zip(ks, ids):
+                v, st = ctx.results(t)
+                e = expect[(k, n)]
+                assert (v, st.tasks, st.epochs, st.peak_entries, st.launched) == e, (k, n, v, st, e)
+            if it >= warmup:
+                kms = sum(kt1[x][0] - kt0[x][0] for x in kt1)
+                times.append((dt, kms, rs))
+        ctx.close()
+        dt = min(t[0] for t in times)
+        kms = min(t[1] for t in times)
+        return dict(dt=dt, kernel_ms=kms, rs=times[0][2])
+
+    out = {}
+    for sched in ("persistent", "graph"):
+        r = run(sched, args.wg, steps=args.steps, warmup=args.warmup)
+        out[sched] = {"tasks_per_s": total_tasks / r["dt"], "ms": round(r["dt"] * 1e3, 3),
+                      "kernel_ms": round(r["kernel_ms"], 3), "global_epochs": r["rs"].global_epochs,
+                      "grid": r["rs"].grid,
+                      "tv_GBps_kernel": round(tv_bytes / (r["kernel_ms"] * 1e-3) / 1e9, 1)}
+    best = max(out, key=lambda k: out[k]["tasks_per_s"])
+    # plain: the same trees one after another, one launch per epoch
+    sub = args.plain_subset
+    rp = run("plain", args.wg, steps=1, warmup=0, subset=sub)
+    sub_tasks = sum(expect[k][1] for k in kinds[:sub])
+    out["plain_one_at_a_time"] = {"tasks_per_s": sub_tasks / rp["dt"], "trees": sub, "ms": round(rp["dt"] * 1e3, 1)}
+    factor = out[best]["tasks_per_s"] / out["plain_one_at_a_time"]["tasks_per_s"]
+    ach = tv_bytes / (out[best]["kernel_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "tasks/s", "value": out[best]["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[best]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+int32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(kinds)} trees: fib(10..28) int64 + nqueens(6..11), shared epochs",
+                   "sched": best, "wg": args.wg, "tasks": total_tasks, "tv_bytes": tv_bytes},
+        "epochs_per_s": out[best]["global_epochs"] / (out[best]["ms"] * 1e-3),
+        "schedulers": out,
+        "batched_vs_plain_factor": round(factor, 2),
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"k_epochs<{args.wg},FIB|NQ> ({best})"},
+    }
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +342,8 @@ def main():
     ap.add_argument("--wg", type=int, default=256)
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--trees", type=int, default=4096)
+    ap.add_argument("--plain-subset", type=int, default=4096)
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the graph / persistent / naive-merge runs of the same workload")
     args = ap.parse_args()
@@ -235,12 +351,15 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)
         sys.exit(2)
-    if args.config != 2:
-        print("bench.py: only --config 2 is wired in this version", file=sys.stderr)
+    if args.config == 3:
+        line = bench_cfg3(args)
+    elif args.config == 2:
+        line = bench_cfg2(args)
+        if not args.no_cpu:
+            line["cpu_baseline"] = cpu_baseline_cfg2()
+    else:
+        print(f"bench.py: --config {args.config} is not wired", file=sys.stderr)
         sys.exit(2)
-    line = bench_cfg2(args)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_cfg2()
     print(json.dumps(line), flush=True)
 
 

@@ -56,20 +56,24 @@ __device__ __forceinline__ void ms_merge(uint32_t *keys, uint32_t *tmp, int32_t 
 // most 64 keys, one key per lane, with a bitonic network of lane exchanges.
 // Lanes beyond the run hold the largest key, so the first n lanes end up with
 // the run's keys in order.  Must be called by all 64 lanes.
-__device__ __forceinline__ void wave_sort64(const uint32_t *src, uint32_t *dst, int32_t n) {
+// B independent runs go through the network together, so the lane exchanges
+// of different runs overlap instead of waiting on each other.
+template <int B>
+__device__ __forceinline__ void wave_bitonic64(uint32_t (&v)[B]) {
   const int lane = (int)__lane_id();
-  uint32_t v = lane < n ? src[lane] : 0xFFFFFFFFu;
 #pragma unroll
   for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t w = (uint32_t)__shfl_xor((int)v, j, 64);
       const bool up = (lane & k) == 0;          // this k-block sorts ascending
       const bool low = (lane & j) == 0;         // lower partner keeps the smaller key
-      v = (low == up) ? min(v, w) : max(v, w);
+      uint32_t w[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) w[b] = (uint32_t)__shfl_xor((int)v[b], j, 64);
+#pragma unroll
+      for (int b = 0; b < B; ++b) v[b] = (low == up) ? min(v[b], w[b]) : max(v[b], w[b]);
     }
   }
-  if (lane < n) dst[lane] = v;
 }
 
 // Merge path: how many of the first q outputs of merging A (na keys) and B

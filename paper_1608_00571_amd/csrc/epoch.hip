@@ -371,16 +371,36 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
   // another, all 64 lanes on each run (the leaf body is "sort these <= 64
   // keys"; the keys it leaves behind are those of an insertion sort)
   if (OPS & opbit(OP_MS)) {
+    // up to 8 runs in flight at once: their loads are issued together
+    constexpr int B = 8;
     uint64_t lm = ballot64(leaf);
+    const int lane = lane_id();
     while (lm) {
-      const int l = __ffsll((unsigned long long)lm) - 1;
-      lm &= lm - 1;
-      const int32_t lo = __shfl(x0, l, 64), hi = __shfl(x1, l, 64), d = __shfl(x2, l, 64);
-      const int sl = __shfl(slot, l, 64);
-      const TreeStatic *T = &C.ts[sl];
-      uint32_t *keys = (uint32_t *)T->ptr0;
-      uint32_t *dst = (d & 1) ? (uint32_t *)T->ptr1 : keys;
-      wave_sort64(keys + lo, dst + lo, hi - lo);
+      uint32_t v[B];
+      int32_t lo[B], n[B];
+      uint32_t *dst[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        n[b] = 0;
+        lo[b] = 0;
+        dst[b] = nullptr;
+        v[b] = 0xFFFFFFFFu;
+        if (lm) {
+          const int l = __ffsll((unsigned long long)lm) - 1;
+          lm &= lm - 1;
+          const int32_t d = __shfl(x2, l, 64);
+          lo[b] = __shfl(x0, l, 64);
+          n[b] = __shfl(x1, l, 64) - lo[b];
+          const TreeStatic *T = &C.ts[__shfl(slot, l, 64)];
+          const uint32_t *keys = (const uint32_t *)T->ptr0;
+          dst[b] = (d & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
+          if (lane < n[b]) v[b] = keys[lo[b] + lane];
+        }
+      }
+      wave_bitonic64<B>(v);
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (lane < n[b]) dst[b][lo[b] + lane] = v[b];
     }
   }
 
@@ -547,7 +567,6 @@ constexpr int kMaxPortions = 64;   // merge jobs exceed 64 keys, so a tile meets
 
 struct MapLds {
   uint32_t in[kMapTile];
-  uint32_t out[kMapTile];
   int32_t pbase[kMaxPortions + 1];   // tile-relative first output of each portion
   int32_t pna[kMaxPortions];         // keys the portion takes from the job's first half
   int64_t pas[kMaxPortions], pbs[kMaxPortions];   // first key taken from each half
@@ -686,17 +705,13 @@ __device__ void map_merge(const DevCtx &C, MapLds &M, uint32_t J, uint64_t U) {
         while (lo < hi) { const int mid = (lo + hi) >> 1; if (A[mid] <= B[o - mid - 1]) lo = mid + 1; else hi = mid; }
         int ia = lo, ib = o - lo;
         const int cnt = min(e1 - e, len - o);
+        uint32_t *out = M.pdst[k] + M.plo[k] + M.pqs[k] + o;
         for (int t = 0; t < cnt; ++t) {
           const bool takeA = ib >= nb || (ia < na && A[ia] <= B[ib]);
-          M.out[e + t] = takeA ? A[ia++] : B[ib++];
+          out[t] = takeA ? A[ia++] : B[ib++];
         }
         e += cnt;
       }
-    }
-    __syncthreads();
-    for (int e = tid; e < tl; e += WG) {
-      const int k = portion_of(M, e);
-      M.pdst[k][M.plo[k] + M.pqs[k] + (e - M.pbase[k])] = M.out[e];
     }
     __syncthreads();
   }
