@@ -294,11 +294,12 @@ def bench_cfg3(args):
                 assert (v, st.tasks, st.epochs, st.peak_entries, st.launched) == e, (k, n, v, st, e)
             if it >= warmup:
                 kms = sum(kt1[x][0] - kt0[x][0] for x in kt1)
-                times.append((dt, kms, rs))
+                et = ctx.epoch_times() if sched != "plain" else None
+                times.append((dt, kms, rs, et))
         ctx.close()
         dt = min(t[0] for t in times)
         kms = min(t[1] for t in times)
-        return dict(dt=dt, kernel_ms=kms, rs=times[0][2])
+        return dict(dt=dt, kernel_ms=kms, rs=times[0][2], et=times[0][3])
 
     out = {}
     for sched in ("persistent", "graph"):
@@ -307,6 +308,12 @@ def bench_cfg3(args):
                       "kernel_ms": round(r["kernel_ms"], 3), "global_epochs": r["rs"].global_epochs,
                       "grid": r["rs"].grid,
                       "tv_GBps_kernel": round(tv_bytes / (r["kernel_ms"] * 1e-3) / 1e9, 1)}
+        et = r["et"]
+        if et is not None and len(et):
+            import numpy as np
+            out[sched]["epoch_us"] = {"min": round(float(np.min(et)), 2), "median": round(float(np.median(et)), 2),
+                                      "max": round(float(np.max(et)), 2),
+                                      "narrow_epochs_median": round(float(np.median(np.sort(et)[:10])), 2)}
     best = max(out, key=lambda k: out[k]["tasks_per_s"])
     # plain: the same trees one after another, one launch per epoch
     sub = args.plain_subset
@@ -332,6 +339,193 @@ def bench_cfg3(args):
     return line
 
 
+def bench_cfg1(args):
+    """fib(20) with 32-bit sums under the plain scheduler: 32,836 tasks in 39
+    epochs, so the per-epoch launch + readback overhead dominates."""
+    import torch
+
+    import paper_1608_00571_amd as T
+
+    ctx = T.Context(T.tv_bound(T.FIB_I32, [20]) * T.BYTES_PER_ENTRY + 4096, sched="plain", wg=args.wg,
+                    profile=True, max_trees=4)
+    p = ctx.register(T.FIB_I32)
+    for _ in range(args.warmup):
+        t = ctx.submit(p, [20]); ctx.run(); ctx.results(t)
+    kt0 = ctx.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t = ctx.submit(p, [20]); ctx.run(); v, st = ctx.results(t)
+        assert v == 6765 and st.tasks == 32836 and st.epochs == 39
+    dt = (time.perf_counter() - t0) / args.steps
+    kt1 = ctx.kernel_times()
+    kms = (kt1[T.FIB_I32][0] - kt0[T.FIB_I32][0]) / args.steps
+    ctx.close()
+    return {"metric": "tasks/s", "value": 32836 / dt, "unit": "tasks/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "fib(20) int32, plain scheduler", "sched": "plain", "wg": args.wg},
+            "epochs_per_s": 39 / dt, "us_per_epoch": round(dt * 1e6 / 39, 2),
+            "kernel_us_per_epoch": round(kms * 1e3 / 39, 2)}
+
+
+def bench_cfg4(args):
+    """64 R-MAT graphs (scale uniform in [16, 22], E = 16 V), one BFS tree
+    each, in shared epochs; depths checked against the oracle's queue BFS."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import oracle
+    import paper_1608_00571_amd as T
+
+    scales = inputs.bfs_batch_scales(args.graphs)
+    t0 = time.perf_counter()
+    gs, dev = [], []
+    for g, sc in enumerate(scales):
+        G = inputs.bfs_batch_graph(g, sc)
+        rp = torch.from_numpy(G.row_ptr).to("cuda")
+        ci = torch.from_numpy(G.col_idx).to("cuda")
+        d = torch.empty(G.V, dtype=torch.int32, device="cuda")
+        gs.append(G)
+        dev.append((rp, ci, d))
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    want = [oracle.bfs_queue(G.V, G.row_ptr, G.col_idx, G.source) for G in gs]
+    orc_s = time.perf_counter() - t0
+    V = sum(G.V for G in gs)
+    E = sum(G.E for G in gs)
+    # arcs scanned = out-degree summed over reached vertices; algorithmic bytes per VISIT
+    scanned = sum(int(np.diff(G.row_ptr)[w >= 0].sum()) for G, w in zip(gs, want))
+    reached = sum(int((w >= 0).sum()) for w in want)
+    max_depth = max(int(w.max()) for w in want)
+    tv = 12 * reached + 8 * reached            # VISIT entry + the child entry that created it
+    payload = 8 * reached + 8 * scanned + 4 * reached   # row_ptr pair, col + depth probe per arc, claim
+    arena = (V + 4096) * T.BYTES_PER_ENTRY
+    out = {}
+    for sched in args.scheds.split(","):
+        ctx = T.Context(arena, sched=sched, wg=args.wg, profile=True, max_trees=len(gs))
+        p = ctx.register(T.BFS_CSR)
+        best = None
+        for it in range(args.warmup + args.steps):
+            ids = [ctx.submit(p, [G.V, G.source], list(b)) for G, b in zip(gs, dev)]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rs = ctx.run()
+            dt = time.perf_counter() - t1
+            stats = [ctx.results(t)[1] for t in ids]
+            for (G, b, w, st) in zip(gs, dev, want, stats):
+                assert np.array_equal(b[2].cpu().numpy(), w), "BFS depths differ from the queue BFS"
+                assert st.tasks == int((w >= 0).sum()) and st.epochs == int(w.max()) + 1
+            if it >= args.warmup and (best is None or dt < best[0]):
+                best = (dt, rs, ctx.epoch_times() if sched != "plain" else None)
+        ctx.close()
+        dt, rs, et = best
+        out[sched] = {"vertices_per_s": reached / dt, "edges_per_s": scanned / dt, "ms": round(dt * 1e3, 3),
+                      "global_epochs": rs.global_epochs, "GBps_tv_payload": round((tv + payload) / dt / 1e9, 1)}
+        if et is not None and len(et):
+            out[sched]["epoch_us"] = [round(float(x), 1) for x in et]
+    best = max(out, key=lambda k: out[k]["vertices_per_s"])
+    b = out[best]
+    ach = (tv + payload) / (b["ms"] * 1e-3) / 1e9
+    return {"metric": "tasks/s", "value": b["vertices_per_s"], "unit": "tasks/s (vertices visited)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic",
+            "config": {"workload": f"{len(gs)} R-MAT BFS trees, scale 16..22, E=16V", "sched": best,
+                       "V": V, "E": E, "reached": reached, "arcs_scanned": scanned, "max_depth": max_depth},
+            "edges_per_s": b["edges_per_s"], "epochs_per_s": b["global_epochs"] / (b["ms"] * 1e-3),
+            "schedulers": out,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                         "tv_bytes": tv, "payload_bytes": payload},
+            "setup_s": {"generate": round(gen_s, 1), "oracle_bfs": round(orc_s, 1)}}
+
+
+def serving_workload(nreq, rate, seed=0, pool_scales=range(12, 21)):
+    """Requests of the serving mix plus their host payloads (one R-MAT graph
+    per scale, shared by the requests that draw that scale)."""
+    import inputs
+    from paper_1608_00571_amd.serving import make_jobs
+    reqs = inputs.serving_trace(nreq, rate, seed)
+    pool = {sc: inputs.rmat(sc, inputs.item_seed(5, 1000 + sc)) for sc in pool_scales}
+    keys = {}
+
+    def keys_for(r):
+        if r.rid not in keys:
+            keys[r.rid] = inputs.keys_u32(r.size, inputs.sub_seed(r.seed, 7))
+        return keys[r.rid]
+    return reqs, pool, make_jobs(reqs, pool, keys_for)
+
+
+def check_serving(jobs, pool):
+    """Every served result equals the oracle's run of that request alone."""
+    import numpy as np
+    import oracle
+    fibs, bfs = {}, {}
+    tasks = 0
+    for j in jobs:
+        if j.kind == "fib":
+            n = j.args[0]
+            if n not in fibs:
+                fibs[n] = oracle.fib(n)
+            r = fibs[n]
+            assert (j.value, j.stats.tasks, j.stats.epochs, j.stats.peak_entries) == (r.result, r.tasks, r.epochs, r.peak)
+        elif j.kind == "msort":
+            assert np.array_equal(j.out, np.sort(j.host_payload)), f"msort request {j.rid}"
+        else:
+            V = j.args[0]
+            sc = V.bit_length() - 1
+            if sc not in bfs:
+                g = pool[sc]
+                bfs[sc] = oracle.bfs_queue(g.V, g.row_ptr, g.col_idx, g.source)
+            assert np.array_equal(j.out, bfs[sc]), f"bfs request {j.rid}"
+        tasks += j.stats.tasks
+    return tasks
+
+
+def bench_cfg5(args):
+    """Serving: Poisson arrivals of the fib / msort / BFS mix; continuous
+    batching over one context; p50/p99 latency at 50% and 80% of the
+    measured saturation rate."""
+    from paper_1608_00571_amd.serving import Server
+
+    n = args.requests
+    reqs, pool, jobs = serving_workload(n + args.serve_warmup, 1.0)
+    arena = args.serve_arena_gib << 30
+    srv = Server(arena, sched=args.sched if args.sched != "plain" else "graph", burst=args.burst)
+    # warm-up, then the closed batch: saturation throughput
+    srv.serve(jobs[: args.serve_warmup], realtime=False)
+    sat = srv.serve(jobs[args.serve_warmup:], realtime=False)
+    sat_tasks = check_serving(sat.jobs, pool)
+    sat_rate = n / sat.seconds
+    out = {"saturation": {"requests_per_s": round(sat_rate, 1), "tasks_per_s": sat_tasks / sat.seconds,
+                          "seconds": round(sat.seconds, 3), "max_inflight": sat.max_inflight,
+                          "bursts": sat.bursts}}
+    for load in (0.5, 0.8):
+        _, _, jl = serving_workload(n + args.serve_warmup, load * sat_rate)
+        jl = jl[args.serve_warmup:]
+        t0 = jl[0].t_arrive
+        for j in jl:
+            j.t_arrive -= t0
+        r = srv.serve(jl, realtime=True)
+        tasks = check_serving(r.jobs, pool)
+        out[f"load_{int(load * 100)}"] = {
+            "offered_rps": round(load * sat_rate, 1), "requests_per_s": round(n / r.seconds, 1),
+            "tasks_per_s": tasks / r.seconds, "p50_ms": round(r.pct(50) * 1e3, 3),
+            "p99_ms": round(r.pct(99) * 1e3, 3), "max_inflight": r.max_inflight, "bursts": r.bursts}
+    srv.close()
+    l80 = out["load_80"]
+    return {"metric": "tasks/s", "value": l80["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
+            "steps": 1, "warmup": args.serve_warmup, "ms_per_step": round(n / l80["requests_per_s"] * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+u32+int32",
+            "data": "synthetic",
+            "config": {"workload": f"serving {n} requests: 40% fib(12..30), 40% msort 2^10..2^22, 20% R-MAT BFS 12..20",
+                       "sched": args.sched if args.sched != "plain" else "graph", "burst_epochs": args.burst,
+                       "arena_gib": args.serve_arena_gib},
+            "p50_ms": l80["p50_ms"], "p99_ms": l80["p99_ms"], "serving": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,6 +537,12 @@ def main():
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--trees", type=int, default=4096)
+    ap.add_argument("--graphs", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=60)
+    ap.add_argument("--serve-arena-gib", type=int, default=16)
+    ap.add_argument("--burst", type=int, default=4)
+    ap.add_argument("--scheds", default="persistent,graph,plain")
     ap.add_argument("--plain-subset", type=int, default=4096)
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the graph / persistent / naive-merge runs of the same workload")
@@ -351,8 +551,14 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)
         sys.exit(2)
-    if args.config == 3:
+    if args.config == 1:
+        line = bench_cfg1(args)
+    elif args.config == 3:
         line = bench_cfg3(args)
+    elif args.config == 4:
+        line = bench_cfg4(args)
+    elif args.config == 5:
+        line = bench_cfg5(args)
     elif args.config == 2:
         line = bench_cfg2(args)
         if not args.no_cpu:

@@ -191,6 +191,20 @@ typedef struct {
 } trees_ktime;
 trees_status trees_kernel_times(trees_ctx *ctx, trees_ktime *out, int32_t n);
 
+/* Device-clock duration of each epoch of the last GRAPH or PERSISTENT run,
+ * in microseconds, measured from the device's constant-rate clock where the
+ * last work-group of each epoch builds the next work list (it includes the
+ * epoch's barrier and any map phase).  Copies up to cap values (at most 256)
+ * and stores the number of epochs in *n. */
+trees_status trees_epoch_times(trees_ctx *ctx, double *us, int32_t cap, int32_t *n);
+
+/* Debug (TREES_F_DEBUG): summed work-group time, in microseconds, spent in
+ * each phase of the batched epoch sweep since the context was created:
+ * 0 locate, 1 fetch + bodies, 2 fork allocation, 3 child and own writes,
+ * 4 BFS arc expansion, 5 per-tree bookkeeping, 6 between chunks and the
+ * barrier, 7 barrier (including the scan and map phases).  Copies min(n, 8). */
+trees_status trees_debug_phases(trees_ctx *ctx, double *us, int32_t n);
+
 /* Request that a running trees_run stop at the next epoch boundary.  Safe to
  * call from another host thread. */
 trees_status trees_abort(trees_ctx *ctx);

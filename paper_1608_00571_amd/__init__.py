@@ -110,6 +110,10 @@ def lib():
         L.trees_tv_bound.argtypes = [i32, ctypes.POINTER(i64), i32, ctypes.POINTER(i64)]
         L.trees_kernel_times.restype = i32
         L.trees_kernel_times.argtypes = [vp, ctypes.POINTER(_KTime), i32]
+        L.trees_epoch_times.restype = i32
+        L.trees_epoch_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
+        L.trees_debug_phases.restype = i32
+        L.trees_debug_phases.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
         L.trees_free_entries.restype = i64
         L.trees_free_entries.argtypes = [vp]
         L.trees_num_trees.restype = i32
@@ -121,7 +125,7 @@ def lib():
 EXPORTED = ("trees_create", "trees_destroy", "trees_last_error", "trees_register_program",
             "trees_submit", "trees_run", "trees_results", "trees_trace", "trees_abort",
             "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees",
-            "trees_kernel_times")
+            "trees_kernel_times", "trees_epoch_times", "trees_debug_phases")
 
 
 @dataclass
@@ -170,7 +174,8 @@ class Context:
 
     def __init__(self, arena_bytes: int = 1 << 30, *, max_trees: int = 4096, sched="persistent",
                  wg: int = 256, blocks_per_cu: int = 0, graph_chunk: int = 8, trace: bool = False,
-                 profile: bool = False, nomap: bool = False, device: int = 0, timeout_s: float = 0.0):
+                 profile: bool = False, nomap: bool = False, debug: bool = False, device: int = 0,
+                 timeout_s: float = 0.0):
         import torch
         self._torch = torch
         L = lib()
@@ -189,7 +194,8 @@ class Context:
         cfg.wg_size = wg
         cfg.blocks_per_cu = blocks_per_cu
         cfg.graph_chunk = graph_chunk
-        cfg.flags = (F_TRACE if trace else 0) | (F_PROFILE if profile else 0) | (F_NOMAP if nomap else 0)
+        cfg.flags = ((F_TRACE if trace else 0) | (F_PROFILE if profile else 0) | (F_NOMAP if nomap else 0)
+                     | (F_DEBUG if debug else 0))
         cfg.timeout_s = timeout_s
         h = ctypes.c_void_p(0)
         rc = L.trees_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -296,6 +302,19 @@ class Context:
         arr = (_KTime * 7)()
         self._check(lib().trees_kernel_times(self.h, arr, 7), "kernel_times")
         return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(7)}
+
+    def epoch_times(self) -> np.ndarray:
+        """Per-epoch device-clock durations (us) of the last batched run."""
+        out = (ctypes.c_double * 256)()
+        n = ctypes.c_int32(0)
+        self._check(lib().trees_epoch_times(self.h, out, 256, ctypes.byref(n)), "epoch_times")
+        return np.array(out[: min(n.value, 256)])
+
+    def debug_phases(self) -> np.ndarray:
+        """Summed work-group time (us) per sweep phase (TREES_F_DEBUG)."""
+        out = (ctypes.c_double * 8)()
+        self._check(lib().trees_debug_phases(self.h, out, 8), "debug_phases")
+        return np.array(out[:8])
 
     def abort(self):
         self._check(lib().trees_abort(self.h), "abort")

@@ -37,6 +37,13 @@ namespace trees {
 
 enum : int { ACT_NONE = 0, ACT_EMIT = 1, ACT_JOIN = 2, ACT_FINISH = 3 };
 
+// A chunk is the unit of work of one work-group: kChunk consecutive work
+// items, IT = kChunk / WG per lane (item x of the chunk is handled by lane
+// x % WG as its item x / WG, so each of a lane's items is a coalesced
+// work-group-wide access).  All per-tree state a chunk needs is cached in LDS
+// per segment (a run of the chunk's items that belong to one tree).
+constexpr int kChunk = 1024;
+
 template <int WG>
 struct Lds {
   int32_t kfirst;          // first work-list entry of the chunk
@@ -46,29 +53,53 @@ struct Lds {
   uint32_t gen;
   int32_t sink;            // destination of atomics whose completion must be awaited
   int32_t tflag;
-  uint32_t win[WG];        // wl_off[kfirst + 1 + t]
-  int32_t seg_slot[WG];    // tree slot of segment s
-  int32_t seg_cnt[WG];     // children requested per segment (LDS atomics)
-  int32_t seg_base[WG];    // arena-relative first child per segment (-1: overflow)
-  int32_t seg_join[WG];
-  int32_t seg_valid[WG];
-  int32_t scan_tmp[WG / 64 + 1];
-  int64_t scan_tmp64[WG / 64 + 1];
   uint32_t jbase;          // first map job reserved by this work-group
   uint64_t ubase;          // first map unit reserved by this work-group
-  uint64_t mwin[WG];       // map job offsets after the tile's first job
-  int32_t v_row[WG];       // VISIT: first arc of the lane's vertex
-  int32_t v_pre[WG];       // VISIT: exclusive prefix of out-degrees
-  int32_t v_seg[WG];
-  int32_t v_cen[WG];
+  int64_t tprof;           // debug: clock at the last phase boundary
+  int64_t prof[8];         // debug: time per phase
+  uint32_t win[kChunk];    // wl_off[kfirst + 1 + t]
+  int32_t seg_slot[kChunk];   // tree slot of segment s
+  int32_t seg_cen[kChunk];    // its epoch number
+  int64_t seg_start[kChunk];  // absolute task-vector index of its range start
+  int32_t seg_cnt[kChunk];    // children requested per segment (LDS atomics)
+  int32_t seg_base[kChunk];   // arena-relative first child per segment (-1: overflow)
+  int32_t seg_join[kChunk];
+  int32_t seg_valid[kChunk];
+  int32_t scan_tmp[WG / 64 + 1];
+  int64_t scan_tmp64[WG / 64 + 1];
 };
+
+// VISIT expansion state (only in kernels that run BFS).
+constexpr int kClaimQ = 2048;
+constexpr int kArcsPerLane = 4;   // arcs a lane probes per step of the expansion
+struct VisitLds {
+  int32_t row[kChunk];     // first arc of the item's vertex
+  int32_t pre[kChunk];     // exclusive prefix of out-degrees, in (lane, item) order
+  int32_t seg[kChunk];
+  int32_t qu[kClaimQ];     // claimed vertices waiting for their child entries
+  int16_t qs[kClaimQ];     // their segment (< kChunk)
+  int32_t qo[kClaimQ];     // their offset inside the segment's block
+  int32_t qn;
+};
+struct NoVisitLds {};
+
+// Debug phase clock: thread 0 charges the time since the last boundary to
+// phase ph (only with TREES_F_DEBUG; the branch is uniform).
+template <int WG>
+__device__ __forceinline__ void phase_mark(const DevCtx &C, Lds<WG> &L, int ph) {
+  if (C.debug && threadIdx.x == 0) {
+    const int64_t t = realtime();
+    L.prof[ph] += t - L.tprof;
+    L.tprof = t;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Segment helpers
 // ---------------------------------------------------------------------------
 
 // arr[seg] += v for every lane, one LDS atomic per wavefront when the whole
-// wavefront belongs to one segment.  v < 2^16.
+// wavefront belongs to one segment.  0 <= v < 2^16.
 __device__ __forceinline__ void seg_add(int32_t *arr, int seg, int v) {
   uint64_t m = ballot64(v > 0);
   if (!m) return;
@@ -84,38 +115,48 @@ __device__ __forceinline__ void seg_add(int32_t *arr, int seg, int v) {
   }
 }
 
-// Co-operative fork allocation (Tenet 2).  Every thread of the work-group
-// calls it; lane asks for nk (< 16) children of the tree of segment `seg`.
-// Returns the arena-relative index of the lane's first child, or -1 if the
-// tree's arena overflowed.
-template <int WG, bool MULTI>
-__device__ __forceinline__ int32_t wg_alloc(const DevCtx &C, Lds<WG> &L, int seg, int nk,
-                                            const PlainArgs &P, bool with_joins = false) {
+// First half of the co-operative fork allocation (Tenet 2): the lane asks
+// for nk (< 16) children of the tree of segment `seg` and gets its offset
+// inside the work-group's block for that tree.  A wavefront whose requests
+// all go to one tree takes its exclusive prefix from one ballot per bit and
+// adds its total with a single LDS atomic.  All 64 lanes must call it.
+__device__ __forceinline__ int lds_reserve(int32_t *seg_cnt, int seg, int nk) {
   int off = 0;
-  uint64_t m = ballot64(nk > 0);
+  const uint64_t m = ballot64(nk > 0);
   if (m) {
-    int leader = __ffsll((unsigned long long)m) - 1;
-    int s0 = __shfl(seg, leader, 64);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int s0 = __shfl(seg, leader, 64);
     if (__all(nk == 0 || seg == s0)) {
       int tot;
-      int pre = wave_prefix_small<4>(nk, &tot);
+      const int pre = wave_prefix_small<4>(nk, &tot);
       int wb = 0;
-      if (lane_id() == leader) wb = atomicAdd(&L.seg_cnt[s0], tot);
+      if (lane_id() == leader) wb = atomicAdd(&seg_cnt[s0], tot);
       wb = __shfl(wb, leader, 64);
       off = wb + pre;
     } else if (nk > 0) {
-      off = atomicAdd(&L.seg_cnt[seg], nk);
+      off = atomicAdd(&seg_cnt[seg], nk);
     }
   }
+  return off;
+}
+
+// Second half: one device-scope atomic add on the tree's nextFreeCore per
+// segment of the chunk (the plain form adds forks and joins of its single
+// tree with one 64-bit atomic).  Every thread of the work-group calls it;
+// afterwards L.seg_base[s] holds the arena-relative first child of segment s
+// or -1 if the tree's arena overflowed.
+template <int WG, bool MULTI>
+__device__ __forceinline__ void seg_commit(const DevCtx &C, Lds<WG> &L, const PlainArgs &P,
+                                           bool with_joins) {
   __syncthreads();
   const int nseg = L.nseg;
   for (int s = threadIdx.x; s < nseg; s += WG) {
-    int c = L.seg_cnt[s];
+    const int c = L.seg_cnt[s];
     int b = 0;
     if (MULTI) {
       if (c > 0) {
         L.seg_cnt[s] = 0;
-        int slot = L.seg_slot[s];
+        const int slot = L.seg_slot[s];
         b = add_agent(&C.hot[slot].nfc, (int32_t)c);
         if ((int64_t)b + c > (int64_t)C.ts[slot].cap) {
           L.sink = or_agent(&C.hot[slot].flags, (int32_t)TF_OVERFLOW);
@@ -123,7 +164,6 @@ __device__ __forceinline__ int32_t wg_alloc(const DevCtx &C, Lds<WG> &L, int seg
         }
       }
     } else {
-      // plain form: the work-group's forks and joins in one atomic add
       const int j = with_joins ? L.seg_join[s] : 0;
       if (with_joins) L.seg_join[s] = 0;
       if (c > 0 || j > 0) {
@@ -141,8 +181,11 @@ __device__ __forceinline__ int32_t wg_alloc(const DevCtx &C, Lds<WG> &L, int seg
     L.seg_base[s] = b;
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ int32_t child_base(const int32_t *seg_base, int seg, int nk, int off) {
   if (nk == 0) return 0;
-  int b = L.seg_base[seg];
+  const int b = seg_base[seg];
   return b < 0 ? -1 : b + off;
 }
 
@@ -208,199 +251,215 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
 }
 
 // ---------------------------------------------------------------------------
-// One chunk of WG work items.
+// One chunk of kChunk work items.
 // ---------------------------------------------------------------------------
-template <int WG, uint32_t OPS, bool MULTI>
-__device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, int32_t nL,
-                          const PlainArgs &P) {
+template <int WG, uint32_t OPS, bool MULTI, typename VL>
+__device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint32_t S, int32_t nL,
+                          const PlainArgs &P, bool follows = false) {
+  constexpr int IT = kChunk / WG;
   const int tid = threadIdx.x;
-  const uint32_t w = w0 + tid;
-  const bool has = w < S;
-  int seg = -1;
-  int slot = 0;
-  int32_t cen = 0;
-  int64_t i = 0;
+  const int lane = lane_id();
 
-  // ---- locate the lane's tree and task-vector entry --------------------
-  if (MULTI) {
-    if (nL == 1) {
-      if (tid == 0) {
-        L.kfirst = 0; L.nseg = 1; L.off0 = 0; L.win[0] = S; L.seg_slot[0] = C.wl_tree[0];
-      }
-    } else {
-      if (tid < 64) {
-        // 64-ary search for the last entry whose offset is <= w0.
-        int lo = 0, hi = nL;
-        while (hi - lo > 1) {
-          int step = (hi - lo + 63) >> 6;
-          int p = lo + tid * step;
-          bool ok = p < hi && C.wl_off[p] <= w0;
-          int j = __popcll(ballot64(ok)) - 1;
-          lo = lo + j * step;
-          hi = min(lo + step, hi);
-        }
-        if (tid == 0) { L.kfirst = lo; L.off0 = C.wl_off[lo]; }
-      }
-      __syncthreads();
-      const int kf = L.kfirst;
-      const int kk = kf + 1 + tid;
-      L.win[tid] = (kk <= nL) ? C.wl_off[kk] : 0xFFFFFFFFu;
-      __syncthreads();
-      if (tid == 0) {
-        // number of entries the chunk touches
-        uint32_t wl = min(w0 + (uint32_t)WG, S) - 1;
-        int lo2 = 0, hi2 = WG;
-        while (lo2 < hi2) { int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= wl) lo2 = mid + 1; else hi2 = mid; }
-        L.nseg = lo2 + 1;
-      }
-      __syncthreads();
-      if (tid < L.nseg) L.seg_slot[tid] = C.wl_tree[kf + tid];
+  // ---- locate the chunk's trees ---------------------------------------------
+  // follows: this chunk starts where the previous chunk of this work-group
+  // ended, so its first entry is found in the previous window (every entry
+  // holds at least one item, so it lies within the next kChunk entries).
+  if (MULTI && nL > 1 && follows) {
+    if (tid == 0) {
+      int lo2 = 0, hi2 = kChunk;
+      while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= w0) lo2 = mid + 1; else hi2 = mid; }
+      L.flag = lo2;
     }
     __syncthreads();
-    if (has) {
+    const int adv = L.flag;
+    const uint32_t noff0 = adv ? L.win[adv - 1] : L.off0;
+    __syncthreads();
+    if (tid == 0) { L.kfirst += adv; L.off0 = noff0; }
+  }
+  if (MULTI && nL > 1) {
+    if (!follows && tid < 64) {
+      // 64-ary search for the last entry whose offset is <= w0
+      int lo = 0, hi = nL;
+      while (hi - lo > 1) {
+        const int step = (hi - lo + 63) >> 6;
+        const int p = lo + tid * step;
+        const bool ok = p < hi && C.wl_off[p] <= w0;
+        const int j = __popcll(ballot64(ok)) - 1;
+        lo = lo + j * step;
+        hi = min(lo + step, hi);
+      }
+      if (tid == 0) { L.kfirst = lo; L.off0 = C.wl_off[lo]; }
+    }
+    __syncthreads();
+    const int kf = L.kfirst;
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int t = k * WG + tid;
+      L.win[t] = (kf + 1 + t <= nL) ? C.wl_off[kf + 1 + t] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t wl = min(w0 + (uint32_t)kChunk, S) - 1;
+      int lo2 = 0, hi2 = kChunk;
+      while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= wl) lo2 = mid + 1; else hi2 = mid; }
+      L.nseg = lo2 + 1;
+    }
+    __syncthreads();
+    for (int t = tid; t < L.nseg; t += WG) {
+      L.seg_slot[t] = C.wl_tree[kf + t];
+      L.seg_cen[t] = C.wl_cen[kf + t];
+      L.seg_start[t] = C.wl_start[kf + t];
+    }
+  } else if (tid == 0) {
+    L.kfirst = 0; L.nseg = 1; L.off0 = 0; L.win[0] = S;
+    if (MULTI) { L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_start[0] = C.wl_start[0]; }
+    else { L.seg_slot[0] = P.slot; L.seg_cen[0] = P.cen; L.seg_start[0] = C.ts[P.slot].base + P.b; }
+  }
+  __syncthreads();
+
+  phase_mark(C, L, 0);
+  // ---- fetch and decode (all loads of all items issued together) ----------
+  const int32_t ntt = C.ntt;
+  int seg[IT], slot[IT], op[IT];
+  int32_t cen[IT];
+  int64_t idx[IT];
+  int32_t code[IT], a0v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const uint32_t w = w0 + (uint32_t)(k * WG + tid);
+    seg[k] = -1; slot[k] = 0; cen[k] = 0; idx[k] = 0; code[k] = 0; a0v[k] = 0; op[k] = OP_NONE;
+    if (w < S) {
       int s = 0;
-      if (nL > 1) {
-        int lo2 = 0, hi2 = WG;
-        while (lo2 < hi2) { int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= w) lo2 = mid + 1; else hi2 = mid; }
+      if (MULTI && nL > 1) {   // segments past the item's offset in the chunk cannot hold it
+        int lo2 = 0, hi2 = min(L.nseg - 1, (int)(w - w0));
+        while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= w) lo2 = mid + 1; else hi2 = mid; }
         s = lo2;
       }
-      seg = s;
-      const int k = L.kfirst + s;
-      slot = L.seg_slot[s];
-      cen = C.wl_cen[k];
-      const uint32_t offk = (s == 0) ? L.off0 : L.win[s - 1];
-      i = C.wl_start[k] + (int64_t)(w - offk);
+      seg[k] = s;
+      slot[k] = L.seg_slot[s];
+      cen[k] = L.seg_cen[s];
+      idx[k] = L.seg_start[s] + (int64_t)(w - (s == 0 ? L.off0 : L.win[s - 1]));
+      code[k] = C.code[idx[k]];
+      a0v[k] = C.a0[idx[k]];
     }
-  } else {
-    if (tid == 0) { L.kfirst = 0; L.nseg = 1; L.seg_slot[0] = P.slot; }
-    __syncthreads();
-    slot = P.slot;
-    cen = P.cen;
-    if (has) { seg = 0; i = C.ts[slot].base + P.b + (int64_t)w; }
   }
-
-  // ---- fetch and decode --------------------------------------------------
-  const int32_t ntt = C.ntt;
-  int op = OP_NONE;
-  int32_t gtype = 0;
-  if (has) {
-    const int32_t code = C.code[i];
-    if (code != 0) {
-      gtype = code - cen * ntt;
-      if (gtype >= 1 && gtype <= ntt) op = C.op_of_type[gtype];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    if (code[k] != 0) {
+      const int32_t gtype = code[k] - cen[k] * ntt;
+      if (gtype >= 1 && gtype <= ntt) op[k] = C.op_of_type[gtype];
       // an entry outside the epoch's encoding window, or of a type this
       // kernel was not built for, is an error of its tree
-      if (op == OP_NONE || (opbit(op) & OPS) == 0) {
-        op = OP_NONE;
-        const int32_t prev = or_agent(MULTI ? &C.hot[slot].flags : &C.plain->flags[P.par],
+      if (op[k] == OP_NONE || (opbit(op[k]) & OPS) == 0) {
+        op[k] = OP_NONE;
+        const int32_t prev = or_agent(MULTI ? &C.hot[slot[k]].flags : &C.plain->flags[P.par],
                                       (int32_t)TF_ENCODING);
         if (prev < 0) L.sink = prev;
       }
     }
   }
 
-  // ---- task body: decide children, join or emit ---------------------------
-  int nk = 0, act = ACT_NONE;
-  int64_t val = 0;
-  int32_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
-  bool want_map = false;
-  bool leaf = false;
-  int64_t tb = 0;     // arena base of the lane's tree
-  int32_t tbase = 0;  // global type id of the program's first type
-  if (op != OP_NONE) {
-    const TreeStatic *T = &C.ts[slot];
-    tb = T->base;
-    tbase = T->tbase;
-    switch (op) {
+  // ---- task bodies: decide children, join or emit ---------------------------
+  int nk[IT], act[IT];
+  int64_t val[IT];
+  int32_t x0[IT], x1[IT], x2[IT], x3[IT];
+  bool want_map[IT], leaf[IT];
+  int64_t tb[IT];      // arena base of the item's tree
+  int32_t tbase[IT];   // global type id of its program's first type
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    nk[k] = 0; act[k] = ACT_NONE; val[k] = 0;
+    x0[k] = x1[k] = x2[k] = x3[k] = 0;
+    want_map[k] = false; leaf[k] = false; tb[k] = 0; tbase[k] = 0;
+    if (op[k] == OP_NONE) continue;
+    const TreeStatic *T = &C.ts[slot[k]];
+    tb[k] = T->base;
+    tbase[k] = T->tbase;
+    const int64_t i = idx[k];
+    switch (op[k]) {
       case OP_FIB32:
       case OP_FIB64: {
-        const int32_t n = C.a0[i];
-        if (n < 2) { act = ACT_EMIT; val = n; }
-        else { act = ACT_JOIN; nk = 2; x0 = n; }
+        const int32_t n = a0v[k];
+        if (n < 2) { act[k] = ACT_EMIT; val[k] = n; }
+        else { act[k] = ACT_JOIN; nk[k] = 2; x0[k] = n; }
       } break;
       case OP_SUM32: {
-        const int32_t c = C.a0[i];
-        const uint32_t s = (uint32_t)C.r[tb + c] + (uint32_t)C.r[tb + c + 1];
-        act = ACT_EMIT; val = (int64_t)(int32_t)s;
+        const int32_t c = a0v[k];
+        const uint32_t sm = (uint32_t)C.r[tb[k] + c] + (uint32_t)C.r[tb[k] + c + 1];
+        act[k] = ACT_EMIT; val[k] = (int64_t)(int32_t)sm;
       } break;
       case OP_SUM64: {
-        const int32_t c = C.a0[i];
-        act = ACT_EMIT; val = C.r[tb + c] + C.r[tb + c + 1];
+        const int32_t c = a0v[k];
+        act[k] = ACT_EMIT; val[k] = C.r[tb[k] + c] + C.r[tb[k] + c + 1];
       } break;
       case OP_Q: {
         const int32_t n = T->p0;
-        const int32_t row = C.a0[i];
-        if (row == n) { act = ACT_EMIT; val = 1; break; }
+        const int32_t row = a0v[k];
+        if (row == n) { act[k] = ACT_EMIT; val[k] = 1; break; }
         const uint32_t full = (1u << n) - 1u;
         const uint32_t cols = (uint32_t)C.a1[i], ld = (uint32_t)C.a2[i], rd = (uint32_t)C.a3[i];
         const uint32_t avail = ~(cols | ld | rd) & full;
-        if (!avail) { act = ACT_EMIT; val = 0; break; }
-        act = ACT_JOIN; nk = __popc(avail);
-        x0 = row; x1 = (int32_t)cols; x2 = (int32_t)ld; x3 = (int32_t)rd;
+        if (!avail) { act[k] = ACT_EMIT; val[k] = 0; break; }
+        act[k] = ACT_JOIN; nk[k] = __popc(avail);
+        x0[k] = row; x1[k] = (int32_t)cols; x2[k] = (int32_t)ld; x3[k] = (int32_t)rd;
       } break;
       case OP_QSUM: {
-        const int32_t c = C.a0[i], k = C.a1[i];
-        int64_t s = 0;
-        for (int32_t j = 0; j < k; ++j) s += C.r[tb + c + j];
-        act = ACT_EMIT; val = s;
+        const int32_t c = a0v[k], kk = C.a1[i];
+        int64_t sm = 0;
+        for (int32_t j = 0; j < kk; ++j) sm += C.r[tb[k] + c + j];
+        act[k] = ACT_EMIT; val[k] = sm;
       } break;
       case OP_MS: {
-        const int32_t lo = C.a0[i], hi = C.a1[i], d = C.a2[i];
-        if (hi - lo <= kLeaf) {
-          act = ACT_FINISH;   // sorted co-operatively below
-          leaf = true;
-          x0 = lo; x1 = hi; x2 = d;
-        } else {
-          act = ACT_JOIN; nk = 2; x0 = lo; x1 = hi; x2 = d;
-        }
+        const int32_t lo = a0v[k], hi = C.a1[i], d = C.a2[i];
+        x0[k] = lo; x1[k] = hi; x2[k] = d;
+        if (hi - lo <= kLeaf) { act[k] = ACT_FINISH; leaf[k] = true; }   // sorted co-operatively below
+        else { act[k] = ACT_JOIN; nk[k] = 2; }
       } break;
       case OP_MERGE: {
-        act = ACT_FINISH;
-        x0 = C.a0[i]; x1 = C.a1[i]; x2 = C.a2[i];
-        if (C.mj_cap > 0) want_map = true;   // the merge runs in the map phase
-        else ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0, x1, x2);
+        act[k] = ACT_FINISH;
+        x0[k] = a0v[k]; x1[k] = C.a1[i]; x2[k] = C.a2[i];
+        if (C.mj_cap > 0) want_map[k] = true;   // the merge runs in the map phase
+        else ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0[k], x1[k], x2[k]);
       } break;
       case OP_VISIT:
-        act = ACT_FINISH;   // its arcs are expanded co-operatively below
+        act[k] = ACT_FINISH;   // its arcs are expanded co-operatively below
         break;
       default: break;
     }
   }
 
-  // ---- merge-sort leaves: each wavefront sorts its lanes' runs one after
-  // another, all 64 lanes on each run (the leaf body is "sort these <= 64
-  // keys"; the keys it leaves behind are those of an insertion sort)
+  // ---- merge-sort leaves: each wavefront sorts its lanes' runs, 8 at a time,
+  // all 64 lanes on each run (the leaf body is "sort these <= 64 keys"; the
+  // keys it leaves behind are those of an insertion sort)
   if (OPS & opbit(OP_MS)) {
-    // up to 8 runs in flight at once: their loads are issued together
     constexpr int B = 8;
-    uint64_t lm = ballot64(leaf);
-    const int lane = lane_id();
-    while (lm) {
-      uint32_t v[B];
-      int32_t lo[B], n[B];
-      uint32_t *dst[B];
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
-        n[b] = 0;
-        lo[b] = 0;
-        dst[b] = nullptr;
-        v[b] = 0xFFFFFFFFu;
-        if (lm) {
-          const int l = __ffsll((unsigned long long)lm) - 1;
-          lm &= lm - 1;
-          const int32_t d = __shfl(x2, l, 64);
-          lo[b] = __shfl(x0, l, 64);
-          n[b] = __shfl(x1, l, 64) - lo[b];
-          const TreeStatic *T = &C.ts[__shfl(slot, l, 64)];
-          const uint32_t *keys = (const uint32_t *)T->ptr0;
-          dst[b] = (d & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
-          if (lane < n[b]) v[b] = keys[lo[b] + lane];
+    for (int k = 0; k < IT; ++k) {
+      uint64_t lm = ballot64(leaf[k]);
+      while (lm) {
+        uint32_t v[B];
+        int32_t lo[B], n[B];
+        uint32_t *dst[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          n[b] = 0; lo[b] = 0; dst[b] = nullptr; v[b] = 0xFFFFFFFFu;
+          if (lm) {
+            const int l = __ffsll((unsigned long long)lm) - 1;
+            lm &= lm - 1;
+            const int32_t d = __shfl(x2[k], l, 64);
+            lo[b] = __shfl(x0[k], l, 64);
+            n[b] = __shfl(x1[k], l, 64) - lo[b];
+            const TreeStatic *T = &C.ts[__shfl(slot[k], l, 64)];
+            const uint32_t *keys = (const uint32_t *)T->ptr0;
+            dst[b] = (d & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
+            if (lane < n[b]) v[b] = keys[lo[b] + lane];
+          }
         }
-      }
-      wave_bitonic64<B>(v);
+        wave_bitonic64<B>(v);
 #pragma unroll
-      for (int b = 0; b < B; ++b)
-        if (lane < n[b]) dst[b][lo[b] + lane] = v[b];
+        for (int b = 0; b < B; ++b)
+          if (lane < n[b]) dst[b][lo[b] + lane] = v[b];
+      }
     }
   }
 
@@ -408,126 +467,196 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
   // data-parallel map phase that runs before the next epoch.  One atomic per
   // work-group reserves job slots and output units together.
   if (OPS & opbit(OP_MERGE)) {
-    if (__syncthreads_or(want_map)) {
+    int jl = 0;
+    int64_t ul = 0;
+#pragma unroll
+    for (int k = 0; k < IT; ++k)
+      if (want_map[k]) { ++jl; ul += (int64_t)(x1[k] - x0[k]); }
+    if (__syncthreads_or(jl > 0)) {
       int jtot;
-      const int jpre = wg_excl_scan<WG>(want_map ? 1 : 0, L.scan_tmp, &jtot);
+      int jpre = wg_excl_scan<WG>(jl, L.scan_tmp, &jtot);
       int64_t utot;
-      const int64_t upre = wg_excl_scan64<WG>(want_map ? (int64_t)(x1 - x0) : 0, L.scan_tmp64, &utot);
-      if (threadIdx.x == 0) {
+      int64_t upre = wg_excl_scan64<WG>(ul, L.scan_tmp64, &utot);
+      if (tid == 0) {
         uint64_t *ctr = MULTI ? &C.hdr->map_ctr : &C.plain->map[P.par];
         const uint64_t prev = add_agent(ctr, ((uint64_t)jtot << kMapShift) | (uint64_t)utot);
         L.jbase = (uint32_t)(prev >> kMapShift);
         L.ubase = prev & kMapUnitMask;
       }
       __syncthreads();
-      if (want_map) {
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        if (!want_map[k]) continue;
         const uint32_t j = L.jbase + (uint32_t)jpre;
+        const TreeStatic *T = &C.ts[slot[k]];
         if (j < (uint32_t)C.mj_cap) {
-          const TreeStatic *T = &C.ts[slot];
-          C.mj_lo[j] = x0; C.mj_hi[j] = x1;
-          C.mj_src[j] = ((x2 + 1) & 1) ? (const uint32_t *)T->ptr1 : (const uint32_t *)T->ptr0;
-          C.mj_dst[j] = (x2 & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
+          C.mj_lo[j] = x0[k]; C.mj_hi[j] = x1[k];
+          C.mj_src[j] = ((x2[k] + 1) & 1) ? (const uint32_t *)T->ptr1 : (const uint32_t *)T->ptr0;
+          C.mj_dst[j] = (x2[k] & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
           C.mj_off[j] = L.ubase + (uint64_t)upre;
         } else {   // job list full: this lane merges by itself
-          const TreeStatic *T = &C.ts[slot];
-          ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0, x1, x2);
+          ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0[k], x1[k], x2[k]);
         }
+        ++jpre;
+        upre += (int64_t)(x1[k] - x0[k]);
       }
     }
   }
 
   // ---- fork: co-operative slot allocation, structure-of-arrays writes ------
-  seg_add(L.seg_join, seg, act == ACT_JOIN ? 1 : 0);   // joins counted per tree segment
-  const int32_t cb = wg_alloc<WG, MULTI>(C, L, seg, nk, P, true);
-  if (nk > 0 && cb >= 0) {
-    const int64_t c = tb + cb;
-    const int32_t nxt = (cen + 1) * ntt + tbase;   // code of local type 1, next epoch
-    if (op == OP_FIB32 || op == OP_FIB64) {
-      C.code[c] = nxt; C.a0[c] = x0 - 1;
-      C.code[c + 1] = nxt; C.a0[c + 1] = x0 - 2;
-    } else if (op == OP_Q) {
-      const int32_t n = C.ts[slot].p0;
-      const uint32_t full = (1u << n) - 1u;
-      const uint32_t cols = (uint32_t)x1, ld = (uint32_t)x2, rd = (uint32_t)x3;
-      uint32_t avail = ~(cols | ld | rd) & full;
-      int64_t cc = c;
-      while (avail) {
-        const uint32_t bit = avail & (0u - avail);
-        avail ^= bit;
-        C.code[cc] = nxt;
-        C.a0[cc] = x0 + 1;
-        C.a1[cc] = (int32_t)(cols | bit);
-        C.a2[cc] = (int32_t)(((ld | bit) << 1) & full);
-        C.a3[cc] = (int32_t)((rd | bit) >> 1);
-        ++cc;
+  __syncthreads();
+  phase_mark(C, L, 1);
+  int off[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    seg_add(L.seg_join, seg[k], act[k] == ACT_JOIN ? 1 : 0);   // joins per tree segment
+    if (C.trace_on) seg_add(L.seg_valid, seg[k], op[k] != OP_NONE ? 1 : 0);
+    off[k] = lds_reserve(L.seg_cnt, seg[k], nk[k]);
+  }
+  seg_commit<WG, MULTI>(C, L, P, true);
+  phase_mark(C, L, 2);
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int32_t cb = child_base(L.seg_base, seg[k], nk[k], off[k]);
+    if (nk[k] > 0 && cb >= 0) {
+      const int64_t c = tb[k] + cb;
+      const int32_t nxt = (cen[k] + 1) * ntt + tbase[k];   // code of local type 1, next epoch
+      if (op[k] == OP_FIB32 || op[k] == OP_FIB64) {
+        C.code[c] = nxt; C.a0[c] = x0[k] - 1;
+        C.code[c + 1] = nxt; C.a0[c + 1] = x0[k] - 2;
+      } else if (op[k] == OP_Q) {
+        const int32_t n = C.ts[slot[k]].p0;
+        const uint32_t full = (1u << n) - 1u;
+        const uint32_t cols = (uint32_t)x1[k], ld = (uint32_t)x2[k], rd = (uint32_t)x3[k];
+        uint32_t avail = ~(cols | ld | rd) & full;
+        int64_t cc = c;
+        while (avail) {
+          const uint32_t bit = avail & (0u - avail);
+          avail ^= bit;
+          C.code[cc] = nxt;
+          C.a0[cc] = x0[k] + 1;
+          C.a1[cc] = (int32_t)(cols | bit);
+          C.a2[cc] = (int32_t)(((ld | bit) << 1) & full);
+          C.a3[cc] = (int32_t)((rd | bit) >> 1);
+          ++cc;
+        }
+      } else if (op[k] == OP_MS) {
+        const int32_t mid = x0[k] + (x1[k] - x0[k]) / 2;
+        C.code[c] = nxt; C.a0[c] = x0[k]; C.a1[c] = mid; C.a2[c] = x2[k] + 1;
+        C.code[c + 1] = nxt; C.a0[c + 1] = mid; C.a1[c + 1] = x1[k]; C.a2[c + 1] = x2[k] + 1;
       }
-    } else if (op == OP_MS) {
-      const int32_t mid = x0 + (x1 - x0) / 2;
-      C.code[c] = nxt; C.a0[c] = x0; C.a1[c] = mid; C.a2[c] = x2 + 1;
-      C.code[c + 1] = nxt; C.a0[c + 1] = mid; C.a1[c + 1] = x1; C.a2[c + 1] = x2 + 1;
+    }
+    // ---- join / emit: writes to the item's own entry ----------------------
+    const int64_t i = idx[k];
+    if (act[k] == ACT_EMIT) {
+      C.r[i] = val[k];
+      C.code[i] = 0;
+    } else if (act[k] == ACT_FINISH) {
+      C.code[i] = 0;
+    } else if (act[k] == ACT_JOIN) {
+      C.code[i] = cen[k] * ntt + tbase[k] + 1;   // local type 2: SUM / QSUM / MERGE
+      if (op[k] != OP_MS) {
+        C.a0[i] = cb;
+        if (op[k] == OP_Q) C.a1[i] = nk[k];
+      }
     }
   }
 
-  // ---- join / emit: writes to the lane's own entry -------------------------
-  if (act == ACT_EMIT) {
-    C.r[i] = val;
-    C.code[i] = 0;
-  } else if (act == ACT_FINISH) {
-    C.code[i] = 0;
-  } else if (act == ACT_JOIN) {
-    C.code[i] = cen * ntt + tbase + 1;   // local type 2: SUM / QSUM / MERGE
-    if (op != OP_MS) {
-      C.a0[i] = cb;
-      if (op == OP_Q) C.a1[i] = nk;
-    }
-  }
-
-  // ---- BFS: co-operative expansion of the VISIT lanes' arcs ----------------
-  if (OPS & OPS_BFS) {
-    const bool isv = (op == OP_VISIT);
-    if (__syncthreads_or(isv)) {
-      int32_t deg = 0, row = 0;
-      if (isv) {
-        const int32_t v = C.a0[i];
-        const int32_t *rp = (const int32_t *)C.ts[slot].ptr0;
-        row = rp[v];
-        deg = rp[v + 1] - row;
+  __syncthreads();
+  phase_mark(C, L, 3);
+  // ---- BFS: co-operative expansion of the VISIT items' arcs -----------------
+  if constexpr ((OPS & OPS_BFS) != 0) {
+    bool anyv = false;
+#pragma unroll
+    for (int k = 0; k < IT; ++k) anyv |= (op[k] == OP_VISIT);
+    if (__syncthreads_or(anyv)) {
+      int32_t deg[IT], row[IT];
+      int dsum = 0;
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        deg[k] = 0; row[k] = 0;
+        if (op[k] == OP_VISIT) {
+          const int32_t *rp = (const int32_t *)C.ts[slot[k]].ptr0;
+          row[k] = rp[a0v[k]];
+          deg[k] = rp[a0v[k] + 1] - row[k];
+        }
+        dsum += deg[k];
       }
       int tot;
-      const int pre = wg_excl_scan<WG>(deg, L.scan_tmp, &tot);
-      L.v_row[tid] = row;
-      L.v_pre[tid] = pre;
-      L.v_seg[tid] = seg;
-      L.v_cen[tid] = cen;
+      int pre = wg_excl_scan<WG>(dsum, L.scan_tmp, &tot);
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        V.row[tid * IT + k] = row[k];
+        V.pre[tid * IT + k] = pre;
+        V.seg[tid * IT + k] = seg[k];
+        pre += deg[k];
+      }
+      if (tid == 0) V.qn = 0;
       __syncthreads();
-      for (int e0 = 0; e0 < tot; e0 += WG) {
-        const int e = e0 + tid;
-        int claim = 0, sseg = -1;
-        int32_t u = 0, scen = 0;
-        const TreeStatic *ST = nullptr;
-        if (e < tot) {
-          int lo = 0, hi = WG;   // last lane l with v_pre[l] <= e
-          while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (L.v_pre[mid] <= e) lo = mid; else hi = mid; }
-          sseg = L.v_seg[lo];
-          scen = L.v_cen[lo];
-          ST = &C.ts[L.seg_slot[sseg]];
-          u = ((const int32_t *)ST->ptr1)[L.v_row[lo] + (e - L.v_pre[lo])];
-          int32_t *depth = (int32_t *)ST->ptr2;
-          if (depth[u] == -1 && atomicCAS(&depth[u], -1, scen + 1) == -1) claim = 1;
+      // One arc per lane per step.  A claimed vertex is queued in LDS; the
+      // queue is turned into child entries in bulk (one device atomic per
+      // tree per flush) when it is nearly full and at the end.
+      constexpr int A = kArcsPerLane;
+      int from = 0;   // arcs are visited in increasing order: item searches only move forward
+      for (int e0 = 0; e0 < tot; e0 += WG * A) {
+        int32_t u[A], sseg[A];
+        int32_t *dep[A];
+        int32_t dv[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          const int e = e0 + a * WG + tid;
+          sseg[a] = -1;
+          if (e < tot) {
+            int lo = from, hi = kChunk;   // last item with pre <= e
+            while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
+            from = lo;
+            sseg[a] = V.seg[lo];
+            const TreeStatic *ST = &C.ts[L.seg_slot[sseg[a]]];
+            u[a] = ((const int32_t *)ST->ptr1)[V.row[lo] + (e - V.pre[lo])];
+            dep[a] = (int32_t *)ST->ptr2;
+          }
         }
-        const int32_t vb = wg_alloc<WG, MULTI>(C, L, sseg, claim, P);
-        if (claim && vb >= 0) {
-          const int64_t c = ST->base + vb;
-          C.code[c] = (scen + 1) * ntt + ST->tbase;
-          C.a0[c] = u;
+#pragma unroll
+        for (int a = 0; a < A; ++a) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;   // probes issued together
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          if (sseg[a] >= 0 && dv[a] == -1 &&
+              atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1) {
+            const int q = atomicAdd(&V.qn, 1);
+            V.qu[q] = u[a];
+            V.qs[q] = (int16_t)sseg[a];
+          }
+        }
+        __syncthreads();
+        const int qn = V.qn;
+        if (qn > kClaimQ - WG * A || e0 + WG * A >= tot) {
+          for (int q0 = 0; q0 < qn; q0 += WG) {
+            const int q = q0 + tid;
+            const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
+            if (q < qn) V.qo[q] = o;
+          }
+          seg_commit<WG, MULTI>(C, L, P, false);
+          for (int q = tid; q < qn; q += WG) {
+            const int sseg = V.qs[q];
+            const int32_t vb = L.seg_base[sseg];
+            if (vb >= 0) {
+              const TreeStatic *ST = &C.ts[L.seg_slot[sseg]];
+              const int64_t c = ST->base + vb + V.qo[q];
+              C.code[c] = (L.seg_cen[sseg] + 1) * ntt + ST->tbase;
+              C.a0[c] = V.qu[q];
+            }
+          }
+          __syncthreads();
+          if (tid == 0) V.qn = 0;
+          __syncthreads();
         }
       }
     }
   }
 
-  // ---- per-tree bookkeeping: valid tasks, retired items --------------------
-  if (C.trace_on) seg_add(L.seg_valid, seg, op != OP_NONE ? 1 : 0);
+  // ---- per-tree bookkeeping: retired items ----------------------------------
   __syncthreads();
+  phase_mark(C, L, 4);
   const int nseg = L.nseg;
   for (int s = tid; s < nseg; s += WG) {
     const int32_t j = L.seg_join[s];
@@ -538,7 +667,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
       const int sl = L.seg_slot[s];
       const uint32_t beg = (s == 0) ? L.off0 : L.win[s - 1];
       const uint32_t end = L.win[s];
-      const uint32_t lo = max(beg, w0), hi = min(min(end, w0 + (uint32_t)WG), S);
+      const uint32_t lo = max(beg, w0), hi = min(min(end, w0 + (uint32_t)kChunk), S);
       const uint32_t items = hi - lo;
       if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
       const uint64_t add = ((uint64_t)(uint32_t)j << 32) | items;
@@ -549,6 +678,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, uint32_t w0, uint32_t S, 
     }
   }
   __syncthreads();
+  phase_mark(C, L, 5);
 }
 
 // ---------------------------------------------------------------------------
@@ -734,12 +864,18 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
       T->done_gepoch = H->gepoch;
     }
   }
-  const int ts = H->tslots;
-  const int per = (ts + WG - 1) / WG;
-  const int t0 = min(tid * per, ts), t1 = min(t0 + per, ts);
+  // Candidates: after an epoch, the trees of the last work list (a live
+  // tree always has a non-empty range); at the start of a run, every slot.
+  const int sel = H->live_sel;
+  const int32_t *src = C.live + (size_t)sel * C.tmax;
+  int32_t *dst = C.live + (size_t)(after_epoch ? (sel ^ 1) : 0) * C.tmax;
+  const int n = after_epoch ? H->live : H->tslots;
+  const int per = (n + WG - 1) / WG;
+  const int t0 = min(tid * per, n), t1 = min(t0 + per, n);
   int cnt = 0, items = 0;
   for (int t = t0; t < t1; ++t) {
-    const int len = C.t_len[t];
+    const int slot = after_epoch ? src[t] : t;
+    const int len = C.t_len[slot];
     if (len > 0) { ++cnt; items += len; }
   }
   int ctot, itot;
@@ -749,13 +885,15 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
   uint32_t off = (uint32_t)ipre;
   const int64_t g = H->gepoch + (after_epoch ? 1 : 0);
   for (int t = t0; t < t1; ++t) {
-    const int len = C.t_len[t];
+    const int slot = after_epoch ? src[t] : t;
+    const int len = C.t_len[slot];
     if (len > 0) {
-      C.wl_tree[k] = t;
+      dst[k] = slot;
+      C.wl_tree[k] = slot;
       C.wl_off[k] = off;
-      C.wl_start[k] = C.ts[t].base + C.t_b[t];
-      C.wl_cen[k] = C.t_cen[t];
-      if (C.st[t].start_gepoch < 0) C.st[t].start_gepoch = g;
+      C.wl_start[k] = C.ts[slot].base + C.t_b[slot];
+      C.wl_cen[k] = C.t_cen[slot];
+      if (C.st[slot].start_gepoch < 0) C.st[slot].start_gepoch = g;
       ++k;
       off += (uint32_t)len;
     }
@@ -767,12 +905,17 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
       H->mapJ = (uint32_t)(mc >> kMapShift);
       st_agent(&H->map_ctr, (uint64_t)0);
     }
+    H->live_sel = after_epoch ? (sel ^ 1) : 0;
     C.wl_off[ctot] = (uint32_t)itot;
     H->S = (uint32_t)itot;
     H->L = ctot;
     H->live = ctot;
     H->done_count = 0;
-    if (after_epoch) { H->gepoch += 1; H->run_epochs += 1; }
+    if (after_epoch) {
+      if (H->run_epochs < kEpochStamps) H->stamp[H->run_epochs] = realtime();
+      H->gepoch += 1;
+      H->run_epochs += 1;
+    }
     int stop = 0;
     if (ctot == 0) stop = 1;
     else if (H->max_epochs >= 0 && H->run_epochs >= H->max_epochs) stop = 2;
@@ -786,7 +929,7 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
 
 template <int WG>
 __device__ __forceinline__ void lds_init(Lds<WG> &L) {
-  for (int t = threadIdx.x; t < WG; t += WG) { L.seg_cnt[t] = 0; L.seg_join[t] = 0; L.seg_valid[t] = 0; }
+  for (int t = threadIdx.x; t < kChunk; t += WG) { L.seg_cnt[t] = 0; L.seg_join[t] = 0; L.seg_valid[t] = 0; }
   __syncthreads();
 }
 
@@ -797,7 +940,9 @@ __device__ __forceinline__ void lds_init(Lds<WG> &L) {
 // Plain form: one launch per epoch of one tree; grid covers the range.
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
+  using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG> L;
+  __shared__ VL V;
   lds_init<WG>(L);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int q = P.par ^ 1;   // the next epoch's counters
@@ -805,7 +950,7 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
     C.plain->map[q] = 0;
   }
   const uint32_t S = (uint32_t)(P.e - P.b);
-  run_chunk<WG, OPS, false>(C, L, blockIdx.x * WG, S, 1, P);
+  run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P);
 }
 
 // Grid barrier between epochs (Tenet 1: one arrival per work-group).  Every
@@ -821,10 +966,23 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
   fence_release();
   __syncthreads();
   if (threadIdx.x == 0) {
+    // two-level arrival: work-groups arrive at their group's counter (group
+    // = blockIdx % 8, one group per XCD under round-robin dispatch); the last
+    // of each group arrives at the top counter
     const uint32_t g = ld_agent(&H->gen);
     fence_release();
-    const uint32_t a = add_agent(&H->arrive, 1u);
-    L.flag = (a == gridDim.x - 1);
+    const uint32_t G = gridDim.x;
+    const uint32_t ng = G < 8 ? G : 8;
+    const uint32_t grp = blockIdx.x & 7;
+    const uint32_t gsize = (G - grp + 7) / 8;
+    int last = 0;
+    const uint32_t a = add_agent(&H->grp[grp].n, 1u);
+    if (a == gsize - 1) {
+      st_agent(&H->grp[grp].n, 0u);
+      const uint32_t b = add_agent(&H->arrive, 1u);
+      last = (b == ng - 1);
+    }
+    L.flag = last;
     L.gen = g;
   }
   __syncthreads();
@@ -872,11 +1030,15 @@ template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
   using MapL = typename std::conditional<kMap, MapLds, NoMapLds>::type;
+  using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG> L;
   __shared__ MapL M;
+  __shared__ VL V;
   __shared__ uint32_t s_hdr[4];
   lds_init<WG>(L);
   if (threadIdx.x == 0) L.tflag = 0;
+  if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
+  if (threadIdx.x == 0) L.tprof = realtime();
   SchedHdr *H = C.hdr;
   const PlainArgs P{};
   while (true) {
@@ -899,12 +1061,19 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     }
     if (stop) break;
     if (mapJ && !grid_barrier<WG>(C, L, false, true)) break;
-    const uint32_t nchunks = (S + WG - 1) / WG;
-    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x)
-      run_chunk<WG, OPS, true>(C, L, c * WG, S, nL, P);
+    // each work-group sweeps a contiguous run of chunks
+    const uint32_t nchunks = (S + kChunk - 1) / kChunk;
+    const uint32_t per = (nchunks + gridDim.x - 1) / gridDim.x;
+    const uint32_t c0 = min(blockIdx.x * per, nchunks), c1 = min(c0 + per, nchunks);
+    for (uint32_t c = c0; c < c1; ++c)
+      run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, c != c0);
+    phase_mark(C, L, 6);
     const bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
+    phase_mark(C, L, 7);
     if (!persistent || !ok) break;
   }
+  if (C.debug && threadIdx.x == 0)
+    for (int ph = 0; ph < 8; ++ph) add_agent(&H->phase[ph], (uint64_t)L.prof[ph]);
 }
 
 // Map launches (plain and graph forms).  from_hdr: take the job count the
@@ -945,7 +1114,8 @@ __global__ __launch_bounds__(WG) void k_map_merge(DevCtx C, uint32_t Jarg, int32
 template <int WG>
 __global__ __launch_bounds__(WG) void k_scan(DevCtx C) {
   __shared__ Lds<WG> L;
-  if (threadIdx.x == 0) { C.hdr->arrive = 0; C.hdr->done_count = 0; C.hdr->stop_reason = 0; }
+  if (threadIdx.x < 8) C.hdr->grp[threadIdx.x].n = 0;
+  if (threadIdx.x == 0) { C.hdr->arrive = 0; C.hdr->done_count = 0; C.hdr->stop_reason = 0; C.hdr->stamp0 = realtime(); }
   __syncthreads();
   schedule_scan<WG>(C, L, false);
 }
@@ -1042,7 +1212,7 @@ hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t ne
   const void *fn = kernel_plain(wg, need);
   if (!fn) return hipErrorInvalidValue;
   const uint32_t S = (uint32_t)(P.e - P.b);
-  dim3 grid((S + wg - 1) / wg), block(wg);
+  dim3 grid((S + kChunk - 1) / kChunk), block(wg);
   DevCtx c = C;
   PlainArgs p = P;
   void *args[] = {&c, &p};

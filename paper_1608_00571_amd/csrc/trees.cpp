@@ -410,6 +410,8 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
   c->hdr_host->max_epochs = max_epochs;
   c->hdr_host->tslots = c->tslots;
   c->hdr_host->arrive = 0;
+  for (int g = 0; g < 8; ++g) c->hdr_host->grp[g].n = 0;
+  c->hdr_host->live_sel = 0;
   c->hdr_host->mapJ = 0;
   c->hdr_host->map_ctr = 0;
   c->hdr_host->map_arrive = 0;
@@ -581,7 +583,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
                o_b = take(T * 4), o_stk = take(T * kStackMax * sizeof(int4)),
                o_tr = trace ? take(T * kTraceMax * sizeof(TraceRec)) : 0, o_wt = take((T + 1) * 4),
                o_wo = take((T + 1) * 4), o_ws = take((T + 1) * 8), o_wc = take((T + 1) * 4),
-               o_dl = take(T * 4), o_hdr = take(sizeof(SchedHdr)), o_pl = take(sizeof(PlainCounters)),
+               o_dl = take(T * 4), o_lv = take(2 * T * 4), o_hdr = take(sizeof(SchedHdr)),
+               o_pl = take(sizeof(PlainCounters)),
                o_adm = take(T * sizeof(Admit));
   const bool nomap = (cfg->flags & TREES_F_NOMAP) != 0;
   const size_t MJ = nomap ? 0 : (size_t)kMapJobs;
@@ -604,6 +607,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.wl_start = (int64_t *)(b + o_ws);
   c->dc.wl_cen = (int32_t *)(b + o_wc);
   c->dc.done_list = (int32_t *)(b + o_dl);
+  c->dc.live = (int32_t *)(b + o_lv);
+  c->dc.tmax = (int32_t)T;
   c->dc.hdr = (SchedHdr *)(b + o_hdr);
   c->dc.plain = (PlainCounters *)(b + o_pl);
   c->adm_dev = (Admit *)(b + o_adm);
@@ -911,6 +916,28 @@ trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
   for (int k = 0; k < n && k < 6; ++k) out[k] = c->ktime[k];
   if (n > 6) out[6] = c->mtime;
+  return TREES_OK;
+}
+
+trees_status trees_debug_phases(trees_ctx *c, double *us, int32_t n) {
+  if (!c || !us) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  HIPCHK(c, hipMemcpy(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost));
+  for (int k = 0; k < n && k < 8; ++k) us[k] = (double)c->hdr_host->phase[k] * 1e6 / c->clock_hz;
+  return TREES_OK;
+}
+
+trees_status trees_epoch_times(trees_ctx *c, double *us, int32_t cap, int32_t *n) {
+  if (!c || !n) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  HIPCHK(c, hipMemcpy(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost));
+  const int ne = (int)std::min<int64_t>(c->hdr_host->run_epochs, kEpochStamps);
+  int64_t prev = c->hdr_host->stamp0;
+  for (int e = 0; e < ne && e < cap; ++e) {
+    us[e] = (double)(c->hdr_host->stamp[e] - prev) * 1e6 / c->clock_hz;
+    prev = c->hdr_host->stamp[e];
+  }
+  *n = ne;
   return TREES_OK;
 }
 

@@ -97,14 +97,21 @@ struct SchedHdr {
   int32_t tslots;       // slots [0, tslots) may hold trees
   uint32_t mapJ;        // map jobs registered by the last epoch (raw count)
   int32_t pad0[14];
-  alignas(128) uint32_t arrive;   // barrier arrival counter
+  alignas(128) uint32_t arrive;   // barrier arrivals of the last work-group of each group
   int32_t pad1[31];
+  struct alignas(128) Grp { uint32_t n; int32_t pad[31]; } grp[8];   // per-group arrivals (blockIdx % 8)
+  int32_t live_sel;               // which half of the live-tree list is current
+  int32_t pad4[31];
   alignas(128) uint32_t gen;      // barrier generation
   int32_t pad2[31];
   alignas(128) uint64_t map_ctr;  // (jobs << 38) | units, appended during an epoch
   uint32_t map_arrive;            // work-groups done with the map launch
   int32_t pad3[29];
+  int64_t stamp0;                 // device clock when the run's first work list was built
+  int64_t stamp[256];             // device clock at the end of each epoch of the run
+  uint64_t phase[8];              // debug: summed work-group time per chunk phase (device clock)
 };
+constexpr int kEpochStamps = 256;
 
 // A map counter packs the job count (high 26 bits) and the job units (low
 // 38 bits) so one atomic add per work-group reserves both, and job indices
@@ -136,6 +143,9 @@ struct DevCtx {
   int64_t *wl_start;              // absolute task-vector index of the range start
   int32_t *wl_cen;                // epoch number of the entry
   int32_t *done_list;             // trees finished in this epoch
+  int32_t *live;                  // 2 x tmax: live tree slots in work-list order (double buffer)
+  int32_t tmax;
+  int32_t pad3;
   SchedHdr *hdr;
   PlainCounters *plain;
   const volatile int32_t *abort_flag;  // host-pinned, set by trees_abort

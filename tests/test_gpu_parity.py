@@ -127,3 +127,22 @@ def test_many_small_trees(sched):
             j.collect(ctx, trace=True)
     for j in jobs:
         assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_bfs_batch(sched):
+    """16 R-MAT graphs of scale 10..16 in one run: hubs with thousands of
+    arcs, many trees per chunk, claim queues flushed several times."""
+    scales = [10 + (g % 7) for g in range(16)]
+    jobs = [Job("bfs", graph=inputs.rmat(sc, 500 + g)) for g, sc in enumerate(scales)]
+    run_alone(sched, jobs, trace=True)
+    for j in jobs:
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+def test_bfs_full_scale_graph(sched):
+    """One graph at the batch's largest scale (2^22 vertices, 2^26 arcs)."""
+    g = inputs.bfs_batch_graph(0, 22)
+    (j,) = run_alone(sched, [Job("bfs", graph=g)], trace=False)
+    assert_matches_oracle(j, check_trace=False)
