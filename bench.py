@@ -272,12 +272,18 @@ def bench_cfg3(args):
         else:
             tv_bytes += nq[n][2] + 4 * (launched - tasks)
     total_tasks = sum(expect[k][1] for k in kinds)
-    arena = (sum(T.tv_bound(k, [n]) for k, n in kinds) + 4096) * T.BYTES_PER_ENTRY
+    arena = (sum(T.tv_bound(k, [n]) + 64 for k, n in kinds) + 4096) * T.BYTES_PER_ENTRY
 
     def run(sched, wg, bpc=0, chunk=8, steps=1, warmup=1, subset=None):
         ks = kinds if subset is None else kinds[:subset]
         ctx = T.Context(arena, sched=sched, wg=wg, blocks_per_cu=bpc, graph_chunk=chunk, profile=True,
                         max_trees=len(ks))
+        try:
+            return run_in(ctx, sched, ks, steps, warmup)
+        finally:
+            ctx.close()
+
+    def run_in(ctx, sched, ks, steps, warmup):
         pf, pq = ctx.register(T.FIB_I64), ctx.register(T.NQUEENS)
         times, gep = [], 0
         for it in range(warmup + steps):
@@ -296,14 +302,31 @@ def bench_cfg3(args):
                 kms = sum(kt1[x][0] - kt0[x][0] for x in kt1)
                 et = ctx.epoch_times() if sched != "plain" else None
                 times.append((dt, kms, rs, et))
-        ctx.close()
         dt = min(t[0] for t in times)
         kms = min(t[1] for t in times)
         return dict(dt=dt, kernel_ms=kms, rs=times[0][2], et=times[0][3])
 
     out = {}
-    for sched in ("persistent", "graph"):
-        r = run(sched, args.wg, steps=args.steps, warmup=args.warmup)
+    # autotune scheduler x work-group size x work-groups per CU x graph chunk
+    from paper_1608_00571_amd import autotune
+    tuned = None
+    if args.tune:
+        tctx = T.Context(arena, sched="graph", profile=True, max_trees=len(kinds))
+
+        def measure(shape):
+            shape.apply(tctx)
+            return run_in(tctx, shape.sched, kinds, 1, 0)["dt"]
+        tuned, table = autotune.tune(measure, autotune.candidates(bpcs=(0, 2, 3, 4, 6, 8), chunks=(8, 16)),
+                                     torch.cuda.get_device_name(0), f"batch{len(kinds)}", use_cache=False)
+        tctx.close()
+        out["autotune_top5"] = [{**s.__dict__, "ms": round(t * 1e3, 3)} for s, t in table[:5]]
+    shapes = [("persistent", args.wg, 0, 8), ("graph", args.wg, 0, 8)]
+    if tuned is not None:
+        shapes.insert(0, (tuned.sched, tuned.wg, tuned.blocks_per_cu, tuned.graph_chunk))
+    for i, (sched, wg, bpc, ch) in enumerate(shapes):
+        r = run(sched, wg, bpc, ch, steps=args.steps, warmup=args.warmup)
+        if i == 0 and tuned is not None:
+            sched = f"tuned:{sched}/wg{wg}/bpc{bpc}/chunk{ch}"
         out[sched] = {"tasks_per_s": total_tasks / r["dt"], "ms": round(r["dt"] * 1e3, 3),
                       "kernel_ms": round(r["kernel_ms"], 3), "global_epochs": r["rs"].global_epochs,
                       "grid": r["rs"].grid,
@@ -314,7 +337,7 @@ def bench_cfg3(args):
             out[sched]["epoch_us"] = {"min": round(float(np.min(et)), 2), "median": round(float(np.median(et)), 2),
                                       "max": round(float(np.max(et)), 2),
                                       "narrow_epochs_median": round(float(np.median(np.sort(et)[:10])), 2)}
-    best = max(out, key=lambda k: out[k]["tasks_per_s"])
+    best = max((k for k in out if "tasks_per_s" in out[k]), key=lambda k: out[k]["tasks_per_s"])
     # plain: the same trees one after another, one launch per epoch
     sub = args.plain_subset
     rp = run("plain", args.wg, steps=1, warmup=0, subset=sub)
@@ -334,7 +357,7 @@ def bench_cfg3(args):
         "batched_vs_plain_factor": round(factor, 2),
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"k_epochs<{args.wg},FIB|NQ> ({best})"},
+                     "kernel": f"k_epochs<FIB|NQ> ({best})"},
     }
     return line
 
@@ -401,7 +424,7 @@ def bench_cfg4(args):
     max_depth = max(int(w.max()) for w in want)
     tv = 12 * reached + 8 * reached            # VISIT entry + the child entry that created it
     payload = 8 * reached + 8 * scanned + 4 * reached   # row_ptr pair, col + depth probe per arc, claim
-    arena = (V + 4096) * T.BYTES_PER_ENTRY
+    arena = (V + 64 * len(gs) + 4096) * T.BYTES_PER_ENTRY
     out = {}
     for sched in args.scheds.split(","):
         ctx = T.Context(arena, sched=sched, wg=args.wg, profile=True, max_trees=len(gs))
@@ -542,6 +565,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-arena-gib", type=int, default=16)
     ap.add_argument("--burst", type=int, default=4)
+    ap.add_argument("--no-tune", dest="tune", action="store_false")
     ap.add_argument("--scheds", default="persistent,graph,plain")
     ap.add_argument("--plain-subset", type=int, default=4096)
     ap.add_argument("--no-compare", dest="compare", action="store_false",

@@ -151,7 +151,8 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      (the pointers may be NULL when N = 0).
  *   BFS_CSR:           args = {V, source}; bufs = {row_ptr[V+1], col_idx[E], depth[V] (out)}
  *                      int32 CSR; depth receives hop counts, -1 = unreachable.
- * The arena is sized to the exact task-vector bound of the tree; if it does
+ * The arena is sized to the exact task-vector bound of the tree, rounded up to
+ * a multiple of 64 entries (arenas start on 64-entry boundaries); if it does
  * not fit in the free budget the call returns NOMEM and changes nothing (the
  * caller may retry once other trees have been collected).  Buffers must stay
  * alive and unmodified until trees_results returns OK for the tree.  The tree
@@ -213,8 +214,8 @@ trees_status trees_abort(trees_ctx *ctx);
 trees_status trees_set_schedule(trees_ctx *ctx, int32_t sched, int32_t wg_size,
                                 int32_t blocks_per_cu, int32_t graph_chunk);
 
-/* Exact task-vector entries a tree of `kind` with `args` can occupy at once
- * (the admission size).  Host-only. */
+/* Exact task-vector entries a tree of `kind` with `args` can occupy at once.
+ * Admission charges this rounded up to a multiple of 64.  Host-only. */
 trees_status trees_tv_bound(int32_t kind, const int64_t *args, int32_t nargs, int64_t *entries);
 
 /* Free task-vector entries of the budget (for admission decisions). */

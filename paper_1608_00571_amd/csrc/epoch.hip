@@ -57,14 +57,16 @@ struct Lds {
   uint64_t ubase;          // first map unit reserved by this work-group
   int64_t tprof;           // debug: clock at the last phase boundary
   int64_t prof[8];         // debug: time per phase
+  uint8_t op_tab[kMaxTypes + 1];   // global type id -> operation
   uint32_t win[kChunk];    // wl_off[kfirst + 1 + t]
   int32_t seg_slot[kChunk];   // tree slot of segment s
   int32_t seg_cen[kChunk];    // its epoch number
-  int64_t seg_start[kChunk];  // absolute task-vector index of its range start
+  int32_t seg_b[kChunk];      // arena-relative start of its range
+  uint32_t seg_tb[kChunk];    // its arena base / 64
+  uint32_t seg_tp[kChunk];    // first type id | parameter << 8
   int32_t seg_cnt[kChunk];    // children requested per segment (LDS atomics)
   int32_t seg_base[kChunk];   // arena-relative first child per segment (-1: overflow)
-  int32_t seg_join[kChunk];
-  int32_t seg_valid[kChunk];
+  int32_t seg_jv[kChunk];     // joins (low 16 bits) | valid tasks (high 16 bits) per segment
   int32_t scan_tmp[WG / 64 + 1];
   int64_t scan_tmp64[WG / 64 + 1];
 };
@@ -98,20 +100,19 @@ __device__ __forceinline__ void phase_mark(const DevCtx &C, Lds<WG> &L, int ph) 
 // Segment helpers
 // ---------------------------------------------------------------------------
 
-// arr[seg] += v for every lane, one LDS atomic per wavefront when the whole
-// wavefront belongs to one segment.  0 <= v < 2^16.
-__device__ __forceinline__ void seg_add(int32_t *arr, int seg, int v) {
-  uint64_t m = ballot64(v > 0);
+// Adds two 0/1 flags per lane to a segment's packed counter: `lo` to the
+// low 16 bits and `hi` to the high 16 bits (a segment retires at most
+// kChunk items per chunk, so neither half carries).
+__device__ __forceinline__ void seg_add_pair(int32_t *arr, int seg, bool lo, bool hi) {
+  const uint64_t mlo = ballot64(lo), mhi = ballot64(hi);
+  const uint64_t m = mlo | mhi;
   if (!m) return;
-  int leader = __ffsll((unsigned long long)m) - 1;
-  int s0 = __shfl(seg, leader, 64);
-  if (__all(v == 0 || seg == s0)) {
-    int tot = 0;
-#pragma unroll
-    for (int b = 0; b < 16; ++b) tot += __popcll(ballot64((v >> b) & 1)) << b;
-    if (lane_id() == leader) atomicAdd(&arr[s0], tot);
-  } else if (v > 0) {
-    atomicAdd(&arr[seg], v);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  const int s0 = __shfl(seg, leader, 64);
+  if (__all(!(lo || hi) || seg == s0)) {
+    if (lane_id() == leader) atomicAdd(&arr[s0], __popcll(mlo) + (__popcll(mhi) << 16));
+  } else if (lo || hi) {
+    atomicAdd(&arr[seg], (lo ? 1 : 0) + (hi ? 0x10000 : 0));
   }
 }
 
@@ -164,8 +165,8 @@ __device__ __forceinline__ void seg_commit(const DevCtx &C, Lds<WG> &L, const Pl
         }
       }
     } else {
-      const int j = with_joins ? L.seg_join[s] : 0;
-      if (with_joins) L.seg_join[s] = 0;
+      const int j = with_joins ? (L.seg_jv[s] & 0xFFFF) : 0;
+      if (with_joins) L.seg_jv[s] &= ~0xFFFF;
       if (c > 0 || j > 0) {
         L.seg_cnt[s] = 0;
         const uint64_t prev = add_agent(&C.plain->fj[P.par], ((uint64_t)(uint32_t)j << 32) | (uint32_t)c);
@@ -308,12 +309,21 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
     for (int t = tid; t < L.nseg; t += WG) {
       L.seg_slot[t] = C.wl_tree[kf + t];
       L.seg_cen[t] = C.wl_cen[kf + t];
-      L.seg_start[t] = C.wl_start[kf + t];
+      L.seg_b[t] = C.wl_b[kf + t];
+      L.seg_tb[t] = C.wl_tb[kf + t];
+      L.seg_tp[t] = C.wl_tp[kf + t];
     }
   } else if (tid == 0) {
     L.kfirst = 0; L.nseg = 1; L.off0 = 0; L.win[0] = S;
-    if (MULTI) { L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_start[0] = C.wl_start[0]; }
-    else { L.seg_slot[0] = P.slot; L.seg_cen[0] = P.cen; L.seg_start[0] = C.ts[P.slot].base + P.b; }
+    if (MULTI) {
+      L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_b[0] = C.wl_b[0];
+      L.seg_tb[0] = C.wl_tb[0]; L.seg_tp[0] = C.wl_tp[0];
+    } else {
+      const TreeStatic *T = &C.ts[P.slot];
+      L.seg_slot[0] = P.slot; L.seg_cen[0] = P.cen; L.seg_b[0] = P.b;
+      L.seg_tb[0] = (uint32_t)(T->base >> 6);
+      L.seg_tp[0] = (uint32_t)T->tbase | ((uint32_t)(T->kind == 4 ? T->p0 : 0) << 8);
+    }
   }
   __syncthreads();
 
@@ -323,11 +333,14 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
   int seg[IT], slot[IT], op[IT];
   int32_t cen[IT];
   int64_t idx[IT];
+  int64_t tb[IT];      // arena base of the item's tree
+  uint32_t tp[IT];     // its first type id | parameter << 8
   int32_t code[IT], a0v[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     const uint32_t w = w0 + (uint32_t)(k * WG + tid);
     seg[k] = -1; slot[k] = 0; cen[k] = 0; idx[k] = 0; code[k] = 0; a0v[k] = 0; op[k] = OP_NONE;
+    tb[k] = 0; tp[k] = 0;
     if (w < S) {
       int s = 0;
       if (MULTI && nL > 1) {   // segments past the item's offset in the chunk cannot hold it
@@ -338,7 +351,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
       seg[k] = s;
       slot[k] = L.seg_slot[s];
       cen[k] = L.seg_cen[s];
-      idx[k] = L.seg_start[s] + (int64_t)(w - (s == 0 ? L.off0 : L.win[s - 1]));
+      tb[k] = (int64_t)L.seg_tb[s] << 6;
+      tp[k] = L.seg_tp[s];
+      idx[k] = tb[k] + L.seg_b[s] + (int64_t)(w - (s == 0 ? L.off0 : L.win[s - 1]));
       code[k] = C.code[idx[k]];
       a0v[k] = C.a0[idx[k]];
     }
@@ -347,7 +362,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
   for (int k = 0; k < IT; ++k) {
     if (code[k] != 0) {
       const int32_t gtype = code[k] - cen[k] * ntt;
-      if (gtype >= 1 && gtype <= ntt) op[k] = C.op_of_type[gtype];
+      if (gtype >= 1 && gtype <= ntt) op[k] = L.op_tab[gtype];
       // an entry outside the epoch's encoding window, or of a type this
       // kernel was not built for, is an error of its tree
       if (op[k] == OP_NONE || (opbit(op[k]) & OPS) == 0) {
@@ -364,17 +379,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
   int64_t val[IT];
   int32_t x0[IT], x1[IT], x2[IT], x3[IT];
   bool want_map[IT], leaf[IT];
-  int64_t tb[IT];      // arena base of the item's tree
-  int32_t tbase[IT];   // global type id of its program's first type
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     nk[k] = 0; act[k] = ACT_NONE; val[k] = 0;
     x0[k] = x1[k] = x2[k] = x3[k] = 0;
-    want_map[k] = false; leaf[k] = false; tb[k] = 0; tbase[k] = 0;
+    want_map[k] = false; leaf[k] = false;
     if (op[k] == OP_NONE) continue;
-    const TreeStatic *T = &C.ts[slot[k]];
-    tb[k] = T->base;
-    tbase[k] = T->tbase;
     const int64_t i = idx[k];
     switch (op[k]) {
       case OP_FIB32:
@@ -393,7 +403,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
         act[k] = ACT_EMIT; val[k] = C.r[tb[k] + c] + C.r[tb[k] + c + 1];
       } break;
       case OP_Q: {
-        const int32_t n = T->p0;
+        const int32_t n = (int32_t)(tp[k] >> 8);
         const int32_t row = a0v[k];
         if (row == n) { act[k] = ACT_EMIT; val[k] = 1; break; }
         const uint32_t full = (1u << n) - 1u;
@@ -418,8 +428,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
       case OP_MERGE: {
         act[k] = ACT_FINISH;
         x0[k] = a0v[k]; x1[k] = C.a1[i]; x2[k] = C.a2[i];
-        if (C.mj_cap > 0) want_map[k] = true;   // the merge runs in the map phase
-        else ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0[k], x1[k], x2[k]);
+        if (C.mj_cap > 0) {
+          want_map[k] = true;   // the merge runs in the map phase
+        } else {
+          const TreeStatic *T = &C.ts[slot[k]];
+          ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0[k], x1[k], x2[k]);
+        }
       } break;
       case OP_VISIT:
         act[k] = ACT_FINISH;   // its arcs are expanded co-operatively below
@@ -509,8 +523,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
   int off[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    seg_add(L.seg_join, seg[k], act[k] == ACT_JOIN ? 1 : 0);   // joins per tree segment
-    if (C.trace_on) seg_add(L.seg_valid, seg[k], op[k] != OP_NONE ? 1 : 0);
+    // joins (and, when tracing, valid tasks) per tree segment
+    seg_add_pair(L.seg_jv, seg[k], act[k] == ACT_JOIN, C.trace_on && op[k] != OP_NONE);
     off[k] = lds_reserve(L.seg_cnt, seg[k], nk[k]);
   }
   seg_commit<WG, MULTI>(C, L, P, true);
@@ -520,12 +534,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
     const int32_t cb = child_base(L.seg_base, seg[k], nk[k], off[k]);
     if (nk[k] > 0 && cb >= 0) {
       const int64_t c = tb[k] + cb;
-      const int32_t nxt = (cen[k] + 1) * ntt + tbase[k];   // code of local type 1, next epoch
+      const int32_t nxt = (cen[k] + 1) * ntt + (int32_t)(tp[k] & 0xFF);   // local type 1, next epoch
       if (op[k] == OP_FIB32 || op[k] == OP_FIB64) {
         C.code[c] = nxt; C.a0[c] = x0[k] - 1;
         C.code[c + 1] = nxt; C.a0[c + 1] = x0[k] - 2;
       } else if (op[k] == OP_Q) {
-        const int32_t n = C.ts[slot[k]].p0;
+        const int32_t n = (int32_t)(tp[k] >> 8);
         const uint32_t full = (1u << n) - 1u;
         const uint32_t cols = (uint32_t)x1[k], ld = (uint32_t)x2[k], rd = (uint32_t)x3[k];
         uint32_t avail = ~(cols | ld | rd) & full;
@@ -554,7 +568,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
     } else if (act[k] == ACT_FINISH) {
       C.code[i] = 0;
     } else if (act[k] == ACT_JOIN) {
-      C.code[i] = cen[k] * ntt + tbase[k] + 1;   // local type 2: SUM / QSUM / MERGE
+      C.code[i] = cen[k] * ntt + (int32_t)(tp[k] & 0xFF) + 1;   // local type 2: SUM / QSUM / MERGE
       if (op[k] != OP_MS) {
         C.a0[i] = cb;
         if (op[k] == OP_Q) C.a1[i] = nk[k];
@@ -640,9 +654,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
             const int sseg = V.qs[q];
             const int32_t vb = L.seg_base[sseg];
             if (vb >= 0) {
-              const TreeStatic *ST = &C.ts[L.seg_slot[sseg]];
-              const int64_t c = ST->base + vb + V.qo[q];
-              C.code[c] = (L.seg_cen[sseg] + 1) * ntt + ST->tbase;
+              const int64_t c = ((int64_t)L.seg_tb[sseg] << 6) + vb + V.qo[q];
+              C.code[c] = (L.seg_cen[sseg] + 1) * ntt + (int32_t)(L.seg_tp[sseg] & 0xFF);
               C.a0[c] = V.qu[q];
             }
           }
@@ -659,10 +672,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
   phase_mark(C, L, 4);
   const int nseg = L.nseg;
   for (int s = tid; s < nseg; s += WG) {
-    const int32_t j = L.seg_join[s];
-    const int32_t v = L.seg_valid[s];
-    L.seg_join[s] = 0;
-    L.seg_valid[s] = 0;
+    const int32_t j = L.seg_jv[s] & 0xFFFF;
+    const int32_t v = (int32_t)((uint32_t)L.seg_jv[s] >> 16);
+    L.seg_jv[s] = 0;
     if (MULTI) {
       const int sl = L.seg_slot[s];
       const uint32_t beg = (s == 0) ? L.off0 : L.win[s - 1];
@@ -891,7 +903,12 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
       dst[k] = slot;
       C.wl_tree[k] = slot;
       C.wl_off[k] = off;
-      C.wl_start[k] = C.ts[slot].base + C.t_b[slot];
+      {
+        const TreeStatic *T = &C.ts[slot];
+        C.wl_b[k] = C.t_b[slot];
+        C.wl_tb[k] = (uint32_t)(T->base >> 6);
+        C.wl_tp[k] = (uint32_t)T->tbase | ((uint32_t)(T->kind == 4 ? T->p0 : 0) << 8);
+      }
       C.wl_cen[k] = C.t_cen[slot];
       if (C.st[slot].start_gepoch < 0) C.st[slot].start_gepoch = g;
       ++k;
@@ -928,8 +945,9 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
 }
 
 template <int WG>
-__device__ __forceinline__ void lds_init(Lds<WG> &L) {
-  for (int t = threadIdx.x; t < kChunk; t += WG) { L.seg_cnt[t] = 0; L.seg_join[t] = 0; L.seg_valid[t] = 0; }
+__device__ __forceinline__ void lds_init(const DevCtx &C, Lds<WG> &L) {
+  for (int t = threadIdx.x; t < kChunk; t += WG) { L.seg_cnt[t] = 0; L.seg_jv[t] = 0; }
+  if (threadIdx.x <= kMaxTypes) L.op_tab[threadIdx.x] = C.op_of_type[threadIdx.x];
   __syncthreads();
 }
 
@@ -943,7 +961,7 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG> L;
   __shared__ VL V;
-  lds_init<WG>(L);
+  lds_init<WG>(C, L);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int q = P.par ^ 1;   // the next epoch's counters
     C.plain->fj[q] = 0; C.plain->valid[q] = 0; C.plain->flags[q] = 0;
@@ -1035,7 +1053,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   __shared__ MapL M;
   __shared__ VL V;
   __shared__ uint32_t s_hdr[4];
-  lds_init<WG>(L);
+  lds_init<WG>(C, L);
   if (threadIdx.x == 0) L.tflag = 0;
   if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
   if (threadIdx.x == 0) L.tprof = realtime();

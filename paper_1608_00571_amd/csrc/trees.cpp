@@ -209,7 +209,9 @@ trees_status fail(trees_ctx *c, trees_status st, const std::string &m) {
       return fail(ctx, TREES_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Arenas start on 64-entry boundaries (work lists keep base / 64 in 32 bits).
 int64_t arena_alloc(trees_ctx *c, int64_t n) {
+  n = (n + 63) & ~(int64_t)63;
   for (auto it = c->freel.begin(); it != c->freel.end(); ++it) {
     if (it->second >= n) {
       int64_t s = it->first, len = it->second;
@@ -223,6 +225,7 @@ int64_t arena_alloc(trees_ctx *c, int64_t n) {
 }
 
 void arena_free(trees_ctx *c, int64_t s, int64_t n) {
+  n = (n + 63) & ~(int64_t)63;
   if (n <= 0) return;
   c->free_ent += n;
   auto it = c->freel.emplace(s, n).first;
@@ -582,7 +585,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
                o_hot = take(T * sizeof(TreeHot)), o_len = take(T * 4), o_cen = take(T * 4),
                o_b = take(T * 4), o_stk = take(T * kStackMax * sizeof(int4)),
                o_tr = trace ? take(T * kTraceMax * sizeof(TraceRec)) : 0, o_wt = take((T + 1) * 4),
-               o_wo = take((T + 1) * 4), o_ws = take((T + 1) * 8), o_wc = take((T + 1) * 4),
+               o_wo = take((T + 1) * 4), o_ws = take((T + 1) * 4), o_wc = take((T + 1) * 4),
+               o_wtb = take((T + 1) * 4), o_wtp = take((T + 1) * 4),
                o_dl = take(T * 4), o_lv = take(2 * T * 4), o_hdr = take(sizeof(SchedHdr)),
                o_pl = take(sizeof(PlainCounters)),
                o_adm = take(T * sizeof(Admit));
@@ -604,7 +608,9 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.trace = trace ? (TraceRec *)(b + o_tr) : nullptr;
   c->dc.wl_tree = (int32_t *)(b + o_wt);
   c->dc.wl_off = (uint32_t *)(b + o_wo);
-  c->dc.wl_start = (int64_t *)(b + o_ws);
+  c->dc.wl_b = (int32_t *)(b + o_ws);
+  c->dc.wl_tb = (uint32_t *)(b + o_wtb);
+  c->dc.wl_tp = (uint32_t *)(b + o_wtp);
   c->dc.wl_cen = (int32_t *)(b + o_wc);
   c->dc.done_list = (int32_t *)(b + o_dl);
   c->dc.live = (int32_t *)(b + o_lv);

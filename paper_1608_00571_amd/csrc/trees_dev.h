@@ -140,8 +140,10 @@ struct DevCtx {
   TraceRec *trace;                // [slot * kTraceMax + k] or null
   int32_t *wl_tree;               // work list: tree slot
   uint32_t *wl_off;               // exclusive prefix of range lengths (L+1 entries)
-  int64_t *wl_start;              // absolute task-vector index of the range start
+  int32_t *wl_b;                  // arena-relative range start
   int32_t *wl_cen;                // epoch number of the entry
+  uint32_t *wl_tb;                // arena base / 64 (arenas are 64-entry aligned)
+  uint32_t *wl_tp;                // the tree's first type id | program parameter << 8 (nqueens n)
   int32_t *done_list;             // trees finished in this epoch
   int32_t *live;                  // 2 x tmax: live tree slots in work-list order (double buffer)
   int32_t tmax;
