@@ -205,8 +205,10 @@ def bench_cfg2(args):
         # the msort epoch kernel: task-vector traffic + leaf sorts (8 B per key)
         "k_plain<MS>": dict(ms=kt[T.MSORT_U32][0], launches=kt[T.MSORT_U32][1],
                             bytes=(bm["tv"] + 8 * N) * args.steps, tv=bm["tv"] * args.steps),
-        # the map launches: every merge level reads and writes each key once
-        "k_map": dict(ms=kt[6][0], launches=kt[6][1], bytes=8 * merged * args.steps, tv=0),
+        # the map phase: the partition pass reads O(log) keys per tile boundary
+        # (not counted); the merge pass reads and writes each key once per level
+        f"k_map_part<{args.wg}>": dict(ms=kt[6][0], launches=kt[6][1], bytes=0, tv=0),
+        f"k_map_merge<{args.wg}>": dict(ms=kt[7][0], launches=kt[7][1], bytes=8 * merged * args.steps, tv=0),
     }
     dom = max(per, key=lambda k: per[k]["ms"])
     d = per[dom]
@@ -549,6 +551,28 @@ def bench_cfg5(args):
             "p50_ms": l80["p50_ms"], "p99_ms": l80["p99_ms"], "serving": out}
 
 
+def calib_copy(args):
+    """Counter calibration: a streaming elementwise kernel over int32 buffers
+    (reads and writes each byte once, like a copy) of --calib-mib MiB, run
+    --steps times.  A profiler's FETCH_SIZE / WRITE_SIZE per dispatch of it,
+    against the bytes printed here, gives the counters' scale factor."""
+    import torch
+    n = (args.calib_mib << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    assert int(dst[12345].item()) == ~12345
+    return {"calibration": "int32 bitwise_not", "read_bytes_per_dispatch": 4 * n,
+            "write_bytes_per_dispatch": 4 * n, "dispatches": args.steps + 1,
+            "GBps": round(8 * n / dt / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,12 +594,17 @@ def main():
     ap.add_argument("--plain-subset", type=int, default=4096)
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the graph / persistent / naive-merge runs of the same workload")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only the counter-calibration copy kernel")
+    ap.add_argument("--calib-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)
         sys.exit(2)
-    if args.config == 1:
+    if args.calib_copy:
+        line = calib_copy(args)
+    elif args.config == 1:
         line = bench_cfg1(args)
     elif args.config == 3:
         line = bench_cfg3(args)

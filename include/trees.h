@@ -184,8 +184,9 @@ trees_status trees_trace(trees_ctx *ctx, uint64_t tree, trees_epoch_rec *out, in
  * context's stream around each launch (needs TREES_F_PROFILE).  out[k] for
  * k = 1..5 accumulates the plain scheduler's per-epoch launches of program
  * kind k (trees_builtin); out[0] accumulates batched launches (one graph
- * replay or one persistent launch each); out[6] the plain scheduler's map
- * launches.  Copies min(n, 7) entries. */
+ * replay or one persistent launch each); out[6] and out[7] the plain
+ * scheduler's map phase (Section 4.2): its partition-pass and merge-pass
+ * launches.  Copies min(n, 8) entries. */
 typedef struct {
   double ms;           /* summed launch durations */
   uint64_t launches;   /* number of timed launches */

@@ -298,10 +298,11 @@ class Context:
 
     def kernel_times(self):
         """{kind: (ms, launches)}: HIP-event timed epoch launches; kind 0 =
-        batched launches, kind 6 = the plain scheduler's map launches."""
-        arr = (_KTime * 7)()
-        self._check(lib().trees_kernel_times(self.h, arr, 7), "kernel_times")
-        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(7)}
+        batched launches, kinds 6 and 7 = the plain scheduler's map phase
+        (partition pass, merge pass)."""
+        arr = (_KTime * 8)()
+        self._check(lib().trees_kernel_times(self.h, arr, 8), "kernel_times")
+        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(8)}
 
     def epoch_times(self) -> np.ndarray:
         """Per-epoch device-clock durations (us) of the last batched run."""

@@ -1240,7 +1240,7 @@ hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t ne
 // Map launches: the partition pass then the merge pass.  grid_part and
 // grid_merge are work-group counts (both passes loop over their work).
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
-                      hipStream_t s) {
+                      hipStream_t s, hipEvent_t between) {
   const void *fp = nullptr, *fm = nullptr;
   switch (wg) {
     case 256: fp = (const void *)&k_map_part<256>; fm = (const void *)&k_map_merge<256>; break;
@@ -1254,6 +1254,7 @@ hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int 
   void *args[] = {&c, &j, &f};
   hipError_t e = hipLaunchKernel(fp, dim3(grid_part), dim3(wg), args, 0, s);
   if (e != hipSuccess) return e;
+  if (between && (e = hipEventRecord(between, s)) != hipSuccess) return e;
   return hipLaunchKernel(fm, dim3(grid_merge), dim3(wg), args, 0, s);
 }
 

@@ -20,7 +20,7 @@ namespace trees {
 hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s);
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s);
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
-                      hipStream_t s);
+                      hipStream_t s, hipEvent_t between);
 int coresident_blocks_per_cu(int wg, uint32_t need);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
@@ -186,9 +186,9 @@ struct trees_ctx {
   int ncu = 0;
   int last_grid = 0, last_api_bpc = 0;
   bool profile = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
   trees_ktime ktime[6] = {};
-  trees_ktime mtime = {};     // map launches
+  trees_ktime mtime[2] = {};  // map launches: partition pass, merge pass
   double clock_hz = 1e8;
   bool running = false;
   std::string err;
@@ -338,14 +338,18 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       const int gm = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
       const int gp = (int)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 1 + c->wg / 64 - 1) / (c->wg / 64), cap));
       if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-      HIPCHK(c, launch_map(c->dc, c->wg, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream));
+      HIPCHK(c, launch_map(c->dc, c->wg, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream,
+                           c->profile ? c->evm : nullptr));
       if (c->profile) {
         HIPCHK(c, hipEventRecord(c->ev1, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        float ms = 0;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        c->mtime.ms += ms;
-        c->mtime.launches += 1;
+        float ms0 = 0, ms1 = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms0, c->ev0, c->evm));
+        HIPCHK(c, hipEventElapsedTime(&ms1, c->evm, c->ev1));
+        c->mtime[0].ms += ms0;
+        c->mtime[0].launches += 1;
+        c->mtime[1].ms += ms1;
+        c->mtime[1].launches += 1;
       }
     }
     if (trace && st.epochs < kTraceMax)
@@ -460,7 +464,7 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     for (int k = 0; k < c->chunk; ++k) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
       if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
-        e = launch_map(c->dc, c->wg, 0, 1, grid, grid, c->stream);
+        e = launch_map(c->dc, c->wg, 0, 1, grid, grid, c->stream, nullptr);
       if (e != hipSuccess) {
         hipGraph_t g;
         (void)hipStreamEndCapture(c->stream, &g);
@@ -645,7 +649,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
     return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   c->dc.abort_flag = dev_abort;
   c->profile = (cfg->flags & TREES_F_PROFILE) != 0;
-  if (c->profile && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess))
+  if (c->profile && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+                     hipEventCreate(&c->evm) != hipSuccess))
     return bail(TREES_E_DEVICE, "hipEventCreate failed");
   c->trees.resize(c->tmax);
   *out = c;
@@ -667,6 +672,7 @@ void trees_destroy(trees_ctx *c) {
   if (c->abort_flag) (void)hipHostFree(c->abort_flag);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->evm) (void)hipEventDestroy(c->evm);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -921,7 +927,8 @@ trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
   for (int k = 0; k < n && k < 6; ++k) out[k] = c->ktime[k];
-  if (n > 6) out[6] = c->mtime;
+  if (n > 6) out[6] = c->mtime[0];
+  if (n > 7) out[7] = c->mtime[1];
   return TREES_OK;
 }
 
