@@ -30,6 +30,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel as rocprofv3 counted them (FETCH_SIZE and
+# WRITE_SIZE, each in its own run, scaled by what the same counters read for
+# `bench.py --calib-copy`), for the kernel sources with the given digest.  A
+# source change makes the figure stale, and it is then reported as null.
+MEASURED_TRAFFIC = {}
+
+
+def src_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1608_00571_amd", "csrc")
+    for f in ("epoch.hip", "bodies.h", "prims.h", "trees_dev.h"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, alg_bytes_per_launch: int):
+    m = MEASURED_TRAFFIC.get(kernel)
+    if not m or m["src"] != src_digest():
+        return None
+    return m["fetch_bytes"] + m["write_bytes"]
+
 
 # ---------------------------------------------------------------------------
 # Algorithmic bytes (task-vector fields each task type must touch, reads +
@@ -129,8 +152,10 @@ def cpu_baseline_cfg2(sample_keys_log2: int = 24):
             "sample": f"epoch emulator: fib(32) + msort 2^{sample_keys_log2} (full step, {dt:.1f} s)"}
 
 
-def run_cfg2(args, sched, steps, warmup, nomap=False, key_bufs=None, keys_np=None):
-    """Time `steps` steps of fib(32) + msort under one scheduler."""
+def run_cfg2(args, sched, steps, warmup, nomap=False, key_bufs=None, keys_np=None, timed_kinds=()):
+    """Time `steps` steps of fib(32) + msort under one scheduler.  Launches
+    of the kernel_times() kinds in `timed_kinds` carry HIP events (None:
+    every launch)."""
     import numpy as np
     import torch
 
@@ -140,6 +165,8 @@ def run_cfg2(args, sched, steps, warmup, nomap=False, key_bufs=None, keys_np=Non
     tmp = torch.empty_like(key_bufs[0])
     arena = (T.tv_bound(T.FIB_I64, [32]) + T.tv_bound(T.MSORT_U32, [N]) + 1024) * T.BYTES_PER_ENTRY
     ctx = T.Context(arena, sched=sched, wg=args.wg, profile=True, nomap=nomap, max_trees=8)
+    if timed_kinds is not None:
+        ctx.profile_mask(timed_kinds)
     pf = ctx.register(T.FIB_I64)
     pm = ctx.register(T.MSORT_U32)
     base = key_bufs[-1]
@@ -188,38 +215,47 @@ def bench_cfg2(args):
     key_bufs = [base.clone() for _ in range(nbuf)] + [base]
     torch.cuda.synchronize()
 
-    r = run_cfg2(args, args.sched, args.steps, args.warmup, key_bufs=key_bufs, keys_np=keys_np)
-    dt, outs, kt = r["dt"], r["outs"], r["kt"]
+    # Breakdown: one step with every launch timed (HIP events cost host time
+    # per launch, so this step is not the throughput measurement).
+    bd = run_cfg2(args, args.sched, 1, args.warmup, key_bufs=key_bufs, keys_np=keys_np, timed_kinds=None)
+    kt = bd["kt"]
+    _, sf, sm, _ = bd["outs"][-1]
+    bf = fib_bytes(32, sf.launched, sf.tasks)
+    bm = msort_bytes(N, sm.launched, sm.tasks)
+    internal, leaves, merged = msort_counts(N)
+    kinds = {"k_plain<FIB>": T.FIB_I64, "k_plain<MS>": T.MSORT_U32,
+             f"k_map_part<{args.wg}>": 6, f"k_map_merge<{args.wg}>": 7}
+    per_step_bytes = {
+        "k_plain<FIB>": (bf["tv"], bf["tv"]),
+        # the msort epoch kernel: task-vector traffic + leaf sorts (8 B per key)
+        "k_plain<MS>": (bm["tv"] + 8 * N, bm["tv"]),
+        # the partition pass reads O(log) keys per tile boundary (not counted)
+        f"k_map_part<{args.wg}>": (0, 0),
+        # the merge pass reads and writes each key once per merge level
+        f"k_map_merge<{args.wg}>": (8 * merged, 0),
+    }
+    per = {k: dict(ms=kt[kinds[k]][0], launches=kt[kinds[k]][1], bytes=per_step_bytes[k][0],
+                   tv=per_step_bytes[k][1]) for k in kinds}
+    dom = max(per, key=lambda k: per[k]["ms"])
+
+    # The measurement: only the dominant kernel's launches carry events.
+    r = run_cfg2(args, args.sched, args.steps, args.warmup, key_bufs=key_bufs, keys_np=keys_np,
+                 timed_kinds=[kinds[dom]])
+    dt, outs, ktl = r["dt"], r["outs"], r["kt"]
     vf, sf, sm, rs = outs[-1]
     tasks = sf.tasks + sm.tasks
     epochs = sf.epochs + sm.epochs
     ms_step = dt * 1e3 / args.steps
-
-    # roofline of the dominant kernel (HIP-event time of its launches)
-    bf = fib_bytes(32, sf.launched, sf.tasks)
-    bm = msort_bytes(N, sm.launched, sm.tasks)
-    internal, leaves, merged = msort_counts(N)
-    per = {
-        "k_plain<FIB>": dict(ms=kt[T.FIB_I64][0], launches=kt[T.FIB_I64][1],
-                             bytes=bf["tv"] * args.steps, tv=bf["tv"] * args.steps),
-        # the msort epoch kernel: task-vector traffic + leaf sorts (8 B per key)
-        "k_plain<MS>": dict(ms=kt[T.MSORT_U32][0], launches=kt[T.MSORT_U32][1],
-                            bytes=(bm["tv"] + 8 * N) * args.steps, tv=bm["tv"] * args.steps),
-        # the map phase: the partition pass reads O(log) keys per tile boundary
-        # (not counted); the merge pass reads and writes each key once per level
-        f"k_map_part<{args.wg}>": dict(ms=kt[6][0], launches=kt[6][1], bytes=0, tv=0),
-        f"k_map_merge<{args.wg}>": dict(ms=kt[7][0], launches=kt[7][1], bytes=8 * merged * args.steps, tv=0),
-    }
-    dom = max(per, key=lambda k: per[k]["ms"])
-    d = per[dom]
+    d = dict(ms=ktl[kinds[dom]][0], launches=ktl[kinds[dom]][1], bytes=per[dom]["bytes"] * args.steps)
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic_for(dom, d["launches"] and
+                                                                              d["bytes"] // d["launches"]),
             "kernel": dom, "launches": d["launches"],
             "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 3),
             "algorithmic_bytes_per_launch": int(d["bytes"] / max(1, d["launches"]))}
-    kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 3),
-                   "launches_per_step": v["launches"] // args.steps,
+    kernels = {k: {"ms_per_step": round(v["ms"], 3),
+                   "launches_per_step": v["launches"],
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2) if v["ms"] else None,
                    "tv_GBps": round(v["tv"] / (v["ms"] * 1e-3) / 1e9, 2) if v["ms"] else None}
                for k, v in per.items()}

@@ -193,6 +193,13 @@ typedef struct {
 } trees_ktime;
 trees_status trees_kernel_times(trees_ctx *ctx, trees_ktime *out, int32_t n);
 
+/* Choose which launches trees_kernel_times covers: bit k set = time the
+ * launches that accumulate in out[k] (all eight by default).  Each timed
+ * launch carries two HIP events, which cost host time per launch, so a
+ * throughput measurement times only the launches it reports.  STATE if the
+ * context was created without TREES_F_PROFILE. */
+trees_status trees_profile_mask(trees_ctx *ctx, uint32_t mask);
+
 /* Device-clock duration of each epoch of the last GRAPH or PERSISTENT run,
  * in microseconds, measured from the device's constant-rate clock where the
  * last work-group of each epoch builds the next work list (it includes the

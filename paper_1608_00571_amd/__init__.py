@@ -108,6 +108,8 @@ def lib():
         L.trees_set_schedule.argtypes = [vp, i32, i32, i32, i32]
         L.trees_tv_bound.restype = i32
         L.trees_tv_bound.argtypes = [i32, ctypes.POINTER(i64), i32, ctypes.POINTER(i64)]
+        L.trees_profile_mask.restype = i32
+        L.trees_profile_mask.argtypes = [vp, ctypes.c_uint32]
         L.trees_kernel_times.restype = i32
         L.trees_kernel_times.argtypes = [vp, ctypes.POINTER(_KTime), i32]
         L.trees_epoch_times.restype = i32
@@ -125,7 +127,7 @@ def lib():
 EXPORTED = ("trees_create", "trees_destroy", "trees_last_error", "trees_register_program",
             "trees_submit", "trees_run", "trees_results", "trees_trace", "trees_abort",
             "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees",
-            "trees_kernel_times", "trees_epoch_times", "trees_debug_phases")
+            "trees_kernel_times", "trees_profile_mask", "trees_epoch_times", "trees_debug_phases")
 
 
 @dataclass
@@ -295,6 +297,13 @@ class Context:
         n = ctypes.c_int32(0)
         self._check(lib().trees_trace(self.h, tree, out.ctypes.data, 256, ctypes.byref(n)), "trace")
         return out[: min(n.value, 256)].copy()
+
+    def profile_mask(self, kinds):
+        """Time only the launches of the given kernel_times() kinds."""
+        m = 0
+        for k in kinds:
+            m |= 1 << k
+        self._check(lib().trees_profile_mask(self.h, m), "profile_mask")
 
     def kernel_times(self):
         """{kind: (ms, launches)}: HIP-event timed epoch launches; kind 0 =

@@ -25,6 +25,7 @@
 // scan.  The plain form leaves Phases 1 and 3 to the host, one launch per
 // epoch, as the paper does.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <type_traits>
@@ -965,23 +966,48 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int q = P.par ^ 1;   // the next epoch's counters
     C.plain->fj[q] = 0; C.plain->valid[q] = 0; C.plain->flags[q] = 0;
-    C.plain->map[q] = 0;
+    C.plain->map[q] = 0; C.plain->ticket[q] = 0;
   }
   const uint32_t S = (uint32_t)(P.e - P.b);
   run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P);
+  // Publish the epoch's counters to the host.  Every wavefront's counter
+  // atomics have been performed before its work-group takes a ticket; the
+  // last ticket reads the totals with atomics (performed after every other
+  // work-group's) and stores them into the mirror, `seq` after the rest has
+  // landed.  Only counters cross here -- the task vector reaches the next
+  // launch through the kernel boundary -- so no L2 write-back is needed.
+  wait_vmem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = add_agent(&C.plain->ticket[P.par], 1u);
+    if (t == gridDim.x - 1) {
+      PlainMirror *M = C.mirror;
+      const uint64_t fj = add_agent(&C.plain->fj[P.par], (uint64_t)0);
+      const uint64_t mp = add_agent(&C.plain->map[P.par], (uint64_t)0);
+      const int32_t va = add_agent(&C.plain->valid[P.par], 0);
+      const int32_t fl = or_agent(&C.plain->flags[P.par], 0);
+      __hip_atomic_store(&M->fj, fj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&M->map, mp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&M->valid, va, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&M->flags, fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      wait_vmem();
+      __hip_atomic_store(&M->seq, P.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 // Grid barrier between epochs (Tenet 1: one arrival per work-group).  Every
-// wavefront releases its own task-vector and state writes (a fence by one
-// thread does not cover the other wavefronts' outstanding stores), then one
-// thread arrives.  The last arriver optionally runs the work-list scan and
-// opens the barrier.  wait = false (graph form): the others return at once,
-// the kernel boundary is their barrier.  Returns false if this work-group
-// gave up waiting after the spin limit.
+// wavefront waits until its task-vector and state stores have reached the
+// XCD's L2; then one thread writes the L2 back (a release) and arrives.  The
+// last arriver optionally runs the work-list scan and opens the barrier.
+// Leaving, one thread invalidates the CU's and XCD's caches (an acquire).
+// wait = false (graph form): the others return at once, the kernel
+// boundary is their barrier.  Returns false if this work-group gave up
+// waiting after the spin limit.
 template <int WG>
 __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool wait) {
   SchedHdr *H = C.hdr;
-  fence_release();
+  wait_vmem();
   __syncthreads();
   if (threadIdx.x == 0) {
     // two-level arrival: work-groups arrive at their group's counter (group
@@ -1005,9 +1031,10 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
   }
   __syncthreads();
   if (L.flag) {
-    fence_acquire();
+    if (threadIdx.x == 0) fence_acquire();
+    __syncthreads();
     if (with_scan) schedule_scan<WG>(C, L, true);
-    fence_release();
+    wait_vmem();
     __syncthreads();
     if (threadIdx.x == 0) {
       st_agent(&H->arrive, 0u);
@@ -1031,7 +1058,7 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
     __syncthreads();
     if (L.tflag) return false;
   }
-  fence_acquire();
+  if (threadIdx.x == 0) fence_acquire();
   __syncthreads();
   return true;
 }
@@ -1226,21 +1253,25 @@ const void *kernel_epochs(int wg, uint32_t need) {
   }
 }
 
-hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s) {
+// ev0 / ev1 (may be null): HIP events that take the kernel's start and end.
+hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   const void *fn = kernel_plain(wg, need);
   if (!fn) return hipErrorInvalidValue;
   const uint32_t S = (uint32_t)(P.e - P.b);
+  if (S == 0) return hipErrorInvalidValue;
   dim3 grid((S + kChunk - 1) / kChunk), block(wg);
   DevCtx c = C;
   PlainArgs p = P;
   void *args[] = {&c, &p};
-  return hipLaunchKernel(fn, grid, block, args, 0, s);
+  return hipExtLaunchKernel(fn, grid, block, args, 0, s, ev0, ev1, 0);
 }
 
 // Map launches: the partition pass then the merge pass.  grid_part and
 // grid_merge are work-group counts (both passes loop over their work).
+// ev (may be null): four HIP events, the start and end of each pass.
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
-                      hipStream_t s, hipEvent_t between) {
+                      hipStream_t s, const hipEvent_t *ev) {
   const void *fp = nullptr, *fm = nullptr;
   switch (wg) {
     case 256: fp = (const void *)&k_map_part<256>; fm = (const void *)&k_map_merge<256>; break;
@@ -1252,10 +1283,11 @@ hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int 
   uint32_t j = jobs;
   int32_t f = from_hdr;
   void *args[] = {&c, &j, &f};
-  hipError_t e = hipLaunchKernel(fp, dim3(grid_part), dim3(wg), args, 0, s);
+  hipError_t e = hipExtLaunchKernel(fp, dim3(grid_part), dim3(wg), args, 0, s, ev ? ev[0] : nullptr,
+                                    ev ? ev[1] : nullptr, 0);
   if (e != hipSuccess) return e;
-  if (between && (e = hipEventRecord(between, s)) != hipSuccess) return e;
-  return hipLaunchKernel(fm, dim3(grid_merge), dim3(wg), args, 0, s);
+  return hipExtLaunchKernel(fm, dim3(grid_merge), dim3(wg), args, 0, s, ev ? ev[2] : nullptr,
+                            ev ? ev[3] : nullptr, 0);
 }
 
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s) {

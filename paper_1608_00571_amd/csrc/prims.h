@@ -120,8 +120,15 @@ __device__ __forceinline__ T or_agent(T *p, T v) {
   return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Release / acquire at agent scope: paid once per work-group per epoch, at
-// the epoch barrier (Tenet 1), never per task.
+// Waits until this wavefront's vector memory operations (loads, stores,
+// atomics) have completed: s_waitcnt vmcnt(0), leaving the other counters.
+// Stores are then in the XCD's L2 and atomics performed, with no L2 write-back.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Release / acquire at agent scope.  On this chip a release writes back the
+// XCD's L2 and an acquire invalidates it (the L2s of the 8 XCDs are not
+// coherent with each other), so they are paid once per work-group per epoch
+// at the epoch barrier (Tenet 1), never per task or per wavefront.
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 

@@ -17,10 +17,11 @@
 #include "trees_dev.h"
 
 namespace trees {
-hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s);
+hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s);
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
-                      hipStream_t s, hipEvent_t between);
+                      hipStream_t s, const hipEvent_t *ev);
 int coresident_blocks_per_cu(int wg, uint32_t need);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
@@ -172,7 +173,8 @@ struct trees_ctx {
   std::vector<DepthInit> depth_inits;
   Admit *adm_host = nullptr;       // pinned staging
   Admit *adm_dev = nullptr;
-  PlainCounters *plain_host = nullptr;
+  PlainMirror *mirror = nullptr;   // host-mapped, written by each plain epoch's last work-group
+  uint32_t plain_seq = 0;
   SchedHdr *hdr_host = nullptr;
   TreeState *st_host = nullptr;
   int32_t *abort_flag = nullptr;
@@ -186,10 +188,15 @@ struct trees_ctx {
   int ncu = 0;
   int last_grid = 0, last_api_bpc = 0;
   bool profile = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
-  trees_ktime ktime[6] = {};
-  trees_ktime mtime[2] = {};  // map launches: partition pass, merge pass
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // plain-scheduler launch timing: event pairs resolved after the tree's
+  // last epoch, so timing adds no synchronisation per epoch
+  std::vector<hipEvent_t> evpool;
+  std::vector<std::pair<int, size_t>> evpend;   // (ktime slot, first event of the pair)
+  trees_ktime ktime[8] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes
+  uint32_t prof_mask = 0xFFu;  // which of the slots above are timed
   double clock_hz = 1e8;
+  double timeout_s = 60.0;   // host and device waits give up after this long
   bool running = false;
   std::string err;
   std::mutex mu;
@@ -207,6 +214,12 @@ trees_status fail(trees_ctx *c, trees_status st, const std::string &m) {
     hipError_t e_ = (call);                                                           \
     if (e_ != hipSuccess)                                                             \
       return fail(ctx, TREES_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(call)                         \
+  do {                                    \
+    const trees_status s_ = (call);       \
+    if (s_ != TREES_OK) return s_;        \
   } while (0)
 
 // Arenas start on 64-entry boundaries (work lists keep base / 64 in 32 bits).
@@ -288,6 +301,55 @@ trees_status sync_states(trees_ctx *c) {
   return TREES_OK;
 }
 
+// Whether launches of ktime slot `slot` are timed.
+bool timed(const trees_ctx *c, int slot) { return c->profile && ((c->prof_mask >> slot) & 1u); }
+
+// Two timing events for a launch whose duration accumulates in ktime[slot].
+trees_status take_events(trees_ctx *c, int slot, hipEvent_t *e0, hipEvent_t *e1) {
+  const size_t i = c->evpend.size() * 2;
+  while (c->evpool.size() < i + 2) {
+    hipEvent_t e = nullptr;
+    HIPCHK(c, hipEventCreate(&e));
+    c->evpool.push_back(e);
+  }
+  c->evpend.emplace_back(slot, i);
+  *e0 = c->evpool[i];
+  *e1 = c->evpool[i + 1];
+  return TREES_OK;
+}
+
+// After the stream has drained: add up the pending launch durations.
+trees_status resolve_events(trees_ctx *c) {
+  for (const auto &p : c->evpend) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->evpool[p.second], c->evpool[p.second + 1]));
+    c->ktime[p.first].ms += ms;
+    c->ktime[p.first].launches += 1;
+  }
+  c->evpend.clear();
+  return TREES_OK;
+}
+
+// Wait until the plain epoch launch `seq` has published its counters in the
+// mirror.  Polls host memory; checks the stream for errors now and then.
+trees_status wait_mirror(trees_ctx *c, uint32_t seq) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 1;; ++spin) {
+    if (__atomic_load_n(&c->mirror->seq, __ATOMIC_ACQUIRE) == seq) return TREES_OK;
+    if ((spin & 1023) == 0) {
+      const hipError_t q = hipStreamQuery(c->stream);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&c->mirror->seq, __ATOMIC_ACQUIRE) == seq) return TREES_OK;
+        return fail(c, TREES_E_DEVICE, "epoch launch ended without publishing its counters");
+      }
+      if (q != hipErrorNotReady) return fail(c, TREES_E_DEVICE, std::string("epoch launch: ") + hipGetErrorString(q));
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el > c->timeout_s) return fail(c, TREES_E_DEVICE, "epoch launch did not finish within the time limit");
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // PLAIN: the paper's host-driven loop, one tree at a time.
 // ---------------------------------------------------------------------------
@@ -312,23 +374,17 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     // Phase 1 happened when the range was popped; launch Phase 2.
     PlainArgs P{slot, st.cen, st.b, st.e, st.old, par};
     if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
-    if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream));
-    if (c->profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->plain_host, c->dc.plain, sizeof(PlainCounters), hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->profile) {
-      float ms = 0;
-      HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-      c->ktime[t.kind].ms += ms;
-      c->ktime[t.kind].launches += 1;
-    }
-    const int32_t forks = (int32_t)(uint32_t)c->plain_host->fj[par];
-    const int32_t joins = (int32_t)(c->plain_host->fj[par] >> 32);
-    const int32_t valid = c->plain_host->valid[par];
-    const int32_t flags = c->plain_host->flags[par];
-    const uint64_t mc = c->plain_host->map[par];
+    P.seq = ++c->plain_seq ? c->plain_seq : ++c->plain_seq;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed(c, t.kind)) TRY(take_events(c, t.kind, &e0, &e1));
+    HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream, e0, e1));
+    TRY(wait_mirror(c, P.seq));
+    const PlainMirror mir = *c->mirror;
+    const int32_t forks = (int32_t)(uint32_t)mir.fj;
+    const int32_t joins = (int32_t)(mir.fj >> 32);
+    const int32_t valid = mir.valid;
+    const int32_t flags = mir.flags;
+    const uint64_t mc = mir.map;
     const int32_t nfc = st.old + forks;
     if (mc >> kMapShift) {
       // map phase: the merges registered by this epoch, before the next one
@@ -337,20 +393,11 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       const uint64_t cap = (uint64_t)c->ncu * 16;
       const int gm = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
       const int gp = (int)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 1 + c->wg / 64 - 1) / (c->wg / 64), cap));
-      if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+      hipEvent_t ev[4] = {};
+      if (timed(c, 6)) TRY(take_events(c, 6, &ev[0], &ev[1]));
+      if (timed(c, 7)) TRY(take_events(c, 7, &ev[2], &ev[3]));
       HIPCHK(c, launch_map(c->dc, c->wg, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream,
-                           c->profile ? c->evm : nullptr));
-      if (c->profile) {
-        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        float ms0 = 0, ms1 = 0;
-        HIPCHK(c, hipEventElapsedTime(&ms0, c->ev0, c->evm));
-        HIPCHK(c, hipEventElapsedTime(&ms1, c->evm, c->ev1));
-        c->mtime[0].ms += ms0;
-        c->mtime[0].launches += 1;
-        c->mtime[1].ms += ms1;
-        c->mtime[1].launches += 1;
-      }
+                           ev));
     }
     if (trace && st.epochs < kTraceMax)
       t.trace.push_back(TraceRec{st.epochs, st.cen, st.b, st.e, st.e - st.b, valid, forks, joins, nfc});
@@ -399,6 +446,7 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
   HIPCHK(c, hipMemcpyAsync(c->dc.t_cen + slot, &lcb[1], 4, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->dc.t_b + slot, &lcb[2], 4, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  TRY(resolve_events(c));
   t.st = st;
   if (done) t.hstatus = H_DONE;
   return TREES_OK;
@@ -479,12 +527,12 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
   s = read_hdr(c);
   if (s) return s;
   while (!c->hdr_host->stop) {
-    if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    if (timed(c, 0)) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-    if (c->profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    if (timed(c, 0)) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     s = read_hdr(c);
     if (s) return s;
-    if (c->profile) {
+    if (timed(c, 0)) {
       float ms = 0;
       HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
       c->ktime[0].ms += ms;
@@ -500,12 +548,12 @@ trees_status run_persistent(trees_ctx *c, int64_t max_epochs) {
   const uint32_t need = ops_needed(c);
   const int grid = grid_size(c, need, true);
   c->last_grid = grid;
-  if (c->profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  if (timed(c, 0)) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   HIPCHK(c, launch_epochs(c->dc, c->wg, need, grid, 1, c->stream));
-  if (c->profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  if (timed(c, 0)) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   s = read_hdr(c);
   if (s) return s;
-  if (c->profile) {
+  if (timed(c, 0)) {
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->ktime[0].ms += ms;
@@ -635,9 +683,11 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.debug = (cfg->flags & TREES_F_DEBUG) ? 1 : 0;
   const double to = cfg->timeout_s > 0 ? cfg->timeout_s : 60.0;
   c->dc.timeout_ticks = (int64_t)(to * c->clock_hz);
+  c->timeout_s = to;
   // pinned host memory
   if (hipHostMalloc((void **)&c->adm_host, T * sizeof(Admit), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->plain_host, sizeof(PlainCounters), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->mirror, sizeof(PlainMirror), hipHostMallocCoherent | hipHostMallocMapped) !=
+          hipSuccess ||
       hipHostMalloc((void **)&c->hdr_host, sizeof(SchedHdr), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->st_host, T * sizeof(TreeState), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->r_host, 64, hipHostMallocDefault) != hipSuccess ||
@@ -648,9 +698,11 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   if (hipHostGetDevicePointer((void **)&dev_abort, c->abort_flag, 0) != hipSuccess)
     return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   c->dc.abort_flag = dev_abort;
+  memset(c->mirror, 0, sizeof(PlainMirror));
+  if (hipHostGetDevicePointer((void **)&c->dc.mirror, c->mirror, 0) != hipSuccess)
+    return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   c->profile = (cfg->flags & TREES_F_PROFILE) != 0;
-  if (c->profile && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-                     hipEventCreate(&c->evm) != hipSuccess))
+  if (c->profile && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess))
     return bail(TREES_E_DEVICE, "hipEventCreate failed");
   c->trees.resize(c->tmax);
   *out = c;
@@ -665,14 +717,14 @@ void trees_destroy(trees_ctx *c) {
   if (c->own_arena && c->arena) (void)hipFree(c->arena);
   if (c->ctl) (void)hipFree(c->ctl);
   if (c->adm_host) (void)hipHostFree(c->adm_host);
-  if (c->plain_host) (void)hipHostFree(c->plain_host);
+  if (c->mirror) (void)hipHostFree(c->mirror);
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   if (c->hdr_host) (void)hipHostFree(c->hdr_host);
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->r_host) (void)hipHostFree(c->r_host);
   if (c->abort_flag) (void)hipHostFree(c->abort_flag);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
-  if (c->evm) (void)hipEventDestroy(c->evm);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -922,13 +974,20 @@ trees_status trees_tv_bound(int32_t kind, const int64_t *args, int32_t nargs, in
   return tv_bound(kind, args, nargs, entries, nullptr);
 }
 
+trees_status trees_profile_mask(trees_ctx *c, uint32_t mask) {
+  if (!c) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
+  c->prof_mask = mask & 0xFFu;
+  return TREES_OK;
+}
+
 trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
   if (!c || !out) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
   for (int k = 0; k < n && k < 6; ++k) out[k] = c->ktime[k];
-  if (n > 6) out[6] = c->mtime[0];
-  if (n > 7) out[7] = c->mtime[1];
+  for (int k = 6; k < n && k < 8; ++k) out[k] = c->ktime[k];
   return TREES_OK;
 }
 

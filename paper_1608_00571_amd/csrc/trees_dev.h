@@ -126,6 +126,19 @@ struct PlainCounters {
   int32_t valid[2];
   int32_t flags[2];
   uint64_t map[2];
+  uint32_t ticket[2];  // work-groups of the epoch that have finished
+};
+
+// Host-visible copy of one epoch's counters (host-mapped, coherent memory),
+// written by the epoch's last work-group; `seq` is written last and names
+// the launch, so the host can wait on it instead of on the stream.
+struct PlainMirror {
+  uint64_t fj;
+  uint64_t map;
+  int32_t valid;
+  int32_t flags;
+  uint32_t seq;
+  uint32_t pad;
 };
 
 // Everything a kernel needs, passed by value.
@@ -150,6 +163,7 @@ struct DevCtx {
   int32_t pad3;
   SchedHdr *hdr;
   PlainCounters *plain;
+  PlainMirror *mirror;            // device address of the host-mapped mirror
   const volatile int32_t *abort_flag;  // host-pinned, set by trees_abort
   int32_t ntt;
   int32_t trace_on;
@@ -177,6 +191,7 @@ struct Admit {
 // Arguments of one plain-scheduler epoch (one tree, host-driven).
 struct PlainArgs {
   int32_t slot, cen, b, e, nfc0, par;
+  uint32_t seq;   // launch number published in the mirror
 };
 
 }  // namespace trees
