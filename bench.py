@@ -224,15 +224,15 @@ def bench_cfg2(args):
     bm = msort_bytes(N, sm.launched, sm.tasks)
     internal, leaves, merged = msort_counts(N)
     kinds = {"k_plain<FIB>": T.FIB_I64, "k_plain<MS>": T.MSORT_U32,
-             f"k_map_part<{args.wg}>": 6, f"k_map_merge<{args.wg}>": 7}
+             "k_map_part<1024>": 6, "k_map_merge<1024>": 7}
     per_step_bytes = {
         "k_plain<FIB>": (bf["tv"], bf["tv"]),
         # the msort epoch kernel: task-vector traffic + leaf sorts (8 B per key)
         "k_plain<MS>": (bm["tv"] + 8 * N, bm["tv"]),
         # the partition pass reads O(log) keys per tile boundary (not counted)
-        f"k_map_part<{args.wg}>": (0, 0),
+        "k_map_part<1024>": (0, 0),
         # the merge pass reads and writes each key once per merge level
-        f"k_map_merge<{args.wg}>": (8 * merged, 0),
+        "k_map_merge<1024>": (8 * merged, 0),
     }
     per = {k: dict(ms=kt[kinds[k]][0], launches=kt[kinds[k]][1], bytes=per_step_bytes[k][0],
                    tv=per_step_bytes[k][1]) for k in kinds}
@@ -616,7 +616,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--sched", default="plain")
-    ap.add_argument("--wg", type=int, default=256)
+    ap.add_argument("--wg", type=int, default=0,
+                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler, 256 batched)")
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--trees", type=int, default=4096)
@@ -634,6 +635,8 @@ def main():
                     help="run only the counter-calibration copy kernel")
     ap.add_argument("--calib-mib", type=int, default=1024)
     args = ap.parse_args()
+    if args.wg == 0:
+        args.wg = 1024 if args.config in (1, 2) and args.sched == "plain" else 256
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)

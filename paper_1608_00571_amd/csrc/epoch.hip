@@ -45,7 +45,7 @@ enum : int { ACT_NONE = 0, ACT_EMIT = 1, ACT_JOIN = 2, ACT_FINISH = 3 };
 // per segment (a run of the chunk's items that belong to one tree).
 constexpr int kChunk = 1024;
 
-template <int WG>
+template <int WG, int NS = kChunk>   // NS: segments a chunk can touch (1 in the plain form)
 struct Lds {
   int32_t kfirst;          // first work-list entry of the chunk
   int32_t nseg;            // entries (trees) the chunk touches
@@ -59,15 +59,15 @@ struct Lds {
   int64_t tprof;           // debug: clock at the last phase boundary
   int64_t prof[8];         // debug: time per phase
   uint8_t op_tab[kMaxTypes + 1];   // global type id -> operation
-  uint32_t win[kChunk];    // wl_off[kfirst + 1 + t]
-  int32_t seg_slot[kChunk];   // tree slot of segment s
-  int32_t seg_cen[kChunk];    // its epoch number
-  int32_t seg_b[kChunk];      // arena-relative start of its range
-  uint32_t seg_tb[kChunk];    // its arena base / 64
-  uint32_t seg_tp[kChunk];    // first type id | parameter << 8
-  int32_t seg_cnt[kChunk];    // children requested per segment (LDS atomics)
-  int32_t seg_base[kChunk];   // arena-relative first child per segment (-1: overflow)
-  int32_t seg_jv[kChunk];     // joins (low 16 bits) | valid tasks (high 16 bits) per segment
+  uint32_t win[NS];        // wl_off[kfirst + 1 + t]
+  int32_t seg_slot[NS];   // tree slot of segment s
+  int32_t seg_cen[NS];    // its epoch number
+  int32_t seg_b[NS];      // arena-relative start of its range
+  uint32_t seg_tb[NS];    // its arena base / 64
+  uint32_t seg_tp[NS];    // first type id | parameter << 8
+  int32_t seg_cnt[NS];    // children requested per segment (LDS atomics)
+  int32_t seg_base[NS];   // arena-relative first child per segment (-1: overflow)
+  int32_t seg_jv[NS];     // joins (low 16 bits) | valid tasks (high 16 bits) per segment
   int32_t scan_tmp[WG / 64 + 1];
   int64_t scan_tmp64[WG / 64 + 1];
 };
@@ -88,8 +88,8 @@ struct NoVisitLds {};
 
 // Debug phase clock: thread 0 charges the time since the last boundary to
 // phase ph (only with TREES_F_DEBUG; the branch is uniform).
-template <int WG>
-__device__ __forceinline__ void phase_mark(const DevCtx &C, Lds<WG> &L, int ph) {
+template <int WG, int NS>
+__device__ __forceinline__ void phase_mark(const DevCtx &C, Lds<WG, NS> &L, int ph) {
   if (C.debug && threadIdx.x == 0) {
     const int64_t t = realtime();
     L.prof[ph] += t - L.tprof;
@@ -147,8 +147,8 @@ __device__ __forceinline__ int lds_reserve(int32_t *seg_cnt, int seg, int nk) {
 // tree with one 64-bit atomic).  Every thread of the work-group calls it;
 // afterwards L.seg_base[s] holds the arena-relative first child of segment s
 // or -1 if the tree's arena overflowed.
-template <int WG, bool MULTI>
-__device__ __forceinline__ void seg_commit(const DevCtx &C, Lds<WG> &L, const PlainArgs &P,
+template <int WG, bool MULTI, int NS>
+__device__ __forceinline__ void seg_commit(const DevCtx &C, Lds<WG, NS> &L, const PlainArgs &P,
                                            bool with_joins) {
   __syncthreads();
   const int nseg = L.nseg;
@@ -255,10 +255,11 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
 // ---------------------------------------------------------------------------
 // One chunk of kChunk work items.
 // ---------------------------------------------------------------------------
-template <int WG, uint32_t OPS, bool MULTI, typename VL>
-__device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint32_t S, int32_t nL,
+template <int WG, uint32_t OPS, bool MULTI, typename VL, int NS>
+__device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, uint32_t S, int32_t nL,
                           const PlainArgs &P, bool follows = false) {
   constexpr int IT = kChunk / WG;
+  static_assert(MULTI ? NS == kChunk : NS >= 1, "a batched chunk can touch kChunk trees");
   const int tid = threadIdx.x;
   const int lane = lane_id();
 
@@ -320,10 +321,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
       L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_b[0] = C.wl_b[0];
       L.seg_tb[0] = C.wl_tb[0]; L.seg_tp[0] = C.wl_tp[0];
     } else {
-      const TreeStatic *T = &C.ts[P.slot];
       L.seg_slot[0] = P.slot; L.seg_cen[0] = P.cen; L.seg_b[0] = P.b;
-      L.seg_tb[0] = (uint32_t)(T->base >> 6);
-      L.seg_tp[0] = (uint32_t)T->tbase | ((uint32_t)(T->kind == 4 ? T->p0 : 0) << 8);
+      L.seg_tb[0] = P.tb; L.seg_tp[0] = P.tp;
     }
   }
   __syncthreads();
@@ -705,8 +704,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG> &L, VL &V, uint32_t w0, uint3
 //    portion the tile covers in LDS with coalesced loads, each lane merges
 //    its share out of LDS, and the tile is stored with coalesced writes.
 // ---------------------------------------------------------------------------
-constexpr int kMapTile = 2048;
-constexpr int kMaxPortions = 64;   // merge jobs exceed 64 keys, so a tile meets at most 33
+constexpr int kMaxPortions = 72;   // merge jobs exceed 64 keys, so a tile meets at most 65
 
 struct MapLds {
   uint32_t in[kMapTile];
@@ -722,17 +720,23 @@ struct MapLds {
   uint64_t U;
 };
 
-// 64-ary merge-path search by one wavefront (all 64 lanes): the number of the
-// first q outputs that come from A, equal keys taken from A first.
+// k-ary merge-path search by one wavefront (all 64 lanes): the number of the
+// first q outputs that come from A, equal keys taken from A first.  Wide
+// ranges take 64 probes a round (each probe reads its own line anyway, and
+// the early rounds are shared by neighbouring tiles in L2); once the probes
+// would be closer than 64 keys, 8 probes a round read 8x fewer lines, and
+// the last round scans the remaining <= 64 keys with every lane.
 __device__ __forceinline__ int64_t wave_merge_path(const uint32_t *A, int64_t na, const uint32_t *B,
                                                    int64_t nb, int64_t q) {
   const int lane = lane_id();
   int64_t lo = q > nb ? q - nb : 0;
   int64_t hi = q < na ? q : na;
   while (lo < hi) {
-    const int64_t step = (hi - lo + 63) >> 6;
+    const int64_t r = hi - lo;
+    const int ar = (r > 64 * 64 || r <= 64) ? 64 : 8;
+    const int64_t step = (r + ar - 1) / ar;
     const int64_t pos = lo + (int64_t)lane * step;
-    const bool t = pos < hi && A[pos] <= B[q - pos - 1];
+    const bool t = lane < ar && pos < hi && A[pos] <= B[q - pos - 1];
     const int c = __popcll(ballot64(t));
     if (c == 0) {
       hi = lo;
@@ -764,7 +768,10 @@ __device__ __forceinline__ void map_extent(const DevCtx &C, uint32_t Jraw, uint3
 __device__ void map_partition(const DevCtx &C, uint32_t J, uint64_t U, int64_t wid, int64_t nwaves) {
   const uint64_t nb = (U + kMapTile - 1) / kMapTile + 1;   // boundaries 0 .. ntiles
   const int lane = lane_id();
-  for (uint64_t t = (uint64_t)wid; t < nb; t += (uint64_t)nwaves) {
+  // each wavefront takes a contiguous run of boundaries
+  const uint64_t per = (nb + (uint64_t)nwaves - 1) / (uint64_t)nwaves;
+  const uint64_t tb = (uint64_t)wid * per, te = min(tb + per, nb);
+  for (uint64_t t = tb; t < te; ++t) {
     const uint64_t u = min(t * kMapTile, U);
     uint32_t lo = 0, hi = J;   // last job whose offset is <= u (u = U: the last job)
     while (hi - lo > 1) {
@@ -945,9 +952,9 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
   __syncthreads();
 }
 
-template <int WG>
-__device__ __forceinline__ void lds_init(const DevCtx &C, Lds<WG> &L) {
-  for (int t = threadIdx.x; t < kChunk; t += WG) { L.seg_cnt[t] = 0; L.seg_jv[t] = 0; }
+template <int WG, int NS>
+__device__ __forceinline__ void lds_init(const DevCtx &C, Lds<WG, NS> &L) {
+  for (int t = threadIdx.x; t < NS; t += WG) { L.seg_cnt[t] = 0; L.seg_jv[t] = 0; }
   if (threadIdx.x <= kMaxTypes) L.op_tab[threadIdx.x] = C.op_of_type[threadIdx.x];
   __syncthreads();
 }
@@ -960,40 +967,38 @@ __device__ __forceinline__ void lds_init(const DevCtx &C, Lds<WG> &L) {
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
-  __shared__ Lds<WG> L;
+  __shared__ Lds<WG, 1> L;   // one tree: one segment
   __shared__ VL V;
   lds_init<WG>(C, L);
+  if (C.debug) {
+    if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
+    if (threadIdx.x == 0) L.tprof = realtime();
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int q = P.par ^ 1;   // the next epoch's counters
     C.plain->fj[q] = 0; C.plain->valid[q] = 0; C.plain->flags[q] = 0;
-    C.plain->map[q] = 0; C.plain->ticket[q] = 0;
+    C.plain->map[q] = 0;
   }
   const uint32_t S = (uint32_t)(P.e - P.b);
   run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P);
-  // Publish the epoch's counters to the host.  Every wavefront's counter
-  // atomics have been performed before its work-group takes a ticket; the
-  // last ticket reads the totals with atomics (performed after every other
-  // work-group's) and stores them into the mirror, `seq` after the rest has
-  // landed.  Only counters cross here -- the task vector reaches the next
-  // launch through the kernel boundary -- so no L2 write-back is needed.
+  phase_mark(C, L, 6);
+  if (C.debug && threadIdx.x == 0)
+    for (int ph = 0; ph < 8; ++ph) add_agent(&C.hdr->phase[ph], (uint64_t)L.prof[ph]);
+}
+
+// Publishes a plain epoch's counters to the host: launched right after the
+// epoch, so the kernel boundary has made every work-group's counter atomics
+// visible.  Stores the totals into the host-mapped mirror, `seq` after the
+// rest has landed, for the host to poll instead of synchronising the stream.
+__global__ void k_publish(DevCtx C, int32_t par, uint32_t seq) {
+  if (threadIdx.x != 0) return;
+  PlainMirror *M = C.mirror;
+  __hip_atomic_store(&M->fj, ld_agent(&C.plain->fj[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&M->map, ld_agent(&C.plain->map[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&M->valid, ld_agent(&C.plain->valid[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&M->flags, ld_agent(&C.plain->flags[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   wait_vmem();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t t = add_agent(&C.plain->ticket[P.par], 1u);
-    if (t == gridDim.x - 1) {
-      PlainMirror *M = C.mirror;
-      const uint64_t fj = add_agent(&C.plain->fj[P.par], (uint64_t)0);
-      const uint64_t mp = add_agent(&C.plain->map[P.par], (uint64_t)0);
-      const int32_t va = add_agent(&C.plain->valid[P.par], 0);
-      const int32_t fl = or_agent(&C.plain->flags[P.par], 0);
-      __hip_atomic_store(&M->fj, fj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(&M->map, mp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(&M->valid, va, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(&M->flags, fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      wait_vmem();
-      __hip_atomic_store(&M->seq, P.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-  }
+  __hip_atomic_store(&M->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Grid barrier between epochs (Tenet 1: one arrival per work-group).  Every
@@ -1131,7 +1136,12 @@ __global__ __launch_bounds__(WG) void k_map_part(DevCtx C, uint32_t Jarg, int32_
   uint32_t J;
   uint64_t U;
   map_extent(C, Jraw, &J, &U);
-  map_partition(C, J, U, (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6), (int64_t)gridDim.x * (WG / 64));
+  // Work-groups are dispatched round-robin over the 8 XCDs (block b on XCD
+  // b % 8).  Renumbered this way, each XCD searches a contiguous run of
+  // boundaries, whose shared upper probes then hit in its own L2.
+  const uint32_t G = gridDim.x;
+  const uint32_t v = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  map_partition(C, J, U, (int64_t)v * (WG / 64) + (threadIdx.x >> 6), (int64_t)G * (WG / 64));
 }
 
 template <int WG>
@@ -1253,7 +1263,8 @@ const void *kernel_epochs(int wg, uint32_t need) {
   }
 }
 
-// ev0 / ev1 (may be null): HIP events that take the kernel's start and end.
+// One plain epoch and the publication of its counters.  ev0 / ev1 (may be
+// null): HIP events that take the epoch kernel's start and end.
 hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t need, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1) {
   const void *fn = kernel_plain(wg, need);
@@ -1264,7 +1275,12 @@ hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t ne
   DevCtx c = C;
   PlainArgs p = P;
   void *args[] = {&c, &p};
-  return hipExtLaunchKernel(fn, grid, block, args, 0, s, ev0, ev1, 0);
+  hipError_t e = hipExtLaunchKernel(fn, grid, block, args, 0, s, ev0, ev1, 0);
+  if (e != hipSuccess) return e;
+  int32_t par = P.par;
+  uint32_t seq = P.seq;
+  void *pargs[] = {&c, &par, &seq};
+  return hipLaunchKernel((const void *)&k_publish, dim3(1), dim3(64), pargs, 0, s);
 }
 
 // Map launches: the partition pass then the merge pass.  grid_part and

@@ -35,8 +35,9 @@ namespace {
 
 constexpr int kBytesPerEntry = 28;   // code + a0..a3 (int32) + r (int64)
 constexpr int kMapJobs = 1 << 20;    // map jobs per epoch; merges beyond it run serially
-constexpr uint64_t kMapTileUnits = 2048;   // map tile (kMapTile in the kernels)
-constexpr int kPartCap = 1 << 21;    // tile boundaries: 2^32 merged keys per epoch
+constexpr uint64_t kMapTileUnits = kMapTile;
+constexpr int kMapWG = 1024;         // map launches: work-group size (a lane merges kMapTile / kMapWG keys)
+constexpr int kPartCap = 1 << 20;    // tile boundaries: 2^32 merged keys per epoch
 
 std::string g_create_error;
 
@@ -56,6 +57,7 @@ struct HostTree {
   int kind = 0;
   int64_t base = 0, cap = 0;
   uint64_t order = 0;              // submission order
+  uint32_t tp = 0;                 // first type id | nqueens n << 8 (as the kernels cache it)
   TreeState st{};                  // mirror of the device state
   std::vector<TraceRec> trace;     // plain-scheduler trace (host-recorded)
   bool host_trace = false;
@@ -173,7 +175,7 @@ struct trees_ctx {
   std::vector<DepthInit> depth_inits;
   Admit *adm_host = nullptr;       // pinned staging
   Admit *adm_dev = nullptr;
-  PlainMirror *mirror = nullptr;   // host-mapped, written by each plain epoch's last work-group
+  PlainMirror *mirror = nullptr;   // host-mapped, written after each plain epoch
   uint32_t plain_seq = 0;
   SchedHdr *hdr_host = nullptr;
   TreeState *st_host = nullptr;
@@ -372,7 +374,7 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
   while (true) {
     if (*budget == 0 || *(volatile int32_t *)c->abort_flag) break;
     // Phase 1 happened when the range was popped; launch Phase 2.
-    PlainArgs P{slot, st.cen, st.b, st.e, st.old, par};
+    PlainArgs P{slot, st.cen, st.b, st.e, st.old, par, 0, (uint32_t)(t.base >> 6), t.tp};
     if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
     P.seq = ++c->plain_seq ? c->plain_seq : ++c->plain_seq;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -392,11 +394,12 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       const uint64_t tiles = (units + kMapTileUnits - 1) / kMapTileUnits;
       const uint64_t cap = (uint64_t)c->ncu * 16;
       const int gm = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
-      const int gp = (int)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 1 + c->wg / 64 - 1) / (c->wg / 64), cap));
+      int gp = (int)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 1 + kMapWG / 64 - 1) / (kMapWG / 64), cap));
+      gp = (gp + 7) & ~7;   // a multiple of the XCD count (the partition pass maps blocks to XCDs)
       hipEvent_t ev[4] = {};
       if (timed(c, 6)) TRY(take_events(c, 6, &ev[0], &ev[1]));
       if (timed(c, 7)) TRY(take_events(c, 7, &ev[2], &ev[3]));
-      HIPCHK(c, launch_map(c->dc, c->wg, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream,
+      HIPCHK(c, launch_map(c->dc, kMapWG, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream,
                            ev));
     }
     if (trace && st.epochs < kTraceMax)
@@ -512,7 +515,7 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     for (int k = 0; k < c->chunk; ++k) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
       if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
-        e = launch_map(c->dc, c->wg, 0, 1, grid, grid, c->stream, nullptr);
+        e = launch_map(c->dc, kMapWG, 0, 1, c->ncu * 8, c->ncu * 8, c->stream, nullptr);
       if (e != hipSuccess) {
         hipGraph_t g;
         (void)hipStreamEndCapture(c->stream, &g);
@@ -826,6 +829,7 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   t.base = base;
   t.cap = bound;
   t.order = c->order++;
+  t.tp = (uint32_t)P.tbase | ((P.kind == TREES_PROG_NQUEENS ? (uint32_t)args[0] : 0u) << 8);
   c->staged.push_back(a);
   if (P.kind == TREES_PROG_BFS_CSR)
     c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1]});

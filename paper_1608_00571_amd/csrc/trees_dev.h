@@ -13,6 +13,7 @@
 
 namespace trees {
 
+constexpr int kMapTile = 4096;     // map phase: merged keys per tile (one work-group)
 constexpr int kMaxTypes = 31;     // global task-type ids 1..NTT, NTT <= 31
 constexpr int kStackMax = 128;    // stack records per tree
 constexpr int kTraceMax = 256;    // per-epoch trace records per tree
@@ -126,12 +127,11 @@ struct PlainCounters {
   int32_t valid[2];
   int32_t flags[2];
   uint64_t map[2];
-  uint32_t ticket[2];  // work-groups of the epoch that have finished
 };
 
 // Host-visible copy of one epoch's counters (host-mapped, coherent memory),
-// written by the epoch's last work-group; `seq` is written last and names
-// the launch, so the host can wait on it instead of on the stream.
+// written after the epoch; `seq` is written last and names the launch, so
+// the host can wait on it instead of on the stream.
 struct PlainMirror {
   uint64_t fj;
   uint64_t map;
@@ -192,6 +192,8 @@ struct Admit {
 struct PlainArgs {
   int32_t slot, cen, b, e, nfc0, par;
   uint32_t seq;   // launch number published in the mirror
+  uint32_t tb;    // the tree's arena base / 64
+  uint32_t tp;    // its first type id | program parameter << 8 (nqueens n)
 };
 
 }  // namespace trees
