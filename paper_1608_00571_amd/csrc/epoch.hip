@@ -256,32 +256,46 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
 // ---------------------------------------------------------------------------
 // One chunk of kChunk work items.
 // ---------------------------------------------------------------------------
+// A tree's finish check whose atomic is still in flight: the work-group that
+// retires a tree's last items of the epoch runs its Phase 3 (tree_finish).
+// The check is made at the next chunk's bookkeeping or after the last chunk,
+// so the atomic's latency overlaps the next chunk.
+struct PendingFinish {
+  int slot = -1;
+  uint32_t items = 0, range = 0, joins = 0;
+  uint64_t prev = 0;
+};
+
+__device__ __forceinline__ void settle(const DevCtx &C, PendingFinish &f) {
+  if (f.slot >= 0) {
+    if ((uint32_t)f.prev + f.items == f.range) tree_finish(C, f.slot, (uint32_t)(f.prev >> 32) + f.joins);
+    f.slot = -1;
+  }
+}
+
 template <int WG, uint32_t OPS, bool MULTI, typename VL, int NS>
 __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, uint32_t S, int32_t nL,
-                          const PlainArgs &P, bool follows = false) {
+                          const PlainArgs &P, PendingFinish &pend, bool follows = false) {
   constexpr int IT = kChunk / WG;
   static_assert(MULTI ? NS == kChunk : NS >= 1, "a batched chunk can touch kChunk trees");
   const int tid = threadIdx.x;
   const int lane = lane_id();
 
   // ---- locate the chunk's trees ---------------------------------------------
-  // follows: this chunk starts where the previous chunk of this work-group
-  // ended, so its first entry is found in the previous window (every entry
-  // holds at least one item, so it lies within the next kChunk entries).
-  if (MULTI && nL > 1 && follows) {
-    if (tid == 0) {
-      int lo2 = 0, hi2 = kChunk;
-      while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= w0) lo2 = mid + 1; else hi2 = mid; }
-      L.flag = lo2;
-    }
-    __syncthreads();
-    const int adv = L.flag;
-    const uint32_t noff0 = adv ? L.win[adv - 1] : L.off0;
-    __syncthreads();
-    if (tid == 0) { L.kfirst += adv; L.off0 = noff0; }
-  }
+  // A chunk touches the work-list entries kfirst .. kfirst + nseg - 1.  The
+  // first chunk of a work-group's run finds kfirst by a 64-ary search; a
+  // following chunk starts in the last entry of the previous one or in the
+  // entry after it.  One round trip then brings the next 64 entries' ends
+  // and tree data; a chunk that spans more than 64 trees loads the rest.
   if (MULTI && nL > 1) {
-    if (!follows && tid < 64) {
+    if (follows) {
+      if (tid == 0) {
+        const int ps = L.nseg - 1;
+        const int adv = (L.win[ps] <= w0) ? ps + 1 : ps;
+        if (adv) L.off0 = L.win[adv - 1];
+        L.kfirst += adv;
+      }
+    } else if (tid < 64) {
       // 64-ary search for the last entry whose offset is <= w0
       int lo = 0, hi = nL;
       while (hi - lo > 1) {
@@ -296,31 +310,51 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
     }
     __syncthreads();
     const int kf = L.kfirst;
+    const uint32_t wl = min(w0 + (uint32_t)kChunk, S) - 1;   // the chunk's last item
+    if (tid < 64) {
+      const int e = kf + tid;
+      const uint32_t end = (e + 1 <= nL) ? C.wl_off[e + 1] : 0xFFFFFFFFu;
+      if (e < nL) {
+        L.seg_slot[tid] = C.wl_tree[e];
+        L.seg_cen[tid] = C.wl_cen[e];
+        L.seg_b[tid] = C.wl_b[e];
+        L.seg_tb[tid] = C.wl_tb[e];
+        L.seg_tp[tid] = C.wl_tp[e];
+      }
+      L.win[tid] = end;
+      const int ended = __popcll(ballot64(end <= wl));   // entries that end inside the chunk
+      if (tid == 0) L.nseg = ended + 1;
+    }
+    __syncthreads();
+    if (L.nseg > 64) {   // more than 64 trees in this chunk
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int t = k * WG + tid;
-      L.win[t] = (kf + 1 + t <= nL) ? C.wl_off[kf + 1 + t] : 0xFFFFFFFFu;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const uint32_t wl = min(w0 + (uint32_t)kChunk, S) - 1;
-      int lo2 = 0, hi2 = kChunk;
-      while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= wl) lo2 = mid + 1; else hi2 = mid; }
-      L.nseg = lo2 + 1;
-    }
-    __syncthreads();
-    for (int t = tid; t < L.nseg; t += WG) {
-      L.seg_slot[t] = C.wl_tree[kf + t];
-      L.seg_cen[t] = C.wl_cen[kf + t];
-      L.seg_b[t] = C.wl_b[kf + t];
-      L.seg_tb[t] = C.wl_tb[kf + t];
-      L.seg_tp[t] = C.wl_tp[kf + t];
+      for (int k = 0; k < IT; ++k) {
+        const int t = k * WG + tid;
+        const int e = kf + t;
+        if (t < 64) continue;
+        L.win[t] = (e + 1 <= nL) ? C.wl_off[e + 1] : 0xFFFFFFFFu;
+        if (e < nL) {
+          L.seg_slot[t] = C.wl_tree[e];
+          L.seg_cen[t] = C.wl_cen[e];
+          L.seg_b[t] = C.wl_b[e];
+          L.seg_tb[t] = C.wl_tb[e];
+          L.seg_tp[t] = C.wl_tp[e];
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int lo2 = 64, hi2 = kChunk;
+        while (lo2 < hi2) { const int mid = (lo2 + hi2) >> 1; if (L.win[mid] <= wl) lo2 = mid + 1; else hi2 = mid; }
+        L.nseg = lo2 + 1;
+      }
     }
   } else if (tid == 0) {
     L.kfirst = 0; L.nseg = 1; L.off0 = 0; L.win[0] = S;
     if (MULTI) {
-      L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_b[0] = C.wl_b[0];
-      L.seg_tb[0] = C.wl_tb[0]; L.seg_tp[0] = C.wl_tp[0];
+      if (!follows) {   // one tree in the work list: its data stays for the whole run
+        L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_b[0] = C.wl_b[0];
+        L.seg_tb[0] = C.wl_tb[0]; L.seg_tp[0] = C.wl_tp[0];
+      }
     } else {
       L.seg_slot[0] = P.slot; L.seg_cen[0] = P.cen; L.seg_b[0] = P.b;
       L.seg_tb[0] = P.tb; L.seg_tp[0] = P.tp;
@@ -337,11 +371,16 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   int64_t tb[IT];      // arena base of the item's tree
   uint32_t tp[IT];     // its first type id | parameter << 8
   int32_t code[IT], a0v[IT];
+  // a1..a3: loaded with code and a0 when the item's program reads them
+  // (the program is known from the tree before the entry's type is)
+  constexpr bool kWide = (OPS & (OPS_NQ | OPS_MS)) != 0;
+  int32_t a1v[IT], a2v[IT], a3v[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     const uint32_t w = w0 + (uint32_t)(k * WG + tid);
     seg[k] = -1; slot[k] = 0; cen[k] = 0; idx[k] = 0; code[k] = 0; a0v[k] = 0; op[k] = OP_NONE;
     tb[k] = 0; tp[k] = 0;
+    a1v[k] = a2v[k] = a3v[k] = 0;
     if (w < S) {
       int s = 0;
       if (MULTI && nL > 1) {   // segments past the item's offset in the chunk cannot hold it
@@ -357,6 +396,11 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       idx[k] = tb[k] + L.seg_b[s] + (int64_t)(w - (s == 0 ? L.off0 : L.win[s - 1]));
       code[k] = C.code[idx[k]];
       a0v[k] = C.a0[idx[k]];
+      if (kWide) {
+        const int pop = L.op_tab[tp[k] & 0xFF];   // the program's first operation
+        if (pop == OP_Q || pop == OP_MS) { a1v[k] = C.a1[idx[k]]; a2v[k] = C.a2[idx[k]]; }
+        if (pop == OP_Q) a3v[k] = C.a3[idx[k]];
+      }
     }
   }
 #pragma unroll
@@ -408,27 +452,33 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         const int32_t row = a0v[k];
         if (row == n) { act[k] = ACT_EMIT; val[k] = 1; break; }
         const uint32_t full = (1u << n) - 1u;
-        const uint32_t cols = (uint32_t)C.a1[i], ld = (uint32_t)C.a2[i], rd = (uint32_t)C.a3[i];
+        const uint32_t cols = (uint32_t)a1v[k], ld = (uint32_t)a2v[k], rd = (uint32_t)a3v[k];
         const uint32_t avail = ~(cols | ld | rd) & full;
         if (!avail) { act[k] = ACT_EMIT; val[k] = 0; break; }
         act[k] = ACT_JOIN; nk[k] = __popc(avail);
         x0[k] = row; x1[k] = (int32_t)cols; x2[k] = (int32_t)ld; x3[k] = (int32_t)rd;
       } break;
       case OP_QSUM: {
-        const int32_t c = a0v[k], kk = C.a1[i];
+        // the children's counts (kk <= 14), all loads issued before the sum
+        const int32_t c = a0v[k], kk = a1v[k];
+        const int64_t *rr = C.r + tb[k] + c;
+        int64_t part[14];
+#pragma unroll
+        for (int j = 0; j < 14; ++j) part[j] = j < kk ? rr[j] : 0;
         int64_t sm = 0;
-        for (int32_t j = 0; j < kk; ++j) sm += C.r[tb[k] + c + j];
+#pragma unroll
+        for (int j = 0; j < 14; ++j) sm += part[j];
         act[k] = ACT_EMIT; val[k] = sm;
       } break;
       case OP_MS: {
-        const int32_t lo = a0v[k], hi = C.a1[i], d = C.a2[i];
+        const int32_t lo = a0v[k], hi = a1v[k], d = a2v[k];
         x0[k] = lo; x1[k] = hi; x2[k] = d;
         if (hi - lo <= kLeaf) { act[k] = ACT_FINISH; leaf[k] = true; }   // sorted co-operatively below
         else { act[k] = ACT_JOIN; nk[k] = 2; }
       } break;
       case OP_MERGE: {
         act[k] = ACT_FINISH;
-        x0[k] = a0v[k]; x1[k] = C.a1[i]; x2[k] = C.a2[i];
+        x0[k] = a0v[k]; x1[k] = a1v[k]; x2[k] = a2v[k];
         if (C.mj_cap > 0) {
           want_map[k] = true;   // the merge runs in the map phase
         } else {
@@ -672,6 +722,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   __syncthreads();
   phase_mark(C, L, 4);
   const int nseg = L.nseg;
+  if (MULTI) settle(C, pend);
   for (int s = tid; s < nseg; s += WG) {
     const int32_t j = L.seg_jv[s] & 0xFFFF;
     const int32_t v = (int32_t)((uint32_t)L.seg_jv[s] >> 16);
@@ -684,8 +735,11 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       const uint32_t items = hi - lo;
       if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
       const uint64_t add = ((uint64_t)(uint32_t)j << 32) | items;
-      const uint64_t prev = add_agent(&C.hot[sl].done, add);
-      if ((uint32_t)prev + items == end - beg) tree_finish(C, sl, (uint32_t)(prev >> 32) + (uint32_t)j);
+      PendingFinish f;
+      f.slot = sl; f.items = items; f.range = end - beg; f.joins = (uint32_t)j;
+      f.prev = add_agent(&C.hot[sl].done, add);
+      if (s + WG < nseg) settle(C, f);   // (only a thread's last segment waits)
+      else pend = f;
     } else {
       if (v) add_agent(&C.plain->valid[P.par], v);
     }
@@ -702,53 +756,88 @@ template <int WG>
 __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
-  if (after_epoch) {
+  if (after_epoch) {   // trees finished this epoch: result and end epoch
     const int nd = H->done_count;
-    for (int j = tid; j < nd; j += WG) {
-      const int slot = C.done_list[j];
-      TreeState *T = &C.st[slot];
-      if (T->err == 0) T->result = C.r[C.ts[slot].base];
-      T->done_gepoch = H->gepoch;
+    const int64_t ge = H->gepoch;
+    constexpr int RD = WG >= 1024 ? 1 : 1024 / WG;
+    for (int j0 = 0; j0 < nd; j0 += WG * RD) {
+      int slot[RD], err[RD];
+      int64_t base[RD], res[RD];
+#pragma unroll
+      for (int r = 0; r < RD; ++r) {
+        const int j = j0 + r * WG + tid;
+        slot[r] = j < nd ? C.done_list[j] : -1;
+      }
+#pragma unroll
+      for (int r = 0; r < RD; ++r) {
+        err[r] = 1; base[r] = 0;
+        if (slot[r] >= 0) { err[r] = C.st[slot[r]].err; base[r] = C.ts[slot[r]].base; }
+      }
+#pragma unroll
+      for (int r = 0; r < RD; ++r) res[r] = (slot[r] >= 0 && err[r] == 0) ? C.r[base[r]] : 0;
+#pragma unroll
+      for (int r = 0; r < RD; ++r) {
+        if (slot[r] < 0) continue;
+        TreeState *T = &C.st[slot[r]];
+        if (err[r] == 0) T->result = res[r];
+        T->done_gepoch = ge;
+      }
     }
   }
   // Candidates: after an epoch, the trees of the last work list (a live
   // tree always has a non-empty range); at the start of a run, every slot.
+  // Rounds of WG x R candidates: every load of a round is issued before any
+  // of its values is used, then one work-group scan places the round.
   const int sel = H->live_sel;
   const int32_t *src = C.live + (size_t)sel * C.tmax;
   int32_t *dst = C.live + (size_t)(after_epoch ? (sel ^ 1) : 0) * C.tmax;
   const int n = after_epoch ? H->live : H->tslots;
-  const int per = (n + WG - 1) / WG;
-  const int t0 = min(tid * per, n), t1 = min(t0 + per, n);
-  int cnt = 0, items = 0;
-  for (int t = t0; t < t1; ++t) {
-    const int slot = after_epoch ? src[t] : t;
-    const int len = C.t_len[slot];
-    if (len > 0) { ++cnt; items += len; }
-  }
-  int ctot, itot;
-  const int cpre = wg_excl_scan<WG>(cnt, L.scan_tmp, &ctot);
-  const int ipre = wg_excl_scan<WG>(items, L.scan_tmp, &itot);
-  int k = cpre;
-  uint32_t off = (uint32_t)ipre;
   const int64_t g = H->gepoch + (after_epoch ? 1 : 0);
-  for (int t = t0; t < t1; ++t) {
-    const int slot = after_epoch ? src[t] : t;
-    const int len = C.t_len[slot];
-    if (len > 0) {
-      dst[k] = slot;
-      C.wl_tree[k] = slot;
-      C.wl_off[k] = off;
-      {
-        const TreeStatic *T = &C.ts[slot];
-        C.wl_b[k] = C.t_b[slot];
-        C.wl_tb[k] = (uint32_t)(T->base >> 6);
-        C.wl_tp[k] = (uint32_t)T->tbase | ((uint32_t)(T->kind == 4 ? T->p0 : 0) << 8);
-      }
-      C.wl_cen[k] = C.t_cen[slot];
-      if (C.st[slot].start_gepoch < 0) C.st[slot].start_gepoch = g;
-      ++k;
-      off += (uint32_t)len;
+  constexpr int R = WG >= 1024 ? 1 : 1024 / WG;   // (bounded: registers of the epoch kernel)
+  int ctot = 0;
+  uint32_t itot = 0;
+  for (int base = 0; base < n; base += WG * R) {
+    int slot[R], len[R], b[R], cen[R];
+    int64_t tbase[R], sg[R];
+    uint32_t tp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = base + r * WG + tid;
+      slot[r] = t < n ? (after_epoch ? src[t] : t) : -1;
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
+      if (slot[r] >= 0) {
+        const int s = slot[r];
+        len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
+        tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
+      }
+    }
+    int cnt = 0, items = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (len[r] > 0) { ++cnt; items += len[r]; }
+    int rc, ri;
+    int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
+    uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (len[r] <= 0) continue;
+      const int s = slot[r];
+      dst[k] = s;
+      C.wl_tree[k] = s;
+      C.wl_off[k] = off;
+      C.wl_b[k] = b[r];
+      C.wl_tb[k] = (uint32_t)(tbase[r] >> 6);
+      C.wl_tp[k] = tp[r];
+      C.wl_cen[k] = cen[r];
+      if (sg[r] < 0) C.st[s].start_gepoch = g;
+      ++k;
+      off += (uint32_t)len[r];
+    }
+    ctot += rc;
+    itot += (uint32_t)ri;
   }
   __syncthreads();
   if (tid == 0) {
@@ -807,7 +896,8 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
     C.plain->map[q] = 0;
   }
   const uint32_t S = (uint32_t)(P.e - P.b);
-  run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P);
+  PendingFinish none;
+  run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P, none);
   phase_mark(C, L, 6);
   if (C.debug && threadIdx.x == 0)
     for (int ph = 0; ph < 8; ++ph) add_agent(&C.hdr->phase[ph], (uint64_t)L.prof[ph]);
@@ -942,8 +1032,10 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     const uint32_t nchunks = (S + kChunk - 1) / kChunk;
     const uint32_t per = (nchunks + gridDim.x - 1) / gridDim.x;
     const uint32_t c0 = min(blockIdx.x * per, nchunks), c1 = min(c0 + per, nchunks);
+    PendingFinish pend;
     for (uint32_t c = c0; c < c1; ++c)
-      run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, c != c0);
+      run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, c != c0);
+    settle(C, pend);
     phase_mark(C, L, 6);
     const bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
     phase_mark(C, L, 7);

@@ -830,6 +830,7 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   t.cap = bound;
   t.order = c->order++;
   t.tp = (uint32_t)P.tbase | ((P.kind == TREES_PROG_NQUEENS ? (uint32_t)args[0] : 0u) << 8);
+  a.ts.tp = t.tp;
   c->staged.push_back(a);
   if (P.kind == TREES_PROG_BFS_CSR)
     c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1]});

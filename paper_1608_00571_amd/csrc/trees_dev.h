@@ -48,7 +48,7 @@ struct TreeStatic {
   int32_t tbase;     // global type id of the program's first type
   int32_t kind;      // trees_builtin
   int32_t p0, p1;    // fib n | nqueens n | msort N | bfs V, source
-  int32_t pad;
+  uint32_t tp;       // tbase | (nqueens n) << 8, as the work list carries it
   uint64_t ptr0, ptr1, ptr2;  // msort: keys, tmp; bfs: row_ptr, col_idx, depth
 };
 
