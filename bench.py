@@ -427,13 +427,19 @@ def bench_cfg1(args):
     p = ctx.register(T.FIB_I32)
     for _ in range(args.warmup):
         t = ctx.submit(p, [20]); ctx.run(); ctx.results(t)
-    kt0 = ctx.kernel_times()
+    # timed steps carry no per-launch events (they cost host time per launch)
+    ctx.profile_mask([])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         t = ctx.submit(p, [20]); ctx.run(); v, st = ctx.results(t)
         assert v == 6765 and st.tasks == 32836 and st.epochs == 39
     dt = (time.perf_counter() - t0) / args.steps
+    # then the same steps with every epoch launch timed, for the kernel share
+    ctx.profile_mask([T.FIB_I32])
+    kt0 = ctx.kernel_times()
+    for _ in range(args.steps):
+        t = ctx.submit(p, [20]); ctx.run(); ctx.results(t)
     kt1 = ctx.kernel_times()
     kms = (kt1[T.FIB_I32][0] - kt0[T.FIB_I32][0]) / args.steps
     ctx.close()
@@ -442,7 +448,8 @@ def bench_cfg1(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
             "config": {"workload": "fib(20) int32, plain scheduler", "sched": "plain", "wg": args.wg},
             "epochs_per_s": 39 / dt, "us_per_epoch": round(dt * 1e6 / 39, 2),
-            "kernel_us_per_epoch": round(kms * 1e3 / 39, 2)}
+            "kernel_us_per_epoch": round(kms * 1e3 / 39, 2),
+            "launch_readback_us_per_epoch": round(dt * 1e6 / 39 - kms * 1e3 / 39, 2)}
 
 
 def bench_cfg4(args):

@@ -846,6 +846,7 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
       H->mapJ = (uint32_t)(mc >> kMapShift);
       st_agent(&H->map_ctr, (uint64_t)0);
     }
+    st_agent(&H->chunk_ctr, 0u);   // every work-group has stopped claiming this epoch's chunks
     H->live_sel = after_epoch ? (sel ^ 1) : 0;
     C.wl_off[ctot] = (uint32_t)itot;
     H->S = (uint32_t)itot;
@@ -1001,7 +1002,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   __shared__ Lds<WG> L;
   __shared__ MapL M;
   __shared__ VL V;
-  __shared__ uint32_t s_hdr[4];
+  __shared__ uint32_t s_hdr[5];
   lds_init<WG>(C, L);
   if (threadIdx.x == 0) L.tflag = 0;
   if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
@@ -1028,13 +1029,31 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     }
     if (stop) break;
     if (mapJ && !grid_barrier<WG>(C, L, false, true)) break;
-    // each work-group sweeps a contiguous run of chunks
+    // Chunks go to work-groups in runs of consecutive chunks; within a run
+    // each chunk continues where the previous one ended.  Kernels with BFS
+    // (whose chunks differ in cost by orders of magnitude) claim runs from a
+    // shared counter, guided: a run is about a quarter of an even share, so
+    // a work-group that drew expensive chunks takes fewer.  The others take
+    // one even share each.
     const uint32_t nchunks = (S + kChunk - 1) / kChunk;
-    const uint32_t per = (nchunks + gridDim.x - 1) / gridDim.x;
-    const uint32_t c0 = min(blockIdx.x * per, nchunks), c1 = min(c0 + per, nchunks);
+    constexpr bool kGuided = (OPS & OPS_BFS) != 0;
+    const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
     PendingFinish pend;
-    for (uint32_t c = c0; c < c1; ++c)
-      run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, c != c0);
+    for (uint32_t turn = 0;; ++turn) {
+      uint32_t c0;
+      if (kGuided) {
+        if (threadIdx.x == 0) s_hdr[4] = add_agent(&H->chunk_ctr, run);
+        __syncthreads();
+        c0 = s_hdr[4];
+        __syncthreads();
+      } else {
+        c0 = turn == 0 ? blockIdx.x * run : nchunks;
+      }
+      if (c0 >= nchunks) break;
+      const uint32_t c1 = min(c0 + run, nchunks);
+      for (uint32_t c = c0; c < c1; ++c)
+        run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, c != c0);
+    }
     settle(C, pend);
     phase_mark(C, L, 6);
     const bool ok = grid_barrier<WG>(C, L, true, persistent != 0);

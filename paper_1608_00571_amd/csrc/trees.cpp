@@ -473,6 +473,7 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
   c->hdr_host->mapJ = 0;
   c->hdr_host->map_ctr = 0;
   c->hdr_host->map_arrive = 0;
+  c->hdr_host->chunk_ctr = 0;
   HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_scan(c->dc, c->stream));
   return TREES_OK;

@@ -108,6 +108,8 @@ struct SchedHdr {
   alignas(128) uint64_t map_ctr;  // (jobs << 38) | units, appended during an epoch
   uint32_t map_arrive;            // work-groups done with the map launch
   int32_t pad3[29];
+  alignas(128) uint32_t chunk_ctr;  // next chunk of the current epoch to hand out
+  int32_t pad5[31];
   int64_t stamp0;                 // device clock when the run's first work list was built
   int64_t stamp[256];             // device clock at the end of each epoch of the run
   uint64_t phase[8];              // debug: summed work-group time per chunk phase (device clock)
