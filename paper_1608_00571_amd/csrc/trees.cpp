@@ -59,8 +59,6 @@ struct HostTree {
   uint64_t order = 0;              // submission order
   uint32_t tp = 0;                 // first type id | nqueens n << 8 (as the kernels cache it)
   TreeState st{};                  // mirror of the device state
-  std::vector<TraceRec> trace;     // plain-scheduler trace (host-recorded)
-  bool host_trace = false;
 };
 
 uint32_t ops_of_kind(int kind) {
@@ -276,8 +274,6 @@ trees_status flush_admissions(trees_ctx *c) {
       memset(&t.st, 0, sizeof(t.st));
       t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 1; t.st.peak = 1;
       t.st.done_gepoch = -1; t.st.start_gepoch = -1;
-      t.trace.clear();
-      t.host_trace = false;
     }
     c->staged.clear();
   }
@@ -366,7 +362,9 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     HIPCHK(c, hipMemcpy(stk.data(), c->dc.stack + (size_t)slot * kStackMax, sizeof(int4) * st.sp,
                         hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemsetAsync(c->dc.plain, 0, sizeof(PlainCounters), c->stream));
-  if (trace) t.host_trace = true;
+  // this run's trace records, appended to the tree's device trace at the end
+  // (a tree may run some epochs batched and others plain)
+  std::vector<TraceRec> recs;
   const uint32_t need = c->progs[t.prog].ops;
   int par = 0;
   int err = 0;
@@ -402,8 +400,8 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       HIPCHK(c, launch_map(c->dc, kMapWG, (uint32_t)(mc >> kMapShift), 0, gp, gm, c->stream,
                            ev));
     }
-    if (trace && st.epochs < kTraceMax)
-      t.trace.push_back(TraceRec{st.epochs, st.cen, st.b, st.e, st.e - st.b, valid, forks, joins, nfc});
+    if (trace && st.ntrace + (int)recs.size() < kTraceMax)
+      recs.push_back(TraceRec{st.epochs, st.cen, st.b, st.e, st.e - st.b, valid, forks, joins, nfc});
     st.epochs += 1;
     st.launched += st.e - st.b;
     st.tasks += (int64_t)forks + joins;
@@ -434,6 +432,11 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       HIPCHK(c, hipMemcpy(c->r_host, c->dc.r + t.base, sizeof(int64_t), hipMemcpyDeviceToHost));
       st.result = c->r_host[0];
     }
+  }
+  if (!recs.empty()) {
+    HIPCHK(c, hipMemcpyAsync(c->dc.trace + (size_t)slot * kTraceMax + st.ntrace, recs.data(),
+                             sizeof(TraceRec) * recs.size(), hipMemcpyHostToDevice, c->stream));
+    st.ntrace += (int32_t)recs.size();
   }
   // Write the state back so any scheduler can continue a paused tree.
   c->st_host[0] = st;
@@ -930,7 +933,6 @@ trees_status trees_results(trees_ctx *c, uint64_t tree, int64_t *out_value, tree
   arena_free(c, t->base, t->cap);
   t->hstatus = H_FREE;
   t->gen++;
-  t->trace.clear();
   c->ntrees--;
   return rc;
 }
@@ -942,12 +944,6 @@ trees_status trees_trace(trees_ctx *c, uint64_t tree, trees_epoch_rec *out, int3
   HostTree *t = find_tree(c, tree, &slot);
   if (!t) return fail(c, TREES_E_INVALID, "unknown tree id");
   static_assert(sizeof(TraceRec) == sizeof(trees_epoch_rec), "trace record layout");
-  if (t->host_trace) {
-    const int m = std::min<int>(cap, (int)t->trace.size());
-    if (m > 0) memcpy(out, t->trace.data(), sizeof(TraceRec) * m);
-    *n = (int)t->trace.size();
-    return TREES_OK;
-  }
   if (!c->dc.trace) return fail(c, TREES_E_STATE, "context created without TREES_F_TRACE");
   const int total = std::min<int>(t->st.ntrace, kTraceMax);
   const int m = std::min<int>(cap, total);

@@ -1,0 +1,111 @@
+"""Failure handling and resumption through the C ABI: an epoch budget pauses
+every tree at an epoch boundary and a later run (under any scheduler)
+finishes it with the oracle's result and statistics; an abort from another
+thread stops a run the same way; a budget that is full refuses admission
+until a tree is collected; bad arguments and late registration are refused."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import Job, assert_matches_oracle, register_all
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx(sched, arena=64 << 20, **kw):
+    import paper_1608_00571_amd as T
+    return T.Context(arena, sched=sched, timeout_s=20.0, **kw)
+
+
+@pytest.mark.parametrize("first,second", [("persistent", "graph"), ("graph", "plain"),
+                                          ("plain", "persistent")])
+def test_epoch_budget_pauses_and_resumes(first, second):
+    import paper_1608_00571_amd as T
+    jobs = [Job("fib64", 18), Job("nqueens", 7), Job("fib64", 3)]
+    with ctx(first, trace=True) as c:
+        register_all(c, jobs)
+        for j in jobs:
+            j.submit(c)
+        rs = c.run(max_epochs=5)
+        assert rs.stop_reason == 2 and rs.live >= 1
+        with pytest.raises(T.TreesError) as e:
+            c.results(jobs[0].tree)
+        assert e.value.status == T.E_PENDING
+        c.set_schedule(second)
+        c.run()
+        for j in jobs:
+            j.collect(c, trace=True)
+    for j in jobs:
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+def test_abort_from_another_thread_then_resume(sched):
+    """The abort lands at an epoch boundary (or after the run ended, if the
+    run was faster than the other thread): either way every tree finishes
+    correctly after a further run."""
+    import time
+    jobs = [Job("fib64", 32) for _ in range(8)]
+    with ctx(sched, arena=2 << 30) as c:
+        register_all(c, jobs)
+        for j in jobs:
+            j.submit(c)
+        out = {}
+
+        def runner():
+            out["rs"] = c.run()
+
+        t = threading.Thread(target=runner)
+        t.start()
+        time.sleep(0.002)
+        c.abort()
+        t.join(60)
+        assert not t.is_alive()
+        rs = out["rs"]
+        assert rs.stop_reason in (1, 3)
+        if rs.stop_reason == 3:
+            assert rs.live >= 1
+            c.run()
+        for j in jobs:
+            j.collect(c, trace=False)
+    for j in jobs:
+        assert_matches_oracle(j, check_trace=False)
+
+
+def test_admission_refused_until_collected():
+    import paper_1608_00571_amd as T
+    need = T.tv_bound(T.FIB_I64, [20])
+    per = ((need + 63) // 64) * 64
+    with ctx("persistent", arena=(per * 2 + 10) * T.BYTES_PER_ENTRY) as c:
+        p = c.register(T.FIB_I64)
+        a = c.submit(p, [20])
+        b = c.submit(p, [20])
+        assert c.try_submit(p, [20]) is None          # the budget holds two arenas
+        c.run()
+        assert c.results(a)[0] == oracle.fib(20).result
+        d = c.submit(p, [20])                          # a's arena came back
+        c.run()
+        assert c.results(b)[0] == oracle.fib(20).result
+        assert c.results(d)[0] == oracle.fib(20).result
+        assert c.num_trees == 0
+
+
+def test_bad_arguments_and_late_registration():
+    import paper_1608_00571_amd as T
+    with ctx("plain") as c:
+        pq = c.register(T.NQUEENS)
+        for bad in ([0], [15], []):
+            with pytest.raises(T.TreesError) as e:
+                c.submit(pq, bad)
+            assert e.value.status == T.E_INVALID
+        pf = c.register(T.FIB_I64)
+        t = c.submit(pf, [10])
+        with pytest.raises(T.TreesError) as e:
+            c.register(T.MSORT_U32)                     # the type ids are frozen at the first submit
+        assert e.value.status == T.E_STATE
+        c.run()
+        assert c.results(t)[0] == 55
+        with pytest.raises(T.TreesError):
+            c.results(t)                                # released: the id is stale
