@@ -273,11 +273,26 @@ __device__ __forceinline__ void settle(const DevCtx &C, PendingFinish &f) {
   }
 }
 
-template <int WG, uint32_t OPS, bool MULTI, typename VL, int NS>
+// Task-vector entries of the next chunk of a work-group's run, loaded while
+// the current chunk is processed (only when the next chunk lies inside the
+// current chunk's last tree, so its indices need no locate).
+template <int IT>
+struct Prefetch {
+  uint32_t w0 = 0xFFFFFFFFu;   // first item of the prefetched chunk (none: ~0)
+  int32_t code[IT], a0[IT], a1[IT], a2[IT], a3[IT];
+};
+
+template <int WG, uint32_t OPS, bool MULTI, typename VL, int NS, int IT>
 __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, uint32_t S, int32_t nL,
-                          const PlainArgs &P, PendingFinish &pend, bool follows = false) {
-  constexpr int IT = kChunk / WG;
+                          const PlainArgs &P, PendingFinish &pend, Prefetch<IT> &pf, uint32_t run_end,
+                          bool follows = false) {
+  static_assert(IT == kChunk / WG, "items per lane");
   static_assert(MULTI ? NS == kChunk : NS >= 1, "a batched chunk can touch kChunk trees");
+  // the previous chunk already loaded this chunk's entries (same tree, same
+  // window); kernels with merge sort or BFS do not prefetch (their register
+  // budget is spent on leaf sorts and arc expansion)
+  constexpr bool kPrefetch = MULTI && (OPS & (OPS_MS | OPS_BFS)) == 0;
+  const bool hit = kPrefetch && follows && pf.w0 == w0;
   const int tid = threadIdx.x;
   const int lane = lane_id();
 
@@ -287,7 +302,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   // following chunk starts in the last entry of the previous one or in the
   // entry after it.  One round trip then brings the next 64 entries' ends
   // and tree data; a chunk that spans more than 64 trees loads the rest.
-  if (MULTI && nL > 1) {
+  if (hit) {
+    // one segment that extends past this chunk: the window stays as it is
+  } else if (MULTI && nL > 1) {
     if (follows) {
       if (tid == 0) {
         const int ps = L.nseg - 1;
@@ -394,13 +411,43 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       tb[k] = (int64_t)L.seg_tb[s] << 6;
       tp[k] = L.seg_tp[s];
       idx[k] = tb[k] + L.seg_b[s] + (int64_t)(w - (s == 0 ? L.off0 : L.win[s - 1]));
-      code[k] = C.code[idx[k]];
-      a0v[k] = C.a0[idx[k]];
-      if (kWide) {
-        const int pop = L.op_tab[tp[k] & 0xFF];   // the program's first operation
-        if (pop == OP_Q || pop == OP_MS) { a1v[k] = C.a1[idx[k]]; a2v[k] = C.a2[idx[k]]; }
-        if (pop == OP_Q) a3v[k] = C.a3[idx[k]];
+      if (hit) {
+        code[k] = pf.code[k]; a0v[k] = pf.a0[k];
+        a1v[k] = pf.a1[k]; a2v[k] = pf.a2[k]; a3v[k] = pf.a3[k];
+      } else {
+        code[k] = C.code[idx[k]];
+        a0v[k] = C.a0[idx[k]];
+        if (kWide) {
+          const int pop = L.op_tab[tp[k] & 0xFF];   // the program's first operation
+          if (pop == OP_Q || pop == OP_MS) { a1v[k] = C.a1[idx[k]]; a2v[k] = C.a2[idx[k]]; }
+          if (pop == OP_Q) a3v[k] = C.a3[idx[k]];
+        }
       }
+    }
+  }
+  // Prefetch: when the next chunk of the run lies wholly inside this chunk's
+  // only tree, issue its loads now; they complete while this chunk runs.
+  pf.w0 = 0xFFFFFFFFu;
+  if (kPrefetch) {
+    const uint32_t n0 = w0 + (uint32_t)kChunk;
+    if (n0 < run_end && L.nseg == 1 && L.win[0] >= min(n0 + (uint32_t)kChunk, S)) {
+      const int64_t base = ((int64_t)L.seg_tb[0] << 6) + L.seg_b[0] - (int64_t)L.off0;
+      const int pop = kWide ? L.op_tab[L.seg_tp[0] & 0xFF] : OP_NONE;
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        const uint32_t w = n0 + (uint32_t)(k * WG + tid);
+        pf.code[k] = 0; pf.a0[k] = 0; pf.a1[k] = 0; pf.a2[k] = 0; pf.a3[k] = 0;
+        if (w < S) {
+          const int64_t i = base + (int64_t)w;
+          pf.code[k] = C.code[i];
+          pf.a0[k] = C.a0[i];
+          if (kWide) {
+            if (pop == OP_Q || pop == OP_MS) { pf.a1[k] = C.a1[i]; pf.a2[k] = C.a2[i]; }
+            if (pop == OP_Q) pf.a3[k] = C.a3[i];
+          }
+        }
+      }
+      pf.w0 = n0;
     }
   }
 #pragma unroll
@@ -898,7 +945,8 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   }
   const uint32_t S = (uint32_t)(P.e - P.b);
   PendingFinish none;
-  run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P, none);
+  Prefetch<kChunk / WG> nopf;
+  run_chunk<WG, OPS, false>(C, L, V, blockIdx.x * kChunk, S, 1, P, none, nopf, 0u);
   phase_mark(C, L, 6);
   if (C.debug && threadIdx.x == 0)
     for (int ph = 0; ph < 8; ++ph) add_agent(&C.hdr->phase[ph], (uint64_t)L.prof[ph]);
@@ -1039,6 +1087,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     constexpr bool kGuided = (OPS & OPS_BFS) != 0;
     const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
     PendingFinish pend;
+    Prefetch<kChunk / WG> pf;
     for (uint32_t turn = 0;; ++turn) {
       uint32_t c0;
       if (kGuided) {
@@ -1051,8 +1100,9 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
       }
       if (c0 >= nchunks) break;
       const uint32_t c1 = min(c0 + run, nchunks);
+      pf.w0 = 0xFFFFFFFFu;
       for (uint32_t c = c0; c < c1; ++c)
-        run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, c != c0);
+        run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, pf, c1 * kChunk, c != c0);
     }
     settle(C, pend);
     phase_mark(C, L, 6);
