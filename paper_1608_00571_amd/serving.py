@@ -9,6 +9,11 @@ overlaps; finished trees are collected after every burst and their arenas
 return to the budget.  Latency is measured from a request's arrival to the
 burst after which its result was collected.
 
+Payloads: a merge-sort request brings its keys in pinned host memory
+(uploaded asynchronously at admission); BFS requests query graphs of a
+device-resident pool (uploaded once per graph, shared by every request on
+that graph); a request's output stays on the device until it is read.
+
 Every step of the epoch path runs in libtrees; this module only decides
 what to submit and when.
 """
@@ -32,15 +37,25 @@ class Job:
     t_arrive: float
     kind: str
     args: list
-    host_payload: object = None      # msort: uint32 keys; bfs: (row_ptr, col_idx)
+    host_payload: object = None      # msort: uint32 keys (numpy); bfs: (row_ptr, col_idx)
+    graph_key: object = None         # bfs: the pool graph the request queries
     tree: int | None = None
     dev: tuple = ()
     t_admit: float = 0.0
     t_done: float = 0.0
     value: int = 0
     stats: object = None
-    out: np.ndarray | None = None
+    out_dev: object = None           # msort: sorted keys; bfs: depths (device tensors)
     bytes_payload: int = 0
+    pinned: object = None            # msort: the keys in pinned host memory
+
+    @property
+    def out(self) -> np.ndarray | None:
+        """The request's output on the host (copied on first use)."""
+        if self.out_dev is None:
+            return None
+        a = self.out_dev.cpu().numpy()
+        return a.view(np.uint32) if self.kind == "msort" else a
 
 
 @dataclass
@@ -69,21 +84,31 @@ class Server:
         self.skip_ahead = skip_ahead
         self.payload_budget = payload_budget
         self.payload_used = 0
+        self.graphs = {}   # graph_key -> (row_ptr, col_idx) on the device
 
     def close(self):
         self.ctx.close()
 
     # -- admission ------------------------------------------------------------
+    def _graph(self, j: Job):
+        key = j.graph_key if j.graph_key is not None else ("job", j.rid)
+        g = self.graphs.get(key)
+        if g is None:
+            rp, ci = j.host_payload
+            g = (self.torch.from_numpy(rp).to("cuda"), self.torch.from_numpy(ci).to("cuda"))
+            if j.graph_key is not None:
+                self.graphs[key] = g
+        return g
+
     def _upload(self, j: Job):
         torch = self.torch
         if j.kind == "msort":
-            k = torch.from_numpy(j.host_payload.view(np.int32)).to("cuda", non_blocking=True)
+            src = j.pinned if j.pinned is not None else torch.from_numpy(j.host_payload.view(np.int32))
+            k = src.to("cuda", non_blocking=True)
             j.dev = (k, torch.empty_like(k))
         elif j.kind == "bfs":
-            rp, ci = j.host_payload
-            j.dev = (torch.from_numpy(rp).to("cuda", non_blocking=True),
-                     torch.from_numpy(ci).to("cuda", non_blocking=True),
-                     torch.empty(rp.shape[0] - 1, dtype=torch.int32, device="cuda"))
+            rp, ci = self._graph(j)
+            j.dev = (rp, ci, torch.empty(rp.shape[0] - 1, dtype=torch.int32, device="cuda"))
 
     def _try_admit(self, j: Job, now: float) -> bool:
         if self.payload_used + j.bytes_payload > self.payload_budget:
@@ -105,9 +130,9 @@ class Server:
         j.value, j.stats = r
         j.t_done = now
         if j.kind == "msort":
-            j.out = j.dev[0].cpu().numpy().view(np.uint32)
+            j.out_dev = j.dev[0]
         elif j.kind == "bfs":
-            j.out = j.dev[2].cpu().numpy()
+            j.out_dev = j.dev[2]
         j.dev = ()
         self.payload_used -= j.bytes_payload
         return True
@@ -160,18 +185,24 @@ class Server:
         return ServeResult(done, total, bursts, max_inflight, epochs, lat)
 
 
-def make_jobs(requests, graph_pool: dict, keys_for) -> list[Job]:
+def make_jobs(requests, graph_pool: dict, keys_for, pin: bool = True) -> list[Job]:
     """Turn request descriptions into jobs.  graph_pool maps an R-MAT scale
-    to a host graph; keys_for(req) returns the request's uint32 keys."""
+    to a host graph (requests on one scale query the same pool graph);
+    keys_for(req) returns the request's uint32 keys, which arrive in pinned
+    host memory when `pin`."""
+    import torch
     jobs = []
     for r in requests:
         if r.kind == "fib":
             jobs.append(Job(r.rid, r.t_arrive, "fib", [r.size]))
         elif r.kind == "msort":
             keys = keys_for(r)
-            jobs.append(Job(r.rid, r.t_arrive, "msort", [r.size], keys, bytes_payload=8 * r.size))
+            pinned = torch.from_numpy(keys.view(np.int32)).pin_memory() if pin else None
+            jobs.append(Job(r.rid, r.t_arrive, "msort", [r.size], keys, bytes_payload=8 * r.size,
+                            pinned=pinned))
         else:
             g = graph_pool[r.size]
+            # the graph is pool-resident; a request holds its depth array
             jobs.append(Job(r.rid, r.t_arrive, "bfs", [g.V, g.source], (g.row_ptr, g.col_idx),
-                            bytes_payload=4 * (2 * g.V + 1 + g.E)))
+                            graph_key=("rmat", r.size), bytes_payload=4 * g.V))
     return jobs
