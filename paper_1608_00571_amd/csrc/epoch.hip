@@ -44,7 +44,7 @@ enum : int { ACT_NONE = 0, ACT_EMIT = 1, ACT_JOIN = 2, ACT_FINISH = 3 };
 // x % WG as its item x / WG, so each of a lane's items is a coalesced
 // work-group-wide access).  All per-tree state a chunk needs is cached in LDS
 // per segment (a run of the chunk's items that belong to one tree).
-constexpr int kChunk = 1024;
+constexpr int kChunk = kChunkItems;
 
 template <int WG, int NS = kChunk>   // NS: segments a chunk can touch (1 in the plain form)
 struct Lds {
@@ -52,6 +52,7 @@ struct Lds {
   int32_t nseg;            // entries (trees) the chunk touches
   uint32_t off0;           // wl_off[kfirst]
   int32_t flag;            // scratch broadcast
+  int32_t flag2;
   uint32_t gen;
   int32_t sink;            // destination of atomics whose completion must be awaited
   int32_t tflag;
@@ -75,7 +76,13 @@ struct Lds {
 
 // VISIT expansion state (only in kernels that run BFS).
 constexpr int kClaimQ = 2048;
-constexpr int kArcsPerLane = 4;   // arcs a lane probes per step of the expansion
+constexpr int kArcsPerLane = 4;   // arcs a lane probes per step of the expansion (at most)
+// Arcs per lane per step for a work-group of WG lanes: one step claims at
+// most WG * A vertices, and a flush leaves room for one more step.
+template <int WG>
+constexpr int arcs_per_lane() {
+  return (kClaimQ / 2) / WG >= kArcsPerLane ? kArcsPerLane : ((kClaimQ / 2) / WG > 0 ? (kClaimQ / 2) / WG : 1);
+}
 struct VisitLds {
   int32_t row[kChunk];     // first arc of the item's vertex
   int32_t pre[kChunk];     // exclusive prefix of out-degrees, in (lane, item) order
@@ -271,6 +278,79 @@ __device__ __forceinline__ void settle(const DevCtx &C, PendingFinish &f) {
     if ((uint32_t)f.prev + f.items == f.range) tree_finish(C, f.slot, (uint32_t)(f.prev >> 32) + f.joins);
     f.slot = -1;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Arc phase (batched forms): publication by the owner chunk, and tiles.
+// ---------------------------------------------------------------------------
+
+// Last index i in [0, kChunk) with pre[i] <= e (pre is non-decreasing, pre[0] = 0).
+__device__ __forceinline__ int last_le(const int32_t *pre, int e) {
+  int lo = 0, hi = kChunk;
+  while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (pre[mid] <= e) lo = mid; else hi = mid; }
+  return lo;
+}
+
+// Publishes the chunk's VISIT arcs (V: lane-major degree prefix, first arcs,
+// segments; tot arcs in all) as a job of tiles.  Returns the job number, or
+// -1 when the epoch's job table is full (the chunk then expands locally).
+// Plain stores: the arc phase reads them after a grid barrier or a kernel
+// boundary.
+template <int WG>
+__device__ int publish_arcs(const DevCtx &C, Lds<WG> &L, VisitLds &V, int tot) {
+  SchedHdr *H = C.hdr;
+  const int tid = threadIdx.x;
+  const int tile = max(kArcTile, (tot + kArcTilesMax - 1) / kArcTilesMax);
+  const int ntiles = (tot + tile - 1) / tile;
+  const int nseg = L.nseg;
+  if (tid == 0) {
+    // a job, its tiles and its segment records; any table full: no job
+    // (the counters keep growing, and a later claim sees they are full)
+    int j = (int)add_agent(&H->arc_jobs, 1u);
+    uint32_t tb = 0, sb = 0;
+    if (j < kArcJobs) {
+      tb = add_agent(&H->arc_tiles, (uint32_t)ntiles);
+      sb = add_agent(&H->arc_segs, (uint32_t)nseg);
+      // reserved tiles of a job that cannot be kept are marked empty (-2)
+      if (tb + (uint32_t)ntiles > (uint32_t)kArcTilesAll || sb + (uint32_t)nseg > (uint32_t)kArcSegPool) j = -2;
+    } else {
+      j = -1;
+    }
+    L.flag = j;
+    L.flag2 = (int)tb;
+    L.jbase = sb;
+  }
+  __syncthreads();
+  const int j = L.flag;
+  const uint32_t tbase = (uint32_t)L.flag2;
+  const uint32_t sbase = L.jbase;
+  __syncthreads();
+  if (j == -2) {
+    for (int t = tid; t < ntiles; t += WG)
+      if (tbase + (uint32_t)t < (uint32_t)kArcTilesAll) C.arc_tile[tbase + t] = make_int4(-1, 0, 0, 0);
+  }
+  if (j < 0) return -1;
+  int32_t *it = C.arc_item + (size_t)j * kArcItemWords;
+  for (int i = tid; i < kChunk; i += WG) {
+    it[i] = V.pre[i];
+    it[kChunk + i] = V.row[i];
+    it[2 * kChunk + i] = V.seg[i];
+  }
+  int32_t *sg = C.arc_seg + sbase;
+  for (int q = tid; q < nseg; q += WG) {
+    sg[q] = L.seg_slot[q];
+    sg[kArcSegPool + q] = L.seg_cen[q];
+    sg[2 * kArcSegPool + q] = (int32_t)L.seg_tb[q];
+    sg[3 * kArcSegPool + q] = (int32_t)L.seg_tp[q];
+  }
+  for (int t = tid; t < ntiles; t += WG)
+    C.arc_tile[tbase + t] = make_int4(j, last_le(V.pre, t * tile), last_le(V.pre, min((t + 1) * tile, tot) - 1), 0);
+  if (tid == 0) {
+    ArcJob *J = &C.arc_job[j];
+    J->tot = tot; J->tile = tile; J->ntiles = ntiles; J->nseg = nseg; J->tbase = tbase; J->sbase = sbase;
+    st_agent(&J->done, 0u);
+  }
+  return j;
 }
 
 // Task-vector entries of the next chunk of a work-group's run, loaded while
@@ -677,6 +757,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   __syncthreads();
   phase_mark(C, L, 3);
   // ---- BFS: co-operative expansion of the VISIT items' arcs -----------------
+  int arc_job = -1;   // >= 0: this chunk's arcs (and its retirement) went to that arc job
   if constexpr ((OPS & OPS_BFS) != 0) {
     bool anyv = false;
 #pragma unroll
@@ -705,12 +786,17 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       }
       if (tid == 0) V.qn = 0;
       __syncthreads();
+      // many arcs: published as tiles for every work-group (batched forms)
+      if constexpr (MULTI) {
+        if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot);
+      }
       // One arc per lane per step.  A claimed vertex is queued in LDS; the
       // queue is turned into child entries in bulk (one device atomic per
       // tree per flush) when it is nearly full and at the end.
-      constexpr int A = kArcsPerLane;
+      constexpr int A = arcs_per_lane<WG>();
+      static_assert(WG * A <= kClaimQ / 2, "claim queue too small for one step");
       int from = 0;   // arcs are visited in increasing order: item searches only move forward
-      for (int e0 = 0; e0 < tot; e0 += WG * A) {
+      for (int e0 = 0; e0 < (arc_job >= 0 ? 0 : tot); e0 += WG * A) {
         int32_t u[A], sseg[A];
         int32_t *dep[A];
         int32_t dv[A];
@@ -780,6 +866,13 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       const uint32_t end = L.win[s];
       const uint32_t lo = max(beg, w0), hi = min(min(end, w0 + (uint32_t)kChunk), S);
       const uint32_t items = hi - lo;
+      if (arc_job >= 0) {   // retired by the arc job's last tile
+        int32_t *sg = C.arc_seg + C.arc_job[arc_job].sbase;
+        sg[4 * kArcSegPool + s] = (int32_t)items;
+        sg[5 * kArcSegPool + s] = (int32_t)(end - beg);
+        sg[6 * kArcSegPool + s] = j | (v << 16);
+        continue;
+      }
       if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
       const uint64_t add = ((uint64_t)(uint32_t)j << 32) | items;
       PendingFinish f;
@@ -894,6 +987,11 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
       st_agent(&H->map_ctr, (uint64_t)0);
     }
     st_agent(&H->chunk_ctr, 0u);   // every work-group has stopped claiming this epoch's chunks
+    st_agent(&H->arc_jobs, 0u);    // and has left this epoch's arc phase
+    st_agent(&H->arc_tiles, 0u);
+    st_agent(&H->arc_segs, 0u);
+    st_agent(&H->arc_next, 0u);
+    H->arc_phase = 0;
     H->live_sel = after_epoch ? (sel ^ 1) : 0;
     C.wl_off[ctot] = (uint32_t)itot;
     H->S = (uint32_t)itot;
@@ -967,6 +1065,126 @@ __global__ void k_publish(DevCtx C, int32_t par, uint32_t seq) {
   __hip_atomic_store(&M->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// The arc phase: every work-group claims tiles of the epoch's arc jobs.  A
+// tile expands arcs [t * tile, (t + 1) * tile) of its job with the same
+// steps as a chunk's own expansion (probe, test-and-CAS claim, LDS queue,
+// child entries in bulk); the work-group that expands a job's last tile
+// retires the owner chunk's items, running Phase 3 of a tree whose last
+// items they were.
+template <int WG>
+__device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
+  SchedHdr *H = C.hdr;
+  const int tid = threadIdx.x;
+  const int32_t ntt = C.ntt;
+  const PlainArgs P{};
+  const uint32_t T = min(ld_agent(&H->arc_tiles), (uint32_t)kArcTilesAll);
+  constexpr int A = arcs_per_lane<WG>();
+      static_assert(WG * A <= kClaimQ / 2, "claim queue too small for one step");
+  while (true) {
+    if (tid == 0) L.flag = (int)add_agent(&H->arc_next, 1u);
+    __syncthreads();
+    const uint32_t t = (uint32_t)L.flag;
+    __syncthreads();
+    if (t >= T) break;
+    const int4 td = C.arc_tile[t];
+    const int j = td.x;
+    if (j < 0) continue;   // a reservation whose job was not kept
+    const ArcJob *J = &C.arc_job[j];
+    const int tot = J->tot, tile = J->tile, ntiles = J->ntiles, nseg = J->nseg;
+    const int lt = (int)(t - J->tbase);
+    const int ilo = td.y, ihi = td.z;
+    const int32_t *it = C.arc_item + (size_t)j * kArcItemWords;
+    for (int i = ilo + tid; i <= ihi; i += WG) {
+      V.pre[i] = it[i];
+      V.row[i] = it[kChunk + i];
+      V.seg[i] = it[2 * kChunk + i];
+    }
+    const int32_t *sg = C.arc_seg + J->sbase;
+    for (int q = tid; q < nseg; q += WG) {
+      L.seg_slot[q] = sg[q];
+      L.seg_cen[q] = sg[kArcSegPool + q];
+      L.seg_tb[q] = (uint32_t)sg[2 * kArcSegPool + q];
+      L.seg_tp[q] = (uint32_t)sg[3 * kArcSegPool + q];
+      L.seg_cnt[q] = 0;
+    }
+    if (tid == 0) { L.nseg = nseg; V.qn = 0; }
+    __syncthreads();
+    const int e_lo = lt * tile, e_hi = min(e_lo + tile, tot);
+    int from = ilo;   // arcs in increasing order: item searches only move forward
+    for (int e0 = e_lo; e0 < e_hi; e0 += WG * A) {
+      int32_t u[A], sseg[A];
+      int32_t *dep[A];
+      int32_t dv[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        const int e = e0 + a * WG + tid;
+        sseg[a] = -1;
+        if (e < e_hi) {
+          int lo = from, hi = ihi + 1;   // last item with pre <= e
+          while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
+          from = lo;
+          sseg[a] = V.seg[lo];
+          const TreeStatic *ST = &C.ts[L.seg_slot[sseg[a]]];
+          u[a] = ((const int32_t *)ST->ptr1)[V.row[lo] + (e - V.pre[lo])];
+          dep[a] = (int32_t *)ST->ptr2;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < A; ++a) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;   // probes issued together
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        if (sseg[a] >= 0 && dv[a] == -1 &&
+            atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1) {
+          const int q = atomicAdd(&V.qn, 1);
+          V.qu[q] = u[a];
+          V.qs[q] = (int16_t)sseg[a];
+        }
+      }
+      __syncthreads();
+      const int qn = V.qn;
+      if (qn > kClaimQ - WG * A || e0 + WG * A >= e_hi) {
+        for (int q0 = 0; q0 < qn; q0 += WG) {
+          const int q = q0 + tid;
+          const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
+          if (q < qn) V.qo[q] = o;
+        }
+        seg_commit<WG, true>(C, L, P, false);
+        for (int q = tid; q < qn; q += WG) {
+          const int ss = V.qs[q];
+          const int32_t vb = L.seg_base[ss];
+          if (vb >= 0) {
+            const int64_t c = ((int64_t)L.seg_tb[ss] << 6) + vb + V.qo[q];
+            C.code[c] = (L.seg_cen[ss] + 1) * ntt + (int32_t)(L.seg_tp[ss] & 0xFF);
+            C.a0[c] = V.qu[q];
+          }
+        }
+        __syncthreads();
+        if (tid == 0) V.qn = 0;
+        __syncthreads();
+      }
+    }
+    // the tile's forks are performed before the tile counts as done
+    wait_vmem();
+    __syncthreads();
+    if (tid == 0) L.flag = (add_agent(&((ArcJob *)J)->done, 1u) + 1u == (uint32_t)ntiles) ? 1 : 0;
+    __syncthreads();
+    if (L.flag) {   // the job's last tile: retire the owner chunk's items
+      for (int q = tid; q < nseg; q += WG) {
+        const int sl = L.seg_slot[q];
+        const uint32_t items = (uint32_t)sg[4 * kArcSegPool + q];
+        const uint32_t range = (uint32_t)sg[5 * kArcSegPool + q];
+        const int32_t jv = sg[6 * kArcSegPool + q];
+        const uint32_t joins = (uint32_t)(jv & 0xFFFF);
+        const int32_t v = (int32_t)((uint32_t)jv >> 16);
+        if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
+        const uint64_t prev = add_agent(&C.hot[sl].done, ((uint64_t)joins << 32) | items);
+        if ((uint32_t)prev + items == range) tree_finish(C, sl, (uint32_t)(prev >> 32) + joins);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Grid barrier between epochs (Tenet 1: one arrival per work-group).  Every
 // wavefront waits until its task-vector and state stores have reached the
 // XCD's L2; then one thread writes the L2 back (a release) and arrives.  The
@@ -1004,7 +1222,17 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
   if (L.flag) {
     if (threadIdx.x == 0) fence_acquire();
     __syncthreads();
-    if (with_scan) schedule_scan<WG>(C, L, true);
+    if (with_scan) {
+      // an epoch that published arc jobs has its arc phase first; the
+      // barrier that ends the arc phase builds the next work list
+      if (threadIdx.x == 0) L.flag2 = (ld_agent(&H->arc_tiles) > 0u && H->arc_phase == 0) ? 1 : 0;
+      __syncthreads();
+      if (L.flag2) {
+        if (threadIdx.x == 0) H->arc_phase = 1;
+      } else {
+        schedule_scan<WG>(C, L, true);
+      }
+    }
     wait_vmem();
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1106,12 +1334,53 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     }
     settle(C, pend);
     phase_mark(C, L, 6);
-    const bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
+    bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
+    if constexpr ((OPS & OPS_BFS) != 0) {
+      if (persistent && ok) {
+        if (threadIdx.x == 0) s_hdr[4] = (uint32_t)H->arc_phase;
+        __syncthreads();
+        const bool arcs = s_hdr[4] != 0;
+        __syncthreads();
+        if (arcs) {
+          arc_phase<WG>(C, L, V);
+          ok = grid_barrier<WG>(C, L, true, true);
+        }
+      }
+    }
     phase_mark(C, L, 7);
     if (!persistent || !ok) break;
   }
   if (C.debug && threadIdx.x == 0)
     for (int ph = 0; ph < 8; ++ph) add_agent(&H->phase[ph], (uint64_t)L.prof[ph]);
+}
+
+// The arc phase of a captured chain: launched after each epoch launch of a
+// kernel with BFS; returns at once unless the epoch published arc jobs.  The
+// last work-group to finish builds the next work list (the epoch launch left
+// it for this launch).
+template <int WG, uint32_t OPS>
+__global__ __launch_bounds__(WG) void k_arcs(DevCtx C) {
+  __shared__ Lds<WG> L;
+  __shared__ VisitLds V;
+  __shared__ int32_t s_phase;
+  SchedHdr *H = C.hdr;
+  if (threadIdx.x == 0) s_phase = H->arc_phase;
+  __syncthreads();
+  if (!s_phase) return;
+  lds_init<WG>(C, L);
+  arc_phase<WG>(C, L, V);
+  wait_vmem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    fence_release();
+    L.flag = (add_agent(&H->arc_arrive, 1u) == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (L.flag) {
+    if (threadIdx.x == 0) { fence_acquire(); st_agent(&H->arc_arrive, 0u); }
+    __syncthreads();
+    schedule_scan<WG>(C, L, true);
+  }
 }
 
 // Builds the first work list of a run from the trees' current ranges.
@@ -1239,6 +1508,20 @@ hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int p
   int32_t p = persistent;
   void *args[] = {&c, &p};
   if (persistent) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(wg), args, 0, s);
+  return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, 0, s);
+}
+
+hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s) {
+  const void *fn = nullptr;
+  switch (wg) {
+    case 256: fn = (const void *)&k_arcs<256, OPS_BFS>; break;
+    case 512: fn = (const void *)&k_arcs<512, OPS_BFS>; break;
+    case 1024: fn = (const void *)&k_arcs<1024, OPS_BFS>; break;
+    default: return hipErrorInvalidValue;
+  }
+  (void)need;
+  DevCtx c = C;
+  void *args[] = {&c};
   return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, 0, s);
 }
 

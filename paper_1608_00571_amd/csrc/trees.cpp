@@ -22,6 +22,7 @@ hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t ne
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s);
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
                       hipStream_t s, const hipEvent_t *ev);
+hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s);
 int coresident_blocks_per_cu(int wg, uint32_t need);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
@@ -477,6 +478,12 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
   c->hdr_host->map_ctr = 0;
   c->hdr_host->map_arrive = 0;
   c->hdr_host->chunk_ctr = 0;
+  c->hdr_host->arc_jobs = 0;
+  c->hdr_host->arc_tiles = 0;
+  c->hdr_host->arc_segs = 0;
+  c->hdr_host->arc_next = 0;
+  c->hdr_host->arc_arrive = 0;
+  c->hdr_host->arc_phase = 0;
   HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_scan(c->dc, c->stream));
   return TREES_OK;
@@ -518,6 +525,7 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < c->chunk; ++k) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
+      if (e == hipSuccess && (need & OPS_BFS)) e = launch_arcs(c->dc, c->wg, need, grid, c->stream);
       if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
         e = launch_map(c->dc, kMapWG, 0, 1, c->ncu * 8, c->ncu * 8, c->stream, nullptr);
       if (e != hipSuccess) {
@@ -654,6 +662,10 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   const size_t PC = nomap ? 0 : (size_t)kPartCap;
   const size_t o_mjl = take(MJ * 4), o_mjh = take(MJ * 4), o_mjs = take(MJ * 8), o_mjd = take(MJ * 8),
                o_mjo = take(MJ * 8), o_pj = take(PC * 4), o_pi = take(PC * 8);
+  const size_t o_aj = take((size_t)kArcJobs * sizeof(ArcJob)),
+               o_ai = take((size_t)kArcJobs * kArcItemWords * 4),
+               o_as = take((size_t)7 * kArcSegPool * 4),
+               o_at = take((size_t)kArcTilesAll * sizeof(int4));
   if (hipMalloc(&c->ctl, off) != hipSuccess) return bail(TREES_E_NOMEM, "hipMalloc of control state failed");
   if (hipMemset(c->ctl, 0, off) != hipSuccess) return bail(TREES_E_DEVICE, "hipMemset failed");
   char *b = (char *)c->ctl;
@@ -682,6 +694,10 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.mj_src = (const uint32_t **)(b + o_mjs);
   c->dc.mj_dst = (uint32_t **)(b + o_mjd);
   c->dc.mj_off = (uint64_t *)(b + o_mjo);
+  c->dc.arc_job = (ArcJob *)(b + o_aj);
+  c->dc.arc_item = (int32_t *)(b + o_ai);
+  c->dc.arc_seg = (int32_t *)(b + o_as);
+  c->dc.arc_tile = (int4 *)(b + o_at);
   c->dc.part_job = (uint32_t *)(b + o_pj);
   c->dc.part_ia = (int64_t *)(b + o_pi);
   c->dc.mj_cap = (int32_t)MJ;

@@ -14,6 +14,7 @@
 namespace trees {
 
 constexpr int kMapTile = 4096;     // map phase: merged keys per tile (one work-group)
+constexpr int kChunkItems = 1024;  // work items per work-group chunk of an epoch
 constexpr int kMaxTypes = 31;     // global task-type ids 1..NTT, NTT <= 31
 constexpr int kStackMax = 128;    // stack records per tree
 constexpr int kTraceMax = 256;    // per-epoch trace records per tree
@@ -110,6 +111,15 @@ struct SchedHdr {
   int32_t pad3[29];
   alignas(128) uint32_t chunk_ctr;  // next chunk of the current epoch to hand out
   int32_t pad5[31];
+  alignas(128) uint32_t arc_jobs;   // arc jobs published this epoch
+  uint32_t arc_tiles;               // their tiles
+  uint32_t arc_segs;                // their segment records
+  int32_t pad6[29];
+  alignas(128) uint32_t arc_next;   // next arc tile to hand out in the arc phase
+  int32_t pad7[31];
+  alignas(128) uint32_t arc_arrive; // work-groups done with the arc launch (graph form)
+  int32_t arc_phase;                // 1: the epoch's arc phase is pending (the scan waits for it)
+  int32_t pad8[30];
   int64_t stamp0;                 // device clock when the run's first work list was built
   int64_t stamp[256];             // device clock at the end of each epoch of the run
   uint64_t phase[8];              // debug: summed work-group time per chunk phase (device clock)
@@ -130,6 +140,35 @@ struct PlainCounters {
   int32_t flags[2];
   uint64_t map[2];
 };
+
+// Arc phase (BFS VISIT, Tenet 2 across work-groups, batched forms).  A chunk
+// whose VISIT items have more than kArcLocal arcs does not expand them: it
+// publishes them as a job of tiles and leaves its retirement to the job.
+// After the epoch's chunks, every work-group claims tiles; the work-group
+// that finishes a job's last tile retires the owner chunk's items.  The
+// owner records, for each of its tiles, the job and the items the tile's
+// arcs come from.
+constexpr int kArcJobs = 8192;      // jobs per epoch (beyond: the owner expands locally)
+constexpr int kArcTile = 2048;      // arcs per tile (larger jobs use larger tiles)
+constexpr int kArcTilesMax = 64;    // tiles per job
+constexpr int kArcTilesAll = 1 << 18;   // tiles per epoch
+constexpr int kArcSegPool = 1 << 16;    // segment records per epoch
+constexpr int kArcLocal = 16384;    // chunks with at most this many arcs expand locally
+struct alignas(64) ArcJob {
+  int32_t tot;       // arcs of the job
+  int32_t tile;      // arcs per tile
+  int32_t ntiles;
+  int32_t nseg;      // segments (trees) of the owner's chunk
+  uint32_t tbase;    // global number of the job's first tile
+  uint32_t done;     // tiles expanded
+  uint32_t sbase;    // first segment record of the job in the pool
+  int32_t pad[9];
+};
+// Per job: item arrays pre, row, seg (kChunkItems each, lane-major order of
+// the owner chunk).  Per segment, a record in the pool's seven planes: slot,
+// cen, tb, tp, items (retired by the job), range (the segment's items this
+// epoch) and jv (joins | valid << 16).
+constexpr int kArcItemWords = 3 * kChunkItems;
 
 // Host-visible copy of one epoch's counters (host-mapped, coherent memory),
 // written after the epoch; `seq` is written last and names the launch, so
@@ -181,6 +220,10 @@ struct DevCtx {
   int64_t *part_ia;               // per tile boundary: first-half keys before it (merge path)
   int32_t mj_cap;                 // 0: map disabled, merges run serially in their lane
   int32_t part_cap;               // tile boundaries the partition arrays hold
+  ArcJob *arc_job;                // [kArcJobs]
+  int32_t *arc_item;              // [kArcJobs * kArcItemWords]
+  int32_t *arc_seg;               // [7 * kArcSegPool]: the segment record planes
+  int4 *arc_tile;                 // [kArcTilesAll]: {job, first item, last item, -}
   uint8_t op_of_type[kMaxTypes + 1];
 };
 

@@ -140,6 +140,28 @@ def test_bfs_batch(sched):
         assert_matches_oracle(j)
 
 
+def hub_graph():
+    """Vertex 0 has 50,000 out-arcs (its chunk publishes an arc job); each
+    leaf points into a second layer of 10,000 vertices whose chunks hold 8
+    arcs per vertex (jobs whose tiles span many items)."""
+    V = 60001
+    arcs = [(0, i) for i in range(1, 50001)]
+    arcs += [(i, 50001 + i % 10000) for i in range(1, 50001)]
+    arcs += [(50001 + i, 50001 + (i + d) % 10000) for i in range(10000) for d in range(1, 9)]
+    return inputs.csr_from_arcs(V, arcs, 0)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+@pytest.mark.parametrize("wg", [256, 512, 1024])
+def test_bfs_arc_phase(sched, wg):
+    """Chunks with many arcs hand them to the arc phase; the hub tree and a
+    small tree in the same epochs both match the oracle."""
+    jobs = [Job("bfs", graph=hub_graph()), Job("bfs", graph=inputs.rmat(9, 4))]
+    run_alone(sched, jobs, wg=wg)
+    for j in jobs:
+        assert_matches_oracle(j)
+
+
 @pytest.mark.parametrize("sched", ["graph", "persistent"])
 def test_bfs_full_scale_graph(sched):
     """One graph at the batch's largest scale (2^22 vertices, 2^26 arcs)."""
