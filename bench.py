@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024>": {"src": "6a669e586e71f213", "fetch_bytes": 69688912, "write_bytes": 67109056},
-    "k_plain<FIB>": {"src": "e1544d65023b7a39", "fetch_bytes": 2812591, "write_bytes": 3496531},
-    "k_plain<MS>": {"src": "e1544d65023b7a39", "fetch_bytes": 2230082, "write_bytes": 2353733},
+    "k_map_merge<1024,8192>": {"src": "0879117378d5e2f3", "fetch_bytes": 68792911, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "6761787af3b1cb05", "fetch_bytes": 2813171, "write_bytes": 3496603},
+    "k_plain<MS>": {"src": "6761787af3b1cb05", "fetch_bytes": 2240540, "write_bytes": 2353814},
 }
 
 
@@ -236,21 +236,21 @@ def bench_cfg2(args):
     bm = msort_bytes(N, sm.launched, sm.tasks)
     internal, leaves, merged = msort_counts(N)
     kinds = {"k_plain<FIB>": T.FIB_I64, "k_plain<MS>": T.MSORT_U32,
-             "k_map_part<1024>": 6, "k_map_merge<1024>": 7}
+             "k_map_part<1024,8192>": 6, "k_map_merge<1024,8192>": 7}
     per_step_bytes = {
         "k_plain<FIB>": (bf["tv"], bf["tv"]),
         # the msort epoch kernel: task-vector traffic + leaf sorts (8 B per key)
         "k_plain<MS>": (bm["tv"] + 8 * N, bm["tv"]),
         # the partition pass reads O(log) keys per tile boundary (not counted)
-        "k_map_part<1024>": (0, 0),
+        "k_map_part<1024,8192>": (0, 0),
         # the merge pass reads and writes each key once per merge level
-        "k_map_merge<1024>": (8 * merged, 0),
+        "k_map_merge<1024,8192>": (8 * merged, 0),
     }
     per = {k: dict(ms=kt[kinds[k]][0], launches=kt[kinds[k]][1], bytes=per_step_bytes[k][0],
                    tv=per_step_bytes[k][1]) for k in kinds}
     # The merge pass holds the largest share of device time (rocprofv3 kernel
     # trace of this step); its launches are the ones the roofline covers.
-    dom = "k_map_merge<1024>"
+    dom = "k_map_merge<1024,8192>"
 
     # The measurement: only the dominant kernel's launches carry events.
     r = run_cfg2(args, args.sched, args.steps, args.warmup, key_bufs=key_bufs, keys_np=keys_np,

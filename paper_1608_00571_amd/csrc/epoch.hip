@@ -1270,10 +1270,23 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
 // kernel boundary is the barrier.
 struct NoMapLds {};
 
+// The map merge of the persistent kernel, kept out of line (its registers
+// then do not add to the epoch code's, and the kernel stays small enough for
+// the compiler to inline the chunk); the arguments are plain pointers so that
+// the call needs no copy of the kernel arguments in private memory.
+template <int WG>
+__device__ __noinline__ void map_merge_call(const uint32_t *part_job, const int64_t *part_ia, const uint64_t *mj_off,
+                                            const int32_t *mj_lo, const int32_t *mj_hi,
+                                            const uint32_t *const *mj_src, uint32_t *const *mj_dst,
+                                            MapLds<kMapTile> &M, uint32_t J, uint64_t U) {
+  const MapView v{part_job, part_ia, mj_off, mj_lo, mj_hi, mj_src, mj_dst};
+  map_merge<WG, kMapTile, false>(v, M, J, U);   // (the lean form: fewer registers)
+}
+
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
-  using MapL = typename std::conditional<kMap, MapLds, NoMapLds>::type;
+  using MapL = typename std::conditional<kMap, MapLds<kMapTile>, NoMapLds>::type;
   using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG> L;
   __shared__ MapL M;
@@ -1296,11 +1309,11 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
       if (mapJ) {   // merges registered by the previous epoch: partition, barrier, merge
         uint32_t J;
         uint64_t U;
-        map_extent(C, mapJ, &J, &U);
-        map_partition(C, J, U, (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6),
+        map_extent<kMapTile>(C, mapJ, &J, &U);
+        map_partition<kMapTile>(C, J, U, (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6),
                       (int64_t)gridDim.x * (WG / 64));
         if (!grid_barrier<WG>(C, L, false, true)) break;
-        map_merge<WG>(C, M, J, U);
+        map_merge_call<WG>(C.part_job, C.part_ia, C.mj_off, C.mj_lo, C.mj_hi, C.mj_src, C.mj_dst, M, J, U);
       }
     }
     if (stop) break;

@@ -12,30 +12,32 @@ namespace trees {
 // Map launches (plain and graph forms).  from_hdr: take the job count the
 // last scan recorded; the merge launch clears it when done so that a later
 // launch in a captured chain does not repeat it.
-template <int WG>
+template <int WG, int TILE>
 __global__ __launch_bounds__(WG) void k_map_part(DevCtx C, uint32_t Jarg, int32_t from_hdr) {
   const uint32_t Jraw = from_hdr ? C.hdr->mapJ : Jarg;
   if (!Jraw) return;
   uint32_t J;
   uint64_t U;
-  map_extent(C, Jraw, &J, &U);
+  map_extent<TILE>(C, Jraw, &J, &U);
   // Work-groups are dispatched round-robin over the 8 XCDs (block b on XCD
   // b % 8).  Renumbered this way, each XCD searches a contiguous run of
   // boundaries, whose shared upper probes then hit in its own L2.
   const uint32_t G = gridDim.x;
   const uint32_t v = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
-  map_partition(C, J, U, (int64_t)v * (WG / 64) + (threadIdx.x >> 6), (int64_t)G * (WG / 64));
+  map_partition<TILE>(C, J, U, (int64_t)v * (WG / 64) + (threadIdx.x >> 6), (int64_t)G * (WG / 64));
 }
 
-template <int WG>
-__global__ __launch_bounds__(WG) void k_map_merge(DevCtx C, uint32_t Jarg, int32_t from_hdr) {
-  __shared__ MapLds M;
+// 2048 lanes per CU (8 wavefronts per SIMD): at most 64 registers a lane.
+template <int WG, int TILE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8)))
+void k_map_merge(DevCtx C, uint32_t Jarg, int32_t from_hdr) {
+  __shared__ MapLds<TILE> M;
   const uint32_t Jraw = from_hdr ? C.hdr->mapJ : Jarg;
   if (!Jraw) return;
   uint32_t J;
   uint64_t U;
-  map_extent(C, Jraw, &J, &U);
-  map_merge<WG>(C, M, J, U);
+  map_extent<TILE>(C, Jraw, &J, &U);
+  map_merge<WG, TILE, true>(map_view(C), M, J, U);
   if (from_hdr) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -55,9 +57,10 @@ hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int 
                       hipStream_t s, const hipEvent_t *ev) {
   const void *fp = nullptr, *fm = nullptr;
   switch (wg) {
-    case 256: fp = (const void *)&k_map_part<256>; fm = (const void *)&k_map_merge<256>; break;
-    case 512: fp = (const void *)&k_map_part<512>; fm = (const void *)&k_map_merge<512>; break;
-    case 1024: fp = (const void *)&k_map_part<1024>; fm = (const void *)&k_map_merge<1024>; break;
+    case kMapWG:
+      fp = (const void *)&k_map_part<kMapWG, kMapLaunchTile>;
+      fm = (const void *)&k_map_merge<kMapWG, kMapLaunchTile>;
+      break;
     default: return hipErrorInvalidValue;
   }
   DevCtx c = C;

@@ -36,8 +36,7 @@ namespace {
 
 constexpr int kBytesPerEntry = 28;   // code + a0..a3 (int32) + r (int64)
 constexpr int kMapJobs = 1 << 20;    // map jobs per epoch; merges beyond it run serially
-constexpr uint64_t kMapTileUnits = kMapTile;
-constexpr int kMapWG = 1024;         // map launches: work-group size (a lane merges kMapTile / kMapWG keys)
+constexpr uint64_t kMapTileUnits = kMapLaunchTile;
 constexpr int kPartCap = 1 << 20;    // tile boundaries: 2^32 merged keys per epoch
 
 std::string g_create_error;
@@ -392,7 +391,7 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       const uint64_t units = mc & kMapUnitMask;
       const uint64_t tiles = (units + kMapTileUnits - 1) / kMapTileUnits;
       const uint64_t cap = (uint64_t)c->ncu * 16;
-      const int gm = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
+      const int gm = (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)c->ncu * kMapBlocksPerCU));
       int gp = (int)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 1 + kMapWG / 64 - 1) / (kMapWG / 64), cap));
       gp = (gp + 7) & ~7;   // a multiple of the XCD count (the partition pass maps blocks to XCDs)
       hipEvent_t ev[4] = {};

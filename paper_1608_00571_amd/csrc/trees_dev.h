@@ -13,7 +13,12 @@
 
 namespace trees {
 
-constexpr int kMapTile = 4096;     // map phase: merged keys per tile (one work-group)
+constexpr int kMapTile = 4096;     // map phase inside the persistent kernel: merged keys per tile
+// standalone map launches (plain and graph forms): work-group size and
+// keys per tile (8 a lane)
+constexpr int kMapWG = 1024;
+constexpr int kMapLaunchTile = 8192;
+constexpr int kMapBlocksPerCU = 16;   // plain form: merge work-groups per CU at most (one tile each)
 constexpr int kChunkItems = 1024;  // work items per work-group chunk of an epoch
 constexpr int kMaxTypes = 31;     // global task-type ids 1..NTT, NTT <= 31
 constexpr int kStackMax = 128;    // stack records per tree
