@@ -265,8 +265,9 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
 // ---------------------------------------------------------------------------
 // A tree's finish check whose atomic is still in flight: the work-group that
 // retires a tree's last items of the epoch runs its Phase 3 (tree_finish).
-// The check is made at the next chunk's bookkeeping or after the last chunk,
-// so the atomic's latency overlaps the next chunk.
+// The check is made in the next chunk, once its allocation atomic has
+// returned, or after the last chunk, so the atomic's latency overlaps the
+// next chunk.
 struct PendingFinish {
   int slot = -1;
   uint32_t items = 0, range = 0, joins = 0;
@@ -505,31 +506,6 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       }
     }
   }
-  // Prefetch: when the next chunk of the run lies wholly inside this chunk's
-  // only tree, issue its loads now; they complete while this chunk runs.
-  pf.w0 = 0xFFFFFFFFu;
-  if (kPrefetch) {
-    const uint32_t n0 = w0 + (uint32_t)kChunk;
-    if (n0 < run_end && L.nseg == 1 && L.win[0] >= min(n0 + (uint32_t)kChunk, S)) {
-      const int64_t base = ((int64_t)L.seg_tb[0] << 6) + L.seg_b[0] - (int64_t)L.off0;
-      const int pop = kWide ? L.op_tab[L.seg_tp[0] & 0xFF] : OP_NONE;
-#pragma unroll
-      for (int k = 0; k < IT; ++k) {
-        const uint32_t w = n0 + (uint32_t)(k * WG + tid);
-        pf.code[k] = 0; pf.a0[k] = 0; pf.a1[k] = 0; pf.a2[k] = 0; pf.a3[k] = 0;
-        if (w < S) {
-          const int64_t i = base + (int64_t)w;
-          pf.code[k] = C.code[i];
-          pf.a0[k] = C.a0[i];
-          if (kWide) {
-            if (pop == OP_Q || pop == OP_MS) { pf.a1[k] = C.a1[i]; pf.a2[k] = C.a2[i]; }
-            if (pop == OP_Q) pf.a3[k] = C.a3[i];
-          }
-        }
-      }
-      pf.w0 = n0;
-    }
-  }
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     if (code[k] != 0) {
@@ -707,6 +683,39 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   }
   seg_commit<WG, MULTI>(C, L, P, true);
   phase_mark(C, L, 2);
+  // The previous chunk's finish check: with prefetching, here, where nothing
+  // issued later than its atomic is still in flight (a tree whose last items
+  // that chunk retired has none in this chunk); otherwise at the bookkeeping.
+  if (MULTI && kPrefetch) settle(C, pend);
+  // Prefetch: when the next chunk of the run lies wholly inside this chunk's
+  // only tree, issue its loads now (after the allocation atomic has returned,
+  // before this chunk's stores): they complete during the stores, the
+  // bookkeeping and the barrier.  (Vector memory operations complete in
+  // order, so loads issued before this chunk's own waits would be waited
+  // for there.)
+  pf.w0 = 0xFFFFFFFFu;
+  if (kPrefetch) {
+    const uint32_t n0 = w0 + (uint32_t)kChunk;
+    if (n0 < run_end && L.nseg == 1 && L.win[0] >= min(n0 + (uint32_t)kChunk, S)) {
+      const int64_t base = ((int64_t)L.seg_tb[0] << 6) + L.seg_b[0] - (int64_t)L.off0;
+      const int pop = kWide ? L.op_tab[L.seg_tp[0] & 0xFF] : OP_NONE;
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        const uint32_t w = n0 + (uint32_t)(k * WG + tid);
+        pf.code[k] = 0; pf.a0[k] = 0; pf.a1[k] = 0; pf.a2[k] = 0; pf.a3[k] = 0;
+        if (w < S) {
+          const int64_t i = base + (int64_t)w;
+          pf.code[k] = C.code[i];
+          pf.a0[k] = C.a0[i];
+          if (kWide) {
+            if (pop == OP_Q || pop == OP_MS) { pf.a1[k] = C.a1[i]; pf.a2[k] = C.a2[i]; }
+            if (pop == OP_Q) pf.a3[k] = C.a3[i];
+          }
+        }
+      }
+      pf.w0 = n0;
+    }
+  }
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     const int32_t cb = child_base(L.seg_base, seg[k], nk[k], off[k]);
@@ -855,7 +864,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   __syncthreads();
   phase_mark(C, L, 4);
   const int nseg = L.nseg;
-  if (MULTI) settle(C, pend);
+  if (MULTI && !kPrefetch) settle(C, pend);
   for (int s = tid; s < nseg; s += WG) {
     const int32_t j = L.seg_jv[s] & 0xFFFF;
     const int32_t v = (int32_t)((uint32_t)L.seg_jv[s] >> 16);
