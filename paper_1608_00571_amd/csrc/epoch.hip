@@ -1035,6 +1035,20 @@ __device__ __forceinline__ void lds_init(const DevCtx &C, Lds<WG, NS> &L) {
 // ---------------------------------------------------------------------------
 
 // Plain form: one launch per epoch of one tree; grid covers the range.
+// Publishes a plain epoch's counters to the host: the totals go to the
+// host-mapped mirror, `seq` after the rest has landed, for the host to poll
+// instead of synchronising the stream.  Run by one thread of the epoch's last
+// work-group to finish.
+__device__ void publish(const DevCtx &C, int32_t par, uint32_t seq) {
+  PlainMirror *M = C.mirror;
+  __hip_atomic_store(&M->fj, ld_agent(&C.plain->fj[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&M->map, ld_agent(&C.plain->map[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&M->valid, ld_agent(&C.plain->valid[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&M->flags, ld_agent(&C.plain->flags[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  wait_vmem();
+  __hip_atomic_store(&M->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
@@ -1057,21 +1071,21 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   phase_mark(C, L, 6);
   if (C.debug && threadIdx.x == 0)
     for (int ph = 0; ph < 8; ++ph) add_agent(&C.hdr->phase[ph], (uint64_t)L.prof[ph]);
-}
-
-// Publishes a plain epoch's counters to the host: launched right after the
-// epoch, so the kernel boundary has made every work-group's counter atomics
-// visible.  Stores the totals into the host-mapped mirror, `seq` after the
-// rest has landed, for the host to poll instead of synchronising the stream.
-__global__ void k_publish(DevCtx C, int32_t par, uint32_t seq) {
-  if (threadIdx.x != 0) return;
-  PlainMirror *M = C.mirror;
-  __hip_atomic_store(&M->fj, ld_agent(&C.plain->fj[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(&M->map, ld_agent(&C.plain->map[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(&M->valid, ld_agent(&C.plain->valid[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(&M->flags, ld_agent(&C.plain->flags[par]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  wait_vmem();
-  __hip_atomic_store(&M->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  // The work-group that finishes last publishes the counters.  Every counter
+  // moves only by device-scope atomics, and each work-group's have been
+  // performed before it takes a ticket, so the last ticket sees every
+  // work-group's counts (no cache writeback needed): the atomics whose result
+  // a thread uses are waited for before the barrier; the one that returns
+  // nothing (the valid count, nonzero only when tracing) is waited for here.
+  if (C.trace_on) wait_vmem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = add_agent(&C.plain->ticket, 1u);
+    if (t + 1 == P.nwg) {
+      st_agent(&C.plain->ticket, 0u);   // for the next epoch's launch
+      publish(C, P.par, P.seq);
+    }
+  }
 }
 
 // The arc phase: every work-group claims tiles of the epoch's arc jobs.  A
@@ -1514,13 +1528,9 @@ hipError_t launch_plain(const DevCtx &C, const PlainArgs &P, int wg, uint32_t ne
   dim3 grid((S + kChunk - 1) / kChunk), block(wg);
   DevCtx c = C;
   PlainArgs p = P;
+  p.nwg = grid.x;
   void *args[] = {&c, &p};
-  hipError_t e = hipExtLaunchKernel(fn, grid, block, args, 0, s, ev0, ev1, 0);
-  if (e != hipSuccess) return e;
-  int32_t par = P.par;
-  uint32_t seq = P.seq;
-  void *pargs[] = {&c, &par, &seq};
-  return hipLaunchKernel((const void *)&k_publish, dim3(1), dim3(64), pargs, 0, s);
+  return hipExtLaunchKernel(fn, grid, block, args, 0, s, ev0, ev1, 0);
 }
 
 hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int persistent, hipStream_t s) {

@@ -144,6 +144,7 @@ struct PlainCounters {
   int32_t valid[2];
   int32_t flags[2];
   uint64_t map[2];
+  alignas(128) uint32_t ticket;   // work-groups of the epoch that have finished (own line)
 };
 
 // Arc phase (BFS VISIT, Tenet 2 across work-groups, batched forms).  A chunk
@@ -244,6 +245,7 @@ struct PlainArgs {
   uint32_t seq;   // launch number published in the mirror
   uint32_t tb;    // the tree's arena base / 64
   uint32_t tp;    // its first type id | program parameter << 8 (nqueens n)
+  uint32_t nwg;   // work-groups of the launch (the last to finish publishes); set by the launcher
 };
 
 }  // namespace trees

@@ -60,10 +60,13 @@ def test_msort(sched, nomap):
 @pytest.mark.parametrize("sched", SCHEDS)
 def test_msort_large_map(sched):
     """2^20 + 5 keys (ragged halves): map jobs span many tiles at the top and
-    many jobs share a tile at the bottom; also heavy duplicates."""
-    for n, mod in [((1 << 20) + 5, None), (300000, 7)]:
+    many jobs share a tile at the bottom; also heavy duplicates, and keys equal
+    to the largest key (which the merge pads halves with)."""
+    for n, mod in [((1 << 20) + 5, None), (300000, 7), (200003, "top")]:
         keys = inputs.keys_u32(n, 77 + n)
-        if mod:
+        if mod == "top":   # keys in the top eight values: many equal the largest key
+            keys = keys | np.uint32(0xFFFFFFF8)
+        elif mod:
             keys = keys % np.uint32(mod)
         (j,) = run_alone(sched, [Job("msort", keys=keys)], trace=False)
         assert_matches_oracle(j)
