@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "0879117378d5e2f3", "fetch_bytes": 68792911, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "6761787af3b1cb05", "fetch_bytes": 2813171, "write_bytes": 3496603},
-    "k_plain<MS>": {"src": "6761787af3b1cb05", "fetch_bytes": 2240540, "write_bytes": 2353814},
+    "k_map_merge<1024,8192>": {"src": "88ce0c09d066ee85", "fetch_bytes": 68793125, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "756cf794ed63fc61", "fetch_bytes": 2823055, "write_bytes": 3504857},
+    "k_plain<MS>": {"src": "756cf794ed63fc61", "fetch_bytes": 2239189, "write_bytes": 2354724},
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
     "k_epochs<FIB|NQ>": {"src": "b21b909592f34404", "wg": 512, "fetch_bytes": 10426047367,
                          "write_bytes": 12485966464},
