@@ -15,7 +15,7 @@ Prints one JSON line: tasks/s over the whole step (the metric), epochs/s,
 the roofline of the dominant epoch kernel (algorithmic bytes / HIP-event
 kernel time, against 8 TB/s HBM), and the CPU oracle timed on this host.
 
-    python bench.py [--steps K] [--warmup W] [--config 2|1|3|4] [--sched plain|graph|persistent]
+    python bench.py [--steps K] [--warmup W] [--config 2|1|3|4|5|6] [--sched plain|graph|persistent]
 """
 from __future__ import annotations
 
@@ -272,6 +272,8 @@ def bench_cfg2(args):
             "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 3),
             "algorithmic_bytes_per_launch": int(d["bytes"] / max(1, d["launches"])),
             "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (profiles/plain_fib32_msort2e24.md)"}
+    sp = stream_peak(4 * N)
+    roof["achievable"] = {**sp, "frac": round(achieved / sp["GBps"], 4)}
     kernels = {k: {"ms_per_step": round(v["ms"], 3),
                    "launches_per_step": v["launches"],
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2) if v["ms"] else None,
@@ -420,6 +422,8 @@ def bench_cfg3(args):
                      "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE per run, work-groups of 512 "
                                      "(profiles/batched_4096trees_fib_nqueens.md)"},
     }
+    sp = stream_peak(1 << 30)
+    line["roofline"]["achievable"] = {**sp, "frac": round(ach / sp["GBps"], 4)}
     return line
 
 
@@ -617,6 +621,85 @@ def bench_cfg5(args):
             "p50_ms": l80["p50_ms"], "p99_ms": l80["p99_ms"], "serving": out}
 
 
+def bench_cfg6(args):
+    """Figure 2's postorder program over a random binary tree of 2^log2tree
+    nodes (a widening beyond the five configurations): every scheduler; each
+    run's visit log is checked against the tree (every node once, after its
+    children)."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1608_00571_amd as T
+
+    n = 1 << args.log2tree
+    left, right = inputs.postorder_tree(n)
+    lt, rt = torch.from_numpy(left).to("cuda"), torch.from_numpy(right).to("cuda")
+    log = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    arena = (T.tv_bound(T.POSTORDER, [n, 0]) + 64) * T.BYTES_PER_ENTRY
+    pos = np.empty(n, dtype=np.int64)
+    out = {}
+    st = None
+    for sched in ("graph", "persistent", "plain"):
+        ctx = T.Context(arena, sched=sched, wg=args.wg, max_trees=2)
+        prog = ctx.register(T.POSTORDER)
+        times = []
+        for it in range(args.warmup + args.steps):
+            t = ctx.submit(prog, [n, 0], [lt, rt, log])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.run()
+            dt = time.perf_counter() - t0
+            _, st = ctx.results(t)
+            if it >= args.warmup:
+                times.append(dt)
+        ctx.close()
+        lg = log.cpu().numpy()
+        assert lg[n] == n, f"postorder {sched}: {lg[n]} visits of {n} nodes"
+        pos[lg[:n]] = np.arange(n)
+        for arr in (left, right):
+            has = arr >= 0
+            assert np.all(pos[arr[has]] < pos[has]), f"postorder {sched}: a node visited before its child"
+        dt = sum(times) / len(times)
+        out[sched] = {"tasks_per_s": st.tasks / dt, "ms": round(dt * 1e3, 3),
+                      "epochs_per_s": st.epochs / dt}
+    best = max(("graph", "persistent"), key=lambda k: out[k]["tasks_per_s"])
+    return {
+        "metric": "tasks/s", "value": out[best]["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[best]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"postorder (Figure 2) of a random binary tree with 2^{args.log2tree} nodes",
+                   "sched": best, "wg": args.wg, "tasks": st.tasks, "epochs": st.epochs},
+        "epochs_per_s": out[best]["epochs_per_s"],
+        "schedulers": out,
+        "batched_vs_plain_factor": round(out[best]["tasks_per_s"] / out["plain"]["tasks_per_s"], 2),
+    }
+
+
+def stream_peak(bytes_each_way: int) -> dict:
+    """Achievable streaming bandwidth on this GPU: an int32 elementwise kernel
+    that reads and writes `bytes_each_way` bytes per launch (capped at 1 GiB),
+    timed with events over 20 launches.  The roofline reports its kernel's
+    rate against this beside the data-sheet peak."""
+    import torch
+    n = max(1, min(bytes_each_way, 1 << 30) // 4)
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.bitwise_not(src, out=dst)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(20):
+        torch.bitwise_not(src, out=dst)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / 20
+    del src, dst
+    return {"GBps": round(8 * n / us / 1e3, 1), "bytes_per_launch": 8 * n,
+            "kernel": "int32 elementwise read + write (torch bitwise_not)"}
+
+
 def calib_copy(args):
     """Counter calibration: a streaming elementwise kernel over int32 buffers
     (reads and writes each byte once, like a copy) of --calib-mib MiB, run
@@ -649,6 +732,7 @@ def main():
     ap.add_argument("--wg", type=int, default=0,
                     help="epoch-kernel work-group size (default: 1024 for the plain scheduler, 256 batched)")
     ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--log2tree", type=int, default=22, help="config 6: postorder tree of 2^k nodes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--trees", type=int, default=4096)
     ap.add_argument("--graphs", type=int, default=64)
@@ -681,6 +765,8 @@ def main():
         line = bench_cfg4(args)
     elif args.config == 5:
         line = bench_cfg5(args)
+    elif args.config == 6:
+        line = bench_cfg6(args)
     elif args.config == 2:
         line = bench_cfg2(args)
         if not args.no_cpu:

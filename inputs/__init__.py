@@ -63,6 +63,7 @@ def lib():
         L.tin_uniform.argtypes = [u64, u64, i64, i64]
         L.tin_keys_u32.argtypes = [u64, i64, vp]
         L.tin_permutation.argtypes = [u64, i64, vp]
+        L.tin_binary_tree.argtypes = [u64, i64, vp, vp]
         L.tin_rmat_edges.argtypes = [i32, i64, u64, vp, vp, vp]
         L.tin_relabel.argtypes = [i64, vp, vp]
         L.tin_csr.argtypes = [i64, i64, vp, vp, vp, vp]
@@ -112,6 +113,22 @@ def permutation(seed: int, n: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # Sort keys
 # ----------------------------------------------------------------------------
+def binary_tree(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """(left, right) child arrays of a random binary tree of n nodes rooted
+    at node 0 (-1 = no child): node v hangs below a uniform earlier node, on a
+    uniform side, redrawn while that slot is taken."""
+    left = np.empty(max(n, 0), dtype=np.int32)
+    right = np.empty(max(n, 0), dtype=np.int32)
+    if n:
+        lib().tin_binary_tree(seed, n, left.ctypes.data, right.ctypes.data)
+    return left, right
+
+
+def postorder_tree(n: int = 1 << 22) -> tuple[np.ndarray, np.ndarray]:
+    """The postorder workload: a random binary tree of n nodes."""
+    return binary_tree(n, item_seed(6, 0))
+
+
 def keys_u32(n: int, seed: int) -> np.ndarray:
     out = np.empty(n, dtype=np.uint32)
     if n:

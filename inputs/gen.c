@@ -56,6 +56,21 @@ void tin_permutation(uint64_t seed, int64_t n, int32_t *perm) {
     }
 }
 
+/* A random binary tree of n nodes rooted at node 0: node v (v = 1..n-1)
+ * becomes a child of node p = uniform[0, v-1] on side s = uniform[0, 1]
+ * (0 = left), taken from draw indices v*64 + k and v*64 + k + 32 for the
+ * k-th try; a try whose slot is taken is redrawn.  -1 = no child. */
+void tin_binary_tree(uint64_t seed, int64_t n, int32_t *left, int32_t *right) {
+    for (int64_t v = 0; v < n; ++v) left[v] = right[v] = -1;
+    for (int64_t v = 1; v < n; ++v) {
+        for (uint64_t k = 0;; ++k) {
+            const int64_t p = uni(seed, (uint64_t)v * 64 + k, 0, v - 1);
+            int32_t *side = uni(seed, (uint64_t)v * 64 + k + 32, 0, 1) == 0 ? left : right;
+            if (side[p] == -1) { side[p] = (int32_t)v; break; }
+        }
+    }
+}
+
 /*
  * R-MAT edge list (Chakrabarti, Zhan, Faloutsos, SDM 2004).  Edge j descends
  * `scale` quadrant levels, most significant bit first.  Level l uses one

@@ -30,8 +30,9 @@ PLAIN, GRAPH, PERSISTENT, AUTO = 0, 1, 2, 3
 SCHEDS = {"plain": PLAIN, "graph": GRAPH, "persistent": PERSISTENT, "auto": AUTO}
 
 # built-in programs
-FIB_I32, FIB_I64, MSORT_U32, NQUEENS, BFS_CSR = 1, 2, 3, 4, 5
-PROGRAMS = {"fib32": FIB_I32, "fib64": FIB_I64, "msort": MSORT_U32, "nqueens": NQUEENS, "bfs": BFS_CSR}
+FIB_I32, FIB_I64, MSORT_U32, NQUEENS, BFS_CSR, POSTORDER = 1, 2, 3, 4, 5, 6
+PROGRAMS = {"fib32": FIB_I32, "fib64": FIB_I64, "msort": MSORT_U32, "nqueens": NQUEENS, "bfs": BFS_CSR,
+            "postorder": POSTORDER}
 
 F_TRACE, F_DEBUG, F_PROFILE, F_NOMAP = 1, 2, 4, 8
 BYTES_PER_ENTRY = 28
@@ -307,11 +308,12 @@ class Context:
 
     def kernel_times(self):
         """{kind: (ms, launches)}: HIP-event timed epoch launches; kind 0 =
-        batched launches, kinds 6 and 7 = the plain scheduler's map phase
-        (partition pass, merge pass)."""
-        arr = (_KTime * 8)()
-        self._check(lib().trees_kernel_times(self.h, arr, 8), "kernel_times")
-        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(8)}
+        batched launches, kinds 1..5 = the plain scheduler's epochs per
+        program kind, 6 and 7 = its map phase (partition pass, merge pass),
+        8 = its postorder epochs."""
+        arr = (_KTime * 9)()
+        self._check(lib().trees_kernel_times(self.h, arr, 9), "kernel_times")
+        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(9)}
 
     def epoch_times(self) -> np.ndarray:
         """Per-epoch device-clock durations (us) of the last batched run."""

@@ -592,7 +592,51 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       case OP_VISIT:
         act[k] = ACT_FINISH;   // its arcs are expanded co-operatively below
         break;
+      case OP_POST: {
+        // Figure 2: postorder(node) forks postorder(right), postorder(left)
+        // and joins a visit of node; postorder(-1) ends.
+        const int32_t node = a0v[k], n = (int32_t)(tp[k] >> 8);
+        act[k] = ACT_FINISH;
+        if (node < 0) break;
+        if (node >= n) {   // not a node of this tree: an error of the tree
+          L.sink = or_agent(MULTI ? &C.hot[slot[k]].flags : &C.plain->flags[P.par], (int32_t)TF_ENCODING);
+          break;
+        }
+        const TreeStatic *T = &C.ts[slot[k]];
+        act[k] = ACT_JOIN; nk[k] = 2;
+        x0[k] = node;
+        x1[k] = ((const int32_t *)T->ptr1)[node];   // right child, forked first
+        x2[k] = ((const int32_t *)T->ptr0)[node];   // left child
+      } break;
+      case OP_PVISIT:
+        act[k] = ACT_FINISH;   // the visit: appended to the tree's log below
+        break;
       default: break;
+    }
+  }
+
+  // ---- postorder visits: each appends its node to the tree's log, whose
+  // last word (log[n]) counts the visits; one atomic per wavefront when its
+  // visiting lanes share a tree
+  if constexpr ((OPS & OPS_PO) != 0) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const bool vis = op[k] == OP_PVISIT;
+      const uint64_t m = ballot64(vis);
+      if (!m) continue;
+      int32_t *log = vis ? (int32_t *)C.ts[slot[k]].ptr2 : nullptr;
+      const int32_t n = (int32_t)(tp[k] >> 8);
+      int32_t pos = 0;
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      const int s0 = __shfl(seg[k], leader, 64);
+      if (__all(!vis || seg[k] == s0)) {
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&log[n], __popcll(m));
+        pos = __shfl(base, leader, 64) + mbcnt64(m);
+      } else if (vis) {
+        pos = atomicAdd(&log[n], 1);
+      }
+      if (vis && pos < n) log[pos] = a0v[k];   // (more visits than nodes: the input was no tree)
     }
   }
 
@@ -745,6 +789,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         const int32_t mid = x0[k] + (x1[k] - x0[k]) / 2;
         C.code[c] = nxt; C.a0[c] = x0[k]; C.a1[c] = mid; C.a2[c] = x2[k] + 1;
         C.code[c + 1] = nxt; C.a0[c + 1] = mid; C.a1[c + 1] = x1[k]; C.a2[c + 1] = x2[k] + 1;
+      } else if (op[k] == OP_POST) {
+        C.code[c] = nxt; C.a0[c] = x1[k];
+        C.code[c + 1] = nxt; C.a0[c + 1] = x2[k];
       }
     }
     // ---- join / emit: writes to the item's own entry ----------------------
@@ -755,8 +802,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
     } else if (act[k] == ACT_FINISH) {
       C.code[i] = 0;
     } else if (act[k] == ACT_JOIN) {
-      C.code[i] = cen[k] * ntt + (int32_t)(tp[k] & 0xFF) + 1;   // local type 2: SUM / QSUM / MERGE
-      if (op[k] != OP_MS) {
+      C.code[i] = cen[k] * ntt + (int32_t)(tp[k] & 0xFF) + 1;   // local type 2: SUM / QSUM / MERGE / visit
+      if (op[k] != OP_MS && op[k] != OP_POST) {   // (their joins keep their own arguments)
         C.a0[i] = cb;
         if (op[k] == OP_Q) C.a1[i] = nk[k];
       }

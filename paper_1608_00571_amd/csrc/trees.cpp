@@ -68,6 +68,7 @@ uint32_t ops_of_kind(int kind) {
     case TREES_PROG_MSORT_U32: return OPS_MS;
     case TREES_PROG_NQUEENS: return OPS_NQ;
     case TREES_PROG_BFS_CSR: return OPS_BFS;
+    case TREES_PROG_POSTORDER: return OPS_PO;
   }
   return 0;
 }
@@ -142,6 +143,13 @@ trees_status tv_bound(int kind, const int64_t *args, int nargs, int64_t *out, st
         return bad("bfs: need V >= 1 and 0 <= source < V");
       *out = args[0];
       return TREES_OK;
+    case TREES_PROG_POSTORDER:
+      // every postorder task (the root and two per node, null children
+      // included) holds one entry; a join reuses its own
+      if (nargs < 2 || args[0] < 1 || args[0] >= (1ll << 24) || args[1] < -1 || args[1] >= args[0])
+        return bad("postorder: need 1 <= n < 2^24 and -1 <= root < n");
+      *out = 2 * args[0] + 1;
+      return TREES_OK;
   }
   return bad("unknown program kind");
 }
@@ -193,8 +201,8 @@ struct trees_ctx {
   // last epoch, so timing adds no synchronisation per epoch
   std::vector<hipEvent_t> evpool;
   std::vector<std::pair<int, size_t>> evpend;   // (ktime slot, first event of the pair)
-  trees_ktime ktime[8] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes
-  uint32_t prof_mask = 0xFFu;  // which of the slots above are timed
+  trees_ktime ktime[9] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes, 8 plain postorder
+  uint32_t prof_mask = 0x1FFu;  // which of the slots above are timed
   double clock_hz = 1e8;
   double timeout_s = 60.0;   // host and device waits give up after this long
   bool running = false;
@@ -376,7 +384,8 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
     P.seq = ++c->plain_seq ? c->plain_seq : ++c->plain_seq;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed(c, t.kind)) TRY(take_events(c, t.kind, &e0, &e1));
+    const int kslot = t.kind == TREES_PROG_POSTORDER ? 8 : t.kind;   // (6 and 7 are the map passes)
+    if (timed(c, kslot)) TRY(take_events(c, kslot, &e0, &e1));
     HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream, e0, e1));
     TRY(wait_mirror(c, P.seq));
     const PlainMirror mir = *c->mirror;
@@ -777,6 +786,7 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
     case TREES_PROG_MSORT_U32: c->dc.op_of_type[p.tbase] = OP_MS; c->dc.op_of_type[p.tbase + 1] = OP_MERGE; break;
     case TREES_PROG_NQUEENS: c->dc.op_of_type[p.tbase] = OP_Q; c->dc.op_of_type[p.tbase + 1] = OP_QSUM; break;
     case TREES_PROG_BFS_CSR: c->dc.op_of_type[p.tbase] = OP_VISIT; break;
+    case TREES_PROG_POSTORDER: c->dc.op_of_type[p.tbase] = OP_POST; c->dc.op_of_type[p.tbase + 1] = OP_PVISIT; break;
   }
   c->dc.ntt = c->ntt;
   c->progs.push_back(p);
@@ -830,6 +840,22 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       a.ts.ptr1 = (uint64_t)bufs[1].ptr;
       a.ts.ptr2 = (uint64_t)bufs[2].ptr;
     } break;
+    case TREES_PROG_POSTORDER: {
+      const int64_t n = args[0];
+      if (nbufs < 3 || !bufs || !bufs[0].ptr || !bufs[1].ptr || !bufs[2].ptr ||
+          bufs[0].bytes < (uint64_t)n * 4 || bufs[1].bytes < (uint64_t)n * 4 ||
+          bufs[2].bytes < (uint64_t)(n + 1) * 4)
+        return fail(c, TREES_E_INVALID, "postorder: need bufs {left[n], right[n], log[n+1]} of int32");
+      a.a0 = (int32_t)args[1];
+      a.ts.p0 = (int32_t)n;
+      a.ts.p1 = (int32_t)args[1];
+      a.ts.ptr0 = (uint64_t)bufs[0].ptr;
+      a.ts.ptr1 = (uint64_t)bufs[1].ptr;
+      a.ts.ptr2 = (uint64_t)bufs[2].ptr;
+      // the visit counter (log[n]) starts at zero, before the tree's first epoch
+      if (hipMemsetAsync((int32_t *)bufs[2].ptr + n, 0, 4, c->stream) != hipSuccess)
+        return fail(c, TREES_E_DEVICE, "postorder: clearing the visit counter failed");
+    } break;
   }
   int slot = -1;
   for (int s = 0; s < c->tmax; ++s)
@@ -848,7 +874,10 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   t.base = base;
   t.cap = bound;
   t.order = c->order++;
-  t.tp = (uint32_t)P.tbase | ((P.kind == TREES_PROG_NQUEENS ? (uint32_t)args[0] : 0u) << 8);
+  // the kernels' per-tree parameter: nqueens n, or postorder's node count
+  // (its visit counter sits at log[n])
+  const bool with_n = P.kind == TREES_PROG_NQUEENS || P.kind == TREES_PROG_POSTORDER;
+  t.tp = (uint32_t)P.tbase | ((with_n ? (uint32_t)args[0] : 0u) << 8);
   a.ts.tp = t.tp;
   c->staged.push_back(a);
   if (P.kind == TREES_PROG_BFS_CSR)
@@ -995,7 +1024,7 @@ trees_status trees_profile_mask(trees_ctx *c, uint32_t mask) {
   if (!c) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
-  c->prof_mask = mask & 0xFFu;
+  c->prof_mask = mask & 0x1FFu;
   return TREES_OK;
 }
 
@@ -1003,8 +1032,7 @@ trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
   if (!c || !out) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
-  for (int k = 0; k < n && k < 6; ++k) out[k] = c->ktime[k];
-  for (int k = 6; k < n && k < 8; ++k) out[k] = c->ktime[k];
+  for (int k = 0; k < n && k < 9; ++k) out[k] = c->ktime[k];
   return TREES_OK;
 }
 

@@ -33,14 +33,16 @@ enum Op : int32_t {
   OP_MS = 5, OP_MERGE = 6,
   OP_Q = 7, OP_QSUM = 8,
   OP_VISIT = 9,
-  OP_COUNT = 10
+  OP_POST = 10, OP_PVISIT = 11,
+  OP_COUNT = 12
 };
 constexpr uint32_t opbit(int op) { return 1u << op; }
 constexpr uint32_t OPS_FIB = opbit(OP_FIB32) | opbit(OP_SUM32) | opbit(OP_FIB64) | opbit(OP_SUM64);
 constexpr uint32_t OPS_NQ = opbit(OP_Q) | opbit(OP_QSUM);
 constexpr uint32_t OPS_MS = opbit(OP_MS) | opbit(OP_MERGE);
 constexpr uint32_t OPS_BFS = opbit(OP_VISIT);
-constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS;
+constexpr uint32_t OPS_PO = opbit(OP_POST) | opbit(OP_PVISIT);
+constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS | OPS_PO;
 
 // Tree status values (TreeState::status).
 enum : int32_t { TS_FREE = 0, TS_LIVE = 1, TS_DONE = 2, TS_PAUSED = 3 };

@@ -6,7 +6,7 @@ import numpy as np
 
 SCHEDS = ["plain", "graph", "persistent"]
 
-KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5}
+KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6}
 
 
 def to_dev_u32(a: np.ndarray):
@@ -32,8 +32,9 @@ def register_all(ctx, jobs):
 class Job:
     """One tree: its spec, payload tensors and, after collect(), its outputs."""
 
-    def __init__(self, kind: str, n=None, keys=None, graph=None):
-        self.kind, self.n, self.keys, self.graph = kind, n, keys, graph
+    def __init__(self, kind: str, n=None, keys=None, graph=None, bintree=None):
+        # bintree (postorder): (left, right, root) int32 child arrays, -1 = none
+        self.kind, self.n, self.keys, self.graph, self.bintree = kind, n, keys, graph, bintree
         self.tree = None
         self.value = None
         self.stats = None
@@ -60,6 +61,12 @@ class Job:
             d = torch.empty(g.V, dtype=torch.int32, device="cuda")
             self.bufs = (rp, ci, d)
             self.tree = ctx.submit(prog, [g.V, g.source], [rp, ci, d])
+        elif self.kind == "postorder":
+            left, right, root = self.bintree
+            lt, rt = to_dev_i32(left), to_dev_i32(right)
+            log = torch.full((left.shape[0] + 1,), -7, dtype=torch.int32, device="cuda")
+            self.bufs = (lt, rt, log)
+            self.tree = ctx.submit(prog, [left.shape[0], root], [lt, rt, log])
         else:
             raise ValueError(self.kind)
         return self.tree
@@ -72,6 +79,8 @@ class Job:
             self.out = from_dev_u32(self.bufs[0])
         elif self.kind == "bfs":
             self.out = self.bufs[2].cpu().numpy()
+        elif self.kind == "postorder":
+            self.out = self.bufs[2].cpu().numpy()   # visit log, then the visit count
         return self
 
 
@@ -91,17 +100,40 @@ def oracle_run(job: Job):
         g = job.graph
         d, r = oracle.bfs(g.V, g.row_ptr, g.col_idx, g.source, records=True)
         return r, d
+    if job.kind == "postorder":
+        left, right, root = job.bintree
+        log, _, r = oracle.postorder(left, right, root, records=True)
+        return r, log
     raise ValueError(job.kind)
+
+
+def check_postorder_log(job: Job, want_log: np.ndarray):
+    """The GPU's visit log holds each visited node once, the same nodes as the
+    oracle's, and every node after its children (the order of visits within
+    one epoch is not unique, so the logs are not compared entry by entry)."""
+    left, right, _ = job.bintree
+    n = left.shape[0]
+    cnt = int(job.out[n])
+    assert cnt == len(want_log), f"postorder: {cnt} visits, oracle {len(want_log)}"
+    log = job.out[:cnt]
+    assert np.array_equal(np.sort(log), np.sort(want_log)), "postorder: visited nodes differ"
+    pos = np.full(n, -1, dtype=np.int64)
+    pos[log] = np.arange(cnt)
+    for child in (left, right):
+        has = (pos >= 0) & (child >= 0)
+        assert np.all(pos[child[has]] < pos[has]), "postorder: a node visited before its child"
 
 
 def assert_matches_oracle(job: Job, check_trace=True):
     want, out = oracle_run(job)
     s = job.stats
-    got = (job.value if job.kind not in ("msort", "bfs") else want.result, s.epochs, s.tasks,
+    got = (job.value if job.kind not in ("msort", "bfs", "postorder") else want.result, s.epochs, s.tasks,
            s.launched, s.peak_entries)
     exp = (want.result, want.epochs, want.tasks, want.launched, want.peak)
     assert got == exp, f"{job.kind} {job.n}: got {got} want {exp}"
-    if out is not None:
+    if job.kind == "postorder":
+        check_postorder_log(job, out)
+    elif out is not None:
         assert np.array_equal(job.out, out), f"{job.kind}: output differs"
     if check_trace and job.trace is not None and want.records is not None:
         n = min(len(job.trace), 256)

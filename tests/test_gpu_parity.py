@@ -89,6 +89,37 @@ def test_bfs(sched):
         assert_matches_oracle(j)
 
 
+def bintree(left, right, root):
+    return (np.asarray(left, dtype=np.int32), np.asarray(right, dtype=np.int32), root)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_postorder_fig3(sched, golden_dir):
+    """Figure 2's postorder program on the paper's worked example: the
+    per-epoch trace is Figure 3's (CEN 0,1,2,3,2,1,0; 4 lanes launched and 3
+    valid when CEN first falls back to 2)."""
+    from tests.test_oracle_tvm import read_fig3
+    left, right, want = read_fig3(golden_dir)
+    (j,) = run_alone(sched, [Job("postorder", bintree=bintree(left, right, 0))])
+    assert_matches_oracle(j)
+    got = [(int(r["epoch"]), int(r["cen"]), int(r["b"]), int(r["e"]) - 1, int(r["launched"]), int(r["valid"]))
+           for r in j.trace]
+    assert got == want
+    assert j.stats.peak_entries == 13
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_postorder_random_trees(sched):
+    """Random binary trees up to 20,000 nodes (up to 40,001 tasks an epoch
+    apart in the widest epochs), a one-node tree and the empty tree."""
+    jobs = [Job("postorder", bintree=bintree(*inputs.binary_tree(n, seed), 0))
+            for n, seed in [(1, 0), (2, 5), (300, 3), (20000, 7)]]
+    jobs.append(Job("postorder", bintree=bintree([-1], [-1], -1)))
+    for j in jobs:
+        (j,) = run_alone(sched, [j])
+        assert_matches_oracle(j)
+
+
 @pytest.mark.parametrize("sched", ["graph", "persistent"])
 def test_mixed_batch_equals_alone(sched):
     """Independent trees of every program share epochs; each tree's result,
@@ -101,6 +132,7 @@ def test_mixed_batch_equals_alone(sched):
     jobs.append(Job("msort", keys=inputs.keys_u32(64, 6)))
     jobs.append(Job("bfs", graph=inputs.rmat(9, 4)))
     jobs.append(Job("bfs", graph=inputs.csr_from_arcs(5, [(0, 1), (1, 2), (2, 3), (3, 4)], 0)))
+    jobs.append(Job("postorder", bintree=bintree(*inputs.binary_tree(500, 11), 0)))
     with make_ctx(sched) as ctx:
         register_all(ctx, jobs)
         for j in jobs:

@@ -84,3 +84,23 @@ def test_serving_trace():
         assert abs(kinds.count(k) / len(kinds) - p) < 0.04
     ms = [r.size for r in tr if r.kind == "msort"]
     assert min(ms) >= 1 << 10 and max(ms) <= 1 << 22
+
+
+def test_binary_tree_matches_scalar_draws():
+    """The C tree generator takes the same draws as the scalar definition
+    (the oracle's postorder tests build their trees that way)."""
+    from tests.test_oracle_tvm import random_tree
+    for n, seed in [(1, 0), (7, 1), (40, 2), (300, 3), (2000, 9)]:
+        left, right = random_tree(n, seed)
+        L, R = inputs.binary_tree(n, seed)
+        assert L.tolist() == left and R.tolist() == right
+
+
+def test_binary_tree_is_a_tree():
+    L, R = inputs.binary_tree(5000, 4)
+    ch = np.concatenate([L[L >= 0], R[R >= 0]])
+    assert len(ch) == 4999 and len(np.unique(ch)) == 4999 and 0 not in ch
+    # every child comes after its parent
+    for arr in (L, R):
+        has = arr >= 0
+        assert np.all(arr[has] > np.nonzero(has)[0])
