@@ -113,6 +113,19 @@ def permutation(seed: int, n: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # Sort keys
 # ----------------------------------------------------------------------------
+def arc_weights(E: int, seed: int, lo: int = 1, hi: int = 100) -> np.ndarray:
+    """int32 arc weights uniform on [lo, hi]: weight i = lo + (high 32 bits
+    of draw(seed, i)) * (hi - lo + 1) >> 32, the scalar `uniform` rule."""
+    k = keys_u32(E, seed).astype(np.uint64)
+    return (lo + ((k * np.uint64(hi - lo + 1)) >> np.uint64(32))).astype(np.int32)
+
+
+def sssp_graph(scale: int, seed: int, lo: int = 1, hi: int = 100) -> tuple[Graph, np.ndarray]:
+    """An R-MAT graph (as for BFS) with arc weights uniform on [lo, hi]."""
+    g = rmat(scale, seed)
+    return g, arc_weights(g.col_idx.shape[0], sub_seed(seed, 77), lo, hi)
+
+
 def binary_tree(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """(left, right) child arrays of a random binary tree of n nodes rooted
     at node 0 (-1 = no child): node v hangs below a uniform earlier node, on a

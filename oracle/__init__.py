@@ -9,10 +9,10 @@ Thin ctypes wrapper over ``trees_oracle.c``:
 
 * plain sequential evaluators (the results the method must reach):
   :func:`fib_iter`, :func:`fib_rec`, :func:`nqueens_rec`, :func:`sort_u32`,
-  :func:`msort_rec`, :func:`bfs_queue`;
+  :func:`msort_rec`, :func:`bfs_queue`, :func:`dijkstra`;
 * the epoch-semantics emulator (Task Vector Machine, Section 4.3, in the
   TREES representation of Sections 5.1.2-5.2.4): :func:`fib`,
-  :func:`nqueens`, :func:`msort`, :func:`bfs`, :func:`postorder`,
+  :func:`nqueens`, :func:`msort`, :func:`bfs`, :func:`sssp`, :func:`postorder`,
   :func:`run_batch`, plus checkpoint / resume at an epoch boundary.
 
 Every function here is pinned by ``tests/test_oracle_*.py`` against closed
@@ -32,7 +32,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trees_oracle.c")
 LIB_PATH = os.path.join(_HERE, "libtrees_oracle.so")
 
-FIB32, FIB64, MSORT, NQUEENS, BFS, POSTORDER = 1, 2, 3, 4, 5, 6
+FIB32, FIB64, MSORT, NQUEENS, BFS, POSTORDER, SSSP = 1, 2, 3, 4, 5, 6, 7
+UNREACHED = 2**31 - 1   # SSSP distance of a vertex the source does not reach
 E_OVERFLOW, E_ENCODING = -3, -8
 
 REC_DTYPE = np.dtype([(n, np.int32) for n in
@@ -73,6 +74,7 @@ def lib():
         L.orc_sort_u32.argtypes = [vp, i64]
         L.orc_msort_rec.argtypes = [vp, vp, i64]
         L.orc_bfs_queue.argtypes = [i32, vp, vp, i32, vp]
+        L.orc_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
         L.orc_new.restype = vp
         L.orc_new.argtypes = [i32, i32, i32, vp, vp, vp, vp, i64]
         L.orc_free.argtypes = [vp]
@@ -132,6 +134,17 @@ def msort_rec(keys: np.ndarray) -> np.ndarray:
     t = np.empty_like(a)
     lib().orc_msort_rec(a.ctypes.data, t.ctypes.data, a.shape[0])
     return a
+
+
+def dijkstra(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, weights: np.ndarray, source: int) -> np.ndarray:
+    """Shortest distances from `source` over non-negative int32 arc weights
+    (the plain definition SSSP reaches); UNREACHED for unreachable vertices."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    w = np.ascontiguousarray(weights, dtype=np.int32)
+    d = np.empty(V, dtype=np.int32)
+    lib().orc_dijkstra(V, rp.ctypes.data, ci.ctypes.data, w.ctypes.data, source, d.ctypes.data)
+    return d
 
 
 def bfs_queue(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, source: int) -> np.ndarray:
@@ -245,6 +258,20 @@ def bfs(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, source: int, records: 
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     d = np.empty(V, dtype=np.int32)
     em = Emulator(BFS, V, source, ptrs=(rp, ci, d, None), cap=cap, records=records)
+    em.run()
+    return d, em.stats()
+
+
+def sssp(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, weights: np.ndarray, source: int,
+         records: bool = False, cap: int = 0) -> tuple[np.ndarray, Run]:
+    """The relaxation program in the epoch emulator: distances (UNREACHED
+    for unreachable vertices) and the statistics of this one schedule (task
+    counts depend on the order of relaxations inside an epoch)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    w = np.ascontiguousarray(weights, dtype=np.int32)
+    d = np.empty(V, dtype=np.int32)
+    em = Emulator(SSSP, V, source, ptrs=(rp, ci, w, d), cap=cap, records=records)
     em.run()
     return d, em.stats()
 

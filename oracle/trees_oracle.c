@@ -134,11 +134,51 @@ void orc_bfs_queue(int32_t V, const int32_t *row_ptr, const int32_t *col, int32_
     free(q);
 }
 
+/* Shortest distances from src over non-negative int32 arc weights
+ * (Dijkstra, binary heap with lazy deletion); unreachable = INT32_MAX. */
+void orc_dijkstra(int32_t V, const int32_t *row_ptr, const int32_t *col, const int32_t *w,
+                  int32_t src, int32_t *dist) {
+    for (int32_t v = 0; v < V; ++v) dist[v] = INT32_MAX;
+    if (V <= 0) return;
+    int64_t cap = (int64_t)row_ptr[V] + 1, n = 0;
+    int64_t *hd = (int64_t *)malloc((size_t)cap * sizeof(int64_t));   /* key = dist << 32 | vertex */
+    dist[src] = 0;
+    hd[n++] = (int64_t)src;
+    while (n > 0) {
+        const int64_t top = hd[0];
+        hd[0] = hd[--n];
+        for (int64_t i = 0;;) {                                        /* sift down */
+            int64_t l = 2 * i + 1, r = l + 1, m = i;
+            if (l < n && hd[l] < hd[m]) m = l;
+            if (r < n && hd[r] < hd[m]) m = r;
+            if (m == i) break;
+            int64_t t = hd[i]; hd[i] = hd[m]; hd[m] = t; i = m;
+        }
+        const int32_t v = (int32_t)(top & 0xFFFFFFFF), d = (int32_t)(top >> 32);
+        if (d > dist[v]) continue;                                     /* stale entry */
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int32_t u = col[k];
+            const int64_t nd = (int64_t)d + w[k];
+            if (nd < dist[u]) {
+                dist[u] = (int32_t)nd;
+                if (n == cap) { cap *= 2; hd = (int64_t *)realloc(hd, (size_t)cap * sizeof(int64_t)); }
+                int64_t i = n++;
+                hd[i] = (nd << 32) | (uint32_t)u;
+                while (i > 0 && hd[(i - 1) / 2] > hd[i]) {                /* sift up */
+                    int64_t t = hd[i]; hd[i] = hd[(i - 1) / 2]; hd[(i - 1) / 2] = t; i = (i - 1) / 2;
+                }
+            }
+        }
+    }
+    free(hd);
+}
+
 /* ------------------------------------------------------------------------- */
 /* 2. Epoch-semantics emulator                                                */
 /* ------------------------------------------------------------------------- */
 
-enum { ORC_FIB32 = 1, ORC_FIB64 = 2, ORC_MSORT = 3, ORC_NQUEENS = 4, ORC_BFS = 5, ORC_POSTORDER = 6 };
+enum { ORC_FIB32 = 1, ORC_FIB64 = 2, ORC_MSORT = 3, ORC_NQUEENS = 4, ORC_BFS = 5, ORC_POSTORDER = 6,
+       ORC_SSSP = 7 };
 enum { ORC_OK = 0, ORC_E_OVERFLOW = -3, ORC_E_ENCODING = -8, ORC_E_ARGS = -1 };
 
 typedef struct {
@@ -165,8 +205,8 @@ typedef struct orc_tvm {
     /* program parameters and payloads (caller-owned) */
     int32_t p0, p1;
     uint32_t *buf[2];
-    const int32_t *row_ptr, *col;
-    int32_t *depth;
+    const int32_t *row_ptr, *col, *wts;
+    int32_t *depth;       /* BFS depth / SSSP distance */
     const int32_t *left, *right;
     int32_t *visit_log, *visit_epoch;
     int64_t nvisit;
@@ -304,6 +344,25 @@ static void body_bfs(orc_tvm *m, int64_t i, int32_t type) {
     tv_finish(m, i);
 }
 
+/* SSSP VISIT(v) (Section 6.3's graph workloads, relaxation form): with
+ * v's distance as it stands now, lower every out-neighbour's distance that
+ * v improves and fork a visit of it; a vertex improved twice is visited
+ * twice.  Ends when no distance improves. */
+static void body_sssp(orc_tvm *m, int64_t i, int32_t type) {
+    (void)type;
+    int32_t v = m->a0[i];
+    const int64_t d = m->depth[v];
+    for (int32_t k = m->row_ptr[v]; k < m->row_ptr[v + 1]; ++k) {
+        int32_t u = m->col[k];
+        const int64_t nd = d + m->wts[k];
+        if (nd < m->depth[u]) {
+            m->depth[u] = (int32_t)nd;
+            if (tv_fork(m, 1, u, 0, 0, 0) < 0) return;
+        }
+    }
+    tv_finish(m, i);
+}
+
 /* Figure 2: postorder(node) forks right then left and joins visitAfter(node). */
 static void body_postorder(orc_tvm *m, int64_t i, int32_t type) {
     int32_t node = m->a0[i];
@@ -336,7 +395,7 @@ orc_tvm *orc_new(int32_t kind, int32_t p0, int32_t p1, void *ptr0, void *ptr1, v
                  void *ptr3, int64_t cap) {
     orc_tvm *m = (orc_tvm *)calloc(1, sizeof(orc_tvm));
     m->kind = kind;
-    m->ntt = (kind == ORC_BFS) ? 1 : 2;
+    m->ntt = (kind == ORC_BFS || kind == ORC_SSSP) ? 1 : 2;
     m->cap = cap;
     m->p0 = p0; m->p1 = p1;
     if (!grow(m, 1)) { m->st.status = ORC_E_OVERFLOW; return m; }
@@ -359,6 +418,13 @@ orc_tvm *orc_new(int32_t kind, int32_t p0, int32_t p1, void *ptr0, void *ptr1, v
         m->left = (const int32_t *)ptr0; m->right = (const int32_t *)ptr1;
         m->visit_log = (int32_t *)ptr2; m->visit_epoch = (int32_t *)ptr3;
         m->a0[0] = p0;
+        break;
+    case ORC_SSSP:
+        m->row_ptr = (const int32_t *)ptr0; m->col = (const int32_t *)ptr1;
+        m->wts = (const int32_t *)ptr2; m->depth = (int32_t *)ptr3;
+        for (int32_t v = 0; v < p0; ++v) m->depth[v] = INT32_MAX;
+        m->depth[p1] = 0;
+        m->a0[0] = p1;
         break;
     default: m->st.status = ORC_E_ARGS; return m;
     }
@@ -407,6 +473,7 @@ int32_t orc_step(orc_tvm *m) {
         case ORC_MSORT: body_msort(m, i, type); break;
         case ORC_BFS: body_bfs(m, i, type); break;
         case ORC_POSTORDER: body_postorder(m, i, type); break;
+        case ORC_SSSP: body_sssp(m, i, type); break;
         }
         if (m->st.status < 0) return m->st.status;
     }
@@ -527,6 +594,10 @@ orc_tvm *orc_restore(const void *buf, void *ptr0, void *ptr1, void *ptr2, void *
     case ORC_POSTORDER:
         m->left = (const int32_t *)ptr0; m->right = (const int32_t *)ptr1;
         m->visit_log = (int32_t *)ptr2; m->visit_epoch = (int32_t *)ptr3;
+        break;
+    case ORC_SSSP:
+        m->row_ptr = (const int32_t *)ptr0; m->col = (const int32_t *)ptr1;
+        m->wts = (const int32_t *)ptr2; m->depth = (int32_t *)ptr3;
         break;
     default: break;
     }
