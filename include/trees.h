@@ -93,7 +93,8 @@ typedef enum {
   TREES_PROG_MSORT_U32 = 3, /* split-in-halves merge sort of uint32 keys (Section 6.4) */
   TREES_PROG_NQUEENS = 4,   /* N-queens solution count, one task per partial placement (Section 6.5) */
   TREES_PROG_BFS_CSR = 5,   /* task-per-vertex breadth-first search over CSR (Section 6.3) */
-  TREES_PROG_POSTORDER = 6  /* postorder traversal of a binary tree (Figure 2, Section 5.3) */
+  TREES_PROG_POSTORDER = 6, /* postorder traversal of a binary tree (Figure 2, Section 5.3) */
+  TREES_PROG_SSSP_CSR = 7   /* single-source shortest paths by relaxation over CSR (Section 6.3) */
 } trees_builtin;
 
 typedef struct {
@@ -152,6 +153,14 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      (the pointers may be NULL when N = 0).
  *   BFS_CSR:           args = {V, source}; bufs = {row_ptr[V+1], col_idx[E], depth[V] (out)}
  *                      int32 CSR; depth receives hop counts, -1 = unreachable.
+ *   SSSP_CSR:          args = {V, source[, max_entries]}; bufs = {row_ptr[V+1], col_idx[E],
+ *                      weights[E], dist[V] (out)} int32, weights >= 0 and every distance
+ *                      below 2^31 - 1.  visit(v) lowers the distance of each out-neighbour
+ *                      it improves (atomic min) and forks a visit of it; dist receives the
+ *                      shortest distances, 2^31 - 1 = unreachable.  A vertex is visited once
+ *                      per improvement, so the task count depends on the schedule: the arena
+ *                      holds max_entries entries (default 8 V) and a run that needs more
+ *                      ends the tree with OVERFLOW.
  *   POSTORDER:         args = {n, root}, 1 <= n < 2^24, -1 <= root < n (-1: the empty tree);
  *                      bufs = {left[n], right[n], log[n+1] (out)} int32; left/right hold each
  *                      node's children, -1 = none.  postorder(node) forks postorder(right),
@@ -195,8 +204,8 @@ trees_status trees_trace(trees_ctx *ctx, uint64_t tree, trees_epoch_rec *out, in
  * kind k (trees_builtin); out[0] accumulates batched launches (one graph
  * replay or one persistent launch each); out[6] and out[7] the plain
  * scheduler's map phase (Section 4.2): its partition-pass and merge-pass
- * launches; out[8] the plain scheduler's POSTORDER epochs.  Copies min(n, 9)
- * entries. */
+ * launches; out[8] and out[9] the plain scheduler's POSTORDER and SSSP_CSR
+ * epochs.  Copies min(n, 10) entries. */
 typedef struct {
   double ms;           /* summed launch durations */
   uint64_t launches;   /* number of timed launches */
@@ -204,7 +213,7 @@ typedef struct {
 trees_status trees_kernel_times(trees_ctx *ctx, trees_ktime *out, int32_t n);
 
 /* Choose which launches trees_kernel_times covers: bit k set = time the
- * launches that accumulate in out[k] (all nine by default).  Each timed
+ * launches that accumulate in out[k] (all ten by default).  Each timed
  * launch carries two HIP events, which cost host time per launch, so a
  * throughput measurement times only the launches it reports.  STATE if the
  * context was created without TREES_F_PROFILE. */

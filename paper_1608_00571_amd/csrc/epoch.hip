@@ -87,6 +87,7 @@ struct VisitLds {
   int32_t row[kChunk];     // first arc of the item's vertex
   int32_t pre[kChunk];     // exclusive prefix of out-degrees, in (lane, item) order
   int32_t seg[kChunk];
+  int32_t dv[kChunk];      // SSSP item: its vertex's distance when fetched; BFS item: -1
   int32_t qu[kClaimQ];     // claimed vertices waiting for their child entries
   int16_t qs[kClaimQ];     // their segment (< kChunk)
   int32_t qo[kClaimQ];     // their offset inside the segment's block
@@ -168,7 +169,9 @@ __device__ __forceinline__ void seg_commit(const DevCtx &C, Lds<WG, NS> &L, cons
         L.seg_cnt[s] = 0;
         const int slot = L.seg_slot[s];
         b = add_agent(&C.hot[slot].nfc, (int32_t)c);
-        if ((int64_t)b + c > (int64_t)C.ts[slot].cap) {
+        // (b < 0: the counter wrapped after an overflow earlier in the epoch,
+        // possible only for programs whose task count has no exact bound)
+        if (b < 0 || (int64_t)b + c > (int64_t)C.ts[slot].cap) {
           L.sink = or_agent(&C.hot[slot].flags, (int32_t)TF_OVERFLOW);
           b = -1;
         }
@@ -180,7 +183,7 @@ __device__ __forceinline__ void seg_commit(const DevCtx &C, Lds<WG, NS> &L, cons
         L.seg_cnt[s] = 0;
         const uint64_t prev = add_agent(&C.plain->fj[P.par], ((uint64_t)(uint32_t)j << 32) | (uint32_t)c);
         b = (int32_t)(uint32_t)prev;
-        if ((int64_t)P.nfc0 + b + c > (int64_t)C.ts[P.slot].cap) {
+        if (b < 0 || (int64_t)P.nfc0 + b + c > (int64_t)C.ts[P.slot].cap) {
           L.sink = or_agent(&C.plain->flags[P.par], (int32_t)TF_OVERFLOW);
           b = -1;
         } else {
@@ -372,7 +375,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   // the previous chunk already loaded this chunk's entries (same tree, same
   // window); kernels with merge sort or BFS do not prefetch (their register
   // budget is spent on leaf sorts and arc expansion)
-  constexpr bool kPrefetch = MULTI && (OPS & (OPS_MS | OPS_BFS)) == 0;
+  constexpr bool kPrefetch = MULTI && (OPS & (OPS_MS | OPS_GRAPH)) == 0;
   const bool hit = kPrefetch && follows && pf.w0 == w0;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -590,6 +593,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         }
       } break;
       case OP_VISIT:
+      case OP_SVISIT:
         act[k] = ACT_FINISH;   // its arcs are expanded co-operatively below
         break;
       case OP_POST: {
@@ -812,22 +816,30 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
 
   __syncthreads();
   phase_mark(C, L, 3);
-  // ---- BFS: co-operative expansion of the VISIT items' arcs -----------------
+  // ---- BFS and SSSP: co-operative expansion of the VISIT items' arcs -------
   int arc_job = -1;   // >= 0: this chunk's arcs (and its retirement) went to that arc job
-  if constexpr ((OPS & OPS_BFS) != 0) {
-    bool anyv = false;
+  if constexpr ((OPS & OPS_GRAPH) != 0) {
+    constexpr bool kSssp = (OPS & OPS_SSSP) != 0;
+    bool anyv = false, anys = false;
 #pragma unroll
-    for (int k = 0; k < IT; ++k) anyv |= (op[k] == OP_VISIT);
+    for (int k = 0; k < IT; ++k) {
+      anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT);
+      anys |= (op[k] == OP_SVISIT);
+    }
     if (__syncthreads_or(anyv)) {
-      int32_t deg[IT], row[IT];
+      int32_t deg[IT], row[IT], dvs[IT];
       int dsum = 0;
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
-        deg[k] = 0; row[k] = 0;
-        if (op[k] == OP_VISIT) {
-          const int32_t *rp = (const int32_t *)C.ts[slot[k]].ptr0;
+        deg[k] = 0; row[k] = 0; dvs[k] = -1;
+        if (op[k] == OP_VISIT || op[k] == OP_SVISIT) {
+          const TreeStatic *ST = &C.ts[slot[k]];
+          const int32_t *rp = (const int32_t *)ST->ptr0;
           row[k] = rp[a0v[k]];
           deg[k] = rp[a0v[k] + 1] - row[k];
+          // SSSP: the vertex's distance as it stands now (a later, lower one
+          // makes another visit of it)
+          if (kSssp && op[k] == OP_SVISIT) dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
         }
         dsum += deg[k];
       }
@@ -838,13 +850,16 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         V.row[tid * IT + k] = row[k];
         V.pre[tid * IT + k] = pre;
         V.seg[tid * IT + k] = seg[k];
+        if (kSssp) V.dv[tid * IT + k] = dvs[k];
         pre += deg[k];
       }
       if (tid == 0) V.qn = 0;
+      // many arcs: published as tiles for every work-group (batched forms;
+      // BFS chunks only: the arc phase claims by depth)
+      const bool with_sssp = kSssp && __syncthreads_or(anys);
       __syncthreads();
-      // many arcs: published as tiles for every work-group (batched forms)
       if constexpr (MULTI) {
-        if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot);
+        if (tot > kArcLocal && !with_sssp) arc_job = publish_arcs<WG>(C, L, V, tot);
       }
       // One arc per lane per step.  A claimed vertex is queued in LDS; the
       // queue is turned into child entries in bulk (one device atomic per
@@ -856,26 +871,36 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         int32_t u[A], sseg[A];
         int32_t *dep[A];
         int32_t dv[A];
+        int32_t nd[A];   // SSSP arc: the distance it offers its head; BFS arc: -1
 #pragma unroll
         for (int a = 0; a < A; ++a) {
           const int e = e0 + a * WG + tid;
           sseg[a] = -1;
+          nd[a] = -1;
           if (e < tot) {
             int lo = from, hi = kChunk;   // last item with pre <= e
             while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
             from = lo;
             sseg[a] = V.seg[lo];
             const TreeStatic *ST = &C.ts[L.seg_slot[sseg[a]]];
-            u[a] = ((const int32_t *)ST->ptr1)[V.row[lo] + (e - V.pre[lo])];
+            const int32_t arc = V.row[lo] + (e - V.pre[lo]);
+            u[a] = ((const int32_t *)ST->ptr1)[arc];
             dep[a] = (int32_t *)ST->ptr2;
+            if (kSssp && V.dv[lo] >= 0) nd[a] = V.dv[lo] + ((const int32_t *)ST->ptr3)[arc];
           }
         }
 #pragma unroll
         for (int a = 0; a < A; ++a) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;   // probes issued together
 #pragma unroll
         for (int a = 0; a < A; ++a) {
-          if (sseg[a] >= 0 && dv[a] == -1 &&
-              atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1) {
+          // BFS: test, then claim an unreached vertex; SSSP: test, then lower
+          // the head's distance; either way the winner forks a visit of it
+          bool won = false;
+          if (sseg[a] >= 0) {
+            if (kSssp && nd[a] >= 0) won = nd[a] < dv[a] && atomicMin(&dep[a][u[a]], nd[a]) > nd[a];
+            else won = dv[a] == -1 && atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1;
+          }
+          if (won) {
             const int q = atomicAdd(&V.qn, 1);
             V.qu[q] = u[a];
             V.qs[q] = (int16_t)sseg[a];
@@ -1098,7 +1123,7 @@ __device__ void publish(const DevCtx &C, int32_t par, uint32_t seq) {
 
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
-  using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
+  using VL = typename std::conditional<(OPS & OPS_GRAPH) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG, 1> L;   // one tree: one segment
   __shared__ VL V;
   lds_init<WG>(C, L);
@@ -1357,7 +1382,7 @@ template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
   using MapL = typename std::conditional<kMap, MapLds<kMapTile>, NoMapLds>::type;
-  using VL = typename std::conditional<(OPS & OPS_BFS) != 0, VisitLds, NoVisitLds>::type;
+  using VL = typename std::conditional<(OPS & OPS_GRAPH) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG> L;
   __shared__ MapL M;
   __shared__ VL V;
@@ -1395,7 +1420,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     // a work-group that drew expensive chunks takes fewer.  The others take
     // one even share each.
     const uint32_t nchunks = (S + kChunk - 1) / kChunk;
-    constexpr bool kGuided = (OPS & OPS_BFS) != 0;
+    constexpr bool kGuided = (OPS & OPS_GRAPH) != 0;
     const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
     PendingFinish pend;
     Prefetch<kChunk / WG> pf;
@@ -1499,9 +1524,11 @@ __global__ void k_admit(DevCtx C, const Admit *adm, int32_t n) {
 }
 
 // BFS payload initialisation: depth = -1 everywhere, 0 at the source.
-__global__ void k_depth_init(int32_t *depth, int32_t V, int32_t src) {
+// A graph program's per-vertex array before its first epoch: 0 at the
+// source, `fill` elsewhere (BFS depth: -1; SSSP distance: the largest int32).
+__global__ void k_depth_init(int32_t *depth, int32_t V, int32_t src, int32_t fill) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < V; v += (int64_t)gridDim.x * blockDim.x)
-    depth[v] = (v == src) ? 0 : -1;
+    depth[v] = (v == src) ? 0 : fill;
 }
 
 // Release a slot: no range, status free.
@@ -1520,11 +1547,11 @@ __global__ void k_release(DevCtx C, int32_t slot) {
   M(WG, OPS_NQ)                   \
   M(WG, OPS_FIB | OPS_NQ)         \
   M(WG, OPS_MS)                   \
-  M(WG, OPS_BFS)                  \
+  M(WG, OPS_GRAPH)                \
   M(WG, OPS_ALL)
 
 static uint32_t pick_ops(uint32_t need) {
-  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_BFS, OPS_ALL};
+  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_GRAPH, OPS_ALL};
   for (uint32_t s : sets)
     if ((need & ~s) == 0) return s;
   return OPS_ALL;
@@ -1627,9 +1654,9 @@ hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s) 
   return hipLaunchKernel((const void *)&k_admit, dim3((n + 255) / 256), dim3(256), args, 0, s);
 }
 
-hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, hipStream_t s) {
-  int32_t v = V, sc = src;
-  void *args[] = {&depth, &v, &sc};
+hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, int32_t fill, hipStream_t s) {
+  int32_t v = V, sc = src, f = fill;
+  void *args[] = {&depth, &v, &sc, &f};
   int blocks = (int)((V + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;

@@ -26,7 +26,7 @@ hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStre
 int coresident_blocks_per_cu(int wg, uint32_t need);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
-hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, hipStream_t s);
+hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, int32_t fill, hipStream_t s);
 const void *kernel_epochs(int wg, uint32_t need);
 }  // namespace trees
 
@@ -69,6 +69,7 @@ uint32_t ops_of_kind(int kind) {
     case TREES_PROG_NQUEENS: return OPS_NQ;
     case TREES_PROG_BFS_CSR: return OPS_BFS;
     case TREES_PROG_POSTORDER: return OPS_PO;
+    case TREES_PROG_SSSP_CSR: return OPS_SSSP;
   }
   return 0;
 }
@@ -143,6 +144,15 @@ trees_status tv_bound(int kind, const int64_t *args, int nargs, int64_t *out, st
         return bad("bfs: need V >= 1 and 0 <= source < V");
       *out = args[0];
       return TREES_OK;
+    case TREES_PROG_SSSP_CSR:
+      // a vertex is visited once per improvement of its distance, so the
+      // task count depends on the schedule: the arena holds max_entries
+      // (default 8 V) and a run that needs more fails with OVERFLOW
+      if (nargs < 2 || args[0] < 1 || args[0] >= (1ll << 31) || args[1] < 0 || args[1] >= args[0])
+        return bad("sssp: need V >= 1 and 0 <= source < V");
+      if (nargs >= 3 && (args[2] < 1 || args[2] >= (1ll << 31))) return bad("sssp: need 1 <= max_entries < 2^31");
+      *out = nargs >= 3 ? args[2] : std::min<int64_t>(8 * args[0], (1ll << 31) - 1);
+      return TREES_OK;
     case TREES_PROG_POSTORDER:
       // every postorder task (the root and two per node, null children
       // included) holds one entry; a join reuses its own
@@ -177,7 +187,7 @@ struct trees_ctx {
   std::map<int64_t, int64_t> freel;   // arena free list: start -> length
   int64_t free_ent = 0;
   std::vector<Admit> staged;
-  struct DepthInit { int32_t *depth; int32_t V, src; };
+  struct DepthInit { int32_t *depth; int32_t V, src, fill; };
   std::vector<DepthInit> depth_inits;
   Admit *adm_host = nullptr;       // pinned staging
   Admit *adm_dev = nullptr;
@@ -201,8 +211,8 @@ struct trees_ctx {
   // last epoch, so timing adds no synchronisation per epoch
   std::vector<hipEvent_t> evpool;
   std::vector<std::pair<int, size_t>> evpend;   // (ktime slot, first event of the pair)
-  trees_ktime ktime[9] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes, 8 plain postorder
-  uint32_t prof_mask = 0x1FFu;  // which of the slots above are timed
+  trees_ktime ktime[10] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes, 8/9 plain postorder/sssp
+  uint32_t prof_mask = 0x3FFu;  // which of the slots above are timed
   double clock_hz = 1e8;
   double timeout_s = 60.0;   // host and device waits give up after this long
   bool running = false;
@@ -285,7 +295,7 @@ trees_status flush_admissions(trees_ctx *c) {
     }
     c->staged.clear();
   }
-  for (auto &d : c->depth_inits) HIPCHK(c, launch_depth_init(d.depth, d.V, d.src, c->stream));
+  for (auto &d : c->depth_inits) HIPCHK(c, launch_depth_init(d.depth, d.V, d.src, d.fill, c->stream));
   c->depth_inits.clear();
   // the admission staging buffer is reused: wait for the copy
   if (n) HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -384,7 +394,8 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
     P.seq = ++c->plain_seq ? c->plain_seq : ++c->plain_seq;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const int kslot = t.kind == TREES_PROG_POSTORDER ? 8 : t.kind;   // (6 and 7 are the map passes)
+    // (6 and 7 are the map passes)
+    const int kslot = t.kind == TREES_PROG_POSTORDER ? 8 : t.kind == TREES_PROG_SSSP_CSR ? 9 : t.kind;
     if (timed(c, kslot)) TRY(take_events(c, kslot, &e0, &e1));
     HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream, e0, e1));
     TRY(wait_mirror(c, P.seq));
@@ -774,7 +785,7 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
   if (c->frozen) return fail(c, TREES_E_STATE, "programs must be registered before the first submit");
   Prog p;
   p.kind = kind;
-  p.ntypes = (kind == TREES_PROG_BFS_CSR) ? 1 : 2;
+  p.ntypes = (kind == TREES_PROG_BFS_CSR || kind == TREES_PROG_SSSP_CSR) ? 1 : 2;
   p.tbase = c->ntt + 1;
   p.ops = ops;
   if (c->ntt + p.ntypes > kMaxTypes) return fail(c, TREES_E_INVALID, "too many task types");
@@ -787,6 +798,7 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
     case TREES_PROG_NQUEENS: c->dc.op_of_type[p.tbase] = OP_Q; c->dc.op_of_type[p.tbase + 1] = OP_QSUM; break;
     case TREES_PROG_BFS_CSR: c->dc.op_of_type[p.tbase] = OP_VISIT; break;
     case TREES_PROG_POSTORDER: c->dc.op_of_type[p.tbase] = OP_POST; c->dc.op_of_type[p.tbase + 1] = OP_PVISIT; break;
+    case TREES_PROG_SSSP_CSR: c->dc.op_of_type[p.tbase] = OP_SVISIT; break;
   }
   c->dc.ntt = c->ntt;
   c->progs.push_back(p);
@@ -840,6 +852,21 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       a.ts.ptr1 = (uint64_t)bufs[1].ptr;
       a.ts.ptr2 = (uint64_t)bufs[2].ptr;
     } break;
+    case TREES_PROG_SSSP_CSR: {
+      const int64_t V = args[0], src = args[1];
+      if (nbufs < 4 || !bufs || !bufs[0].ptr || !bufs[1].ptr || !bufs[2].ptr || !bufs[3].ptr ||
+          bufs[0].bytes < (uint64_t)(V + 1) * 4 || bufs[2].bytes < bufs[1].bytes ||
+          bufs[3].bytes < (uint64_t)V * 4)
+        return fail(c, TREES_E_INVALID,
+                    "sssp: need bufs {row_ptr[V+1], col_idx[E], weights[E], dist[V]} of int32");
+      a.a0 = (int32_t)src;
+      a.ts.p0 = (int32_t)V;
+      a.ts.p1 = (int32_t)src;
+      a.ts.ptr0 = (uint64_t)bufs[0].ptr;
+      a.ts.ptr1 = (uint64_t)bufs[1].ptr;
+      a.ts.ptr2 = (uint64_t)bufs[3].ptr;   // the per-vertex array (as BFS depth)
+      a.ts.ptr3 = (uint64_t)bufs[2].ptr;   // arc weights
+    } break;
     case TREES_PROG_POSTORDER: {
       const int64_t n = args[0];
       if (nbufs < 3 || !bufs || !bufs[0].ptr || !bufs[1].ptr || !bufs[2].ptr ||
@@ -881,7 +908,9 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   a.ts.tp = t.tp;
   c->staged.push_back(a);
   if (P.kind == TREES_PROG_BFS_CSR)
-    c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1]});
+    c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1], -1});
+  if (P.kind == TREES_PROG_SSSP_CSR)
+    c->depth_inits.push_back({(int32_t *)bufs[3].ptr, (int32_t)args[0], (int32_t)args[1], INT32_MAX});
   c->tslots = std::max(c->tslots, slot + 1);
   c->ntrees++;
   *out_tree = ((uint64_t)t.gen << 32) | (uint32_t)slot;
@@ -1024,7 +1053,7 @@ trees_status trees_profile_mask(trees_ctx *c, uint32_t mask) {
   if (!c) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
-  c->prof_mask = mask & 0x1FFu;
+  c->prof_mask = mask & 0x3FFu;
   return TREES_OK;
 }
 
@@ -1032,7 +1061,7 @@ trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
   if (!c || !out) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
-  for (int k = 0; k < n && k < 9; ++k) out[k] = c->ktime[k];
+  for (int k = 0; k < n && k < 10; ++k) out[k] = c->ktime[k];
   return TREES_OK;
 }
 

@@ -34,7 +34,8 @@ enum Op : int32_t {
   OP_Q = 7, OP_QSUM = 8,
   OP_VISIT = 9,
   OP_POST = 10, OP_PVISIT = 11,
-  OP_COUNT = 12
+  OP_SVISIT = 12,
+  OP_COUNT = 13
 };
 constexpr uint32_t opbit(int op) { return 1u << op; }
 constexpr uint32_t OPS_FIB = opbit(OP_FIB32) | opbit(OP_SUM32) | opbit(OP_FIB64) | opbit(OP_SUM64);
@@ -42,7 +43,9 @@ constexpr uint32_t OPS_NQ = opbit(OP_Q) | opbit(OP_QSUM);
 constexpr uint32_t OPS_MS = opbit(OP_MS) | opbit(OP_MERGE);
 constexpr uint32_t OPS_BFS = opbit(OP_VISIT);
 constexpr uint32_t OPS_PO = opbit(OP_POST) | opbit(OP_PVISIT);
-constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS | OPS_PO;
+constexpr uint32_t OPS_SSSP = opbit(OP_SVISIT);
+constexpr uint32_t OPS_GRAPH = OPS_BFS | OPS_SSSP;   // kernels with the co-operative arc expansion
+constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS | OPS_PO | OPS_SSSP;
 
 // Tree status values (TreeState::status).
 enum : int32_t { TS_FREE = 0, TS_LIVE = 1, TS_DONE = 2, TS_PAUSED = 3 };
@@ -55,9 +58,11 @@ struct TreeStatic {
   int32_t cap;       // arena capacity in entries
   int32_t tbase;     // global type id of the program's first type
   int32_t kind;      // trees_builtin
-  int32_t p0, p1;    // fib n | nqueens n | msort N | bfs V, source
-  uint32_t tp;       // tbase | (nqueens n) << 8, as the work list carries it
-  uint64_t ptr0, ptr1, ptr2;  // msort: keys, tmp; bfs: row_ptr, col_idx, depth
+  int32_t p0, p1;    // fib n | nqueens n | msort N | bfs, sssp V, source | postorder n, root
+  uint32_t tp;       // tbase | (nqueens n or postorder n) << 8, as the work list carries it
+  // msort: keys, tmp; bfs: row_ptr, col_idx, depth; sssp: row_ptr, col_idx,
+  // dist, weights; postorder: left, right, log
+  uint64_t ptr0, ptr1, ptr2, ptr3;
 };
 
 // Per-tree counters updated with device-scope atomics during an epoch.

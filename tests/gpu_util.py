@@ -6,7 +6,7 @@ import numpy as np
 
 SCHEDS = ["plain", "graph", "persistent"]
 
-KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6}
+KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6, "sssp": 7}
 
 
 def to_dev_u32(a: np.ndarray):
@@ -32,9 +32,12 @@ def register_all(ctx, jobs):
 class Job:
     """One tree: its spec, payload tensors and, after collect(), its outputs."""
 
-    def __init__(self, kind: str, n=None, keys=None, graph=None, bintree=None):
+    def __init__(self, kind: str, n=None, keys=None, graph=None, bintree=None, weights=None, cap=None):
         # bintree (postorder): (left, right, root) int32 child arrays, -1 = none
+        # weights (sssp): int32 arc weights in the graph's CSR order; cap: the
+        # tree's task-vector entries (default 8 V)
         self.kind, self.n, self.keys, self.graph, self.bintree = kind, n, keys, graph, bintree
+        self.weights, self.cap = weights, cap
         self.tree = None
         self.value = None
         self.stats = None
@@ -61,6 +64,16 @@ class Job:
             d = torch.empty(g.V, dtype=torch.int32, device="cuda")
             self.bufs = (rp, ci, d)
             self.tree = ctx.submit(prog, [g.V, g.source], [rp, ci, d])
+        elif self.kind == "sssp":
+            g = self.graph
+            rp, ci, w = to_dev_i32(g.row_ptr), to_dev_i32(g.col_idx), to_dev_i32(self.weights)
+            if ci.numel() == 0:
+                ci = torch.zeros(1, dtype=torch.int32, device="cuda")
+                w = torch.zeros(1, dtype=torch.int32, device="cuda")
+            d = torch.empty(g.V, dtype=torch.int32, device="cuda")
+            self.bufs = (rp, ci, w, d)
+            args = [g.V, g.source] + ([self.cap] if self.cap else [])
+            self.tree = ctx.submit(prog, args, [rp, ci, w, d])
         elif self.kind == "postorder":
             left, right, root = self.bintree
             lt, rt = to_dev_i32(left), to_dev_i32(right)
@@ -79,6 +92,8 @@ class Job:
             self.out = from_dev_u32(self.bufs[0])
         elif self.kind == "bfs":
             self.out = self.bufs[2].cpu().numpy()
+        elif self.kind == "sssp":
+            self.out = self.bufs[3].cpu().numpy()
         elif self.kind == "postorder":
             self.out = self.bufs[2].cpu().numpy()   # visit log, then the visit count
         return self
@@ -124,7 +139,36 @@ def check_postorder_log(job: Job, want_log: np.ndarray):
         assert np.all(pos[child[has]] < pos[has]), "postorder: a node visited before its child"
 
 
+def check_sssp(job: Job):
+    """Distances equal Dijkstra's exactly.  The task count of the relaxation
+    program depends on the order of relaxations inside an epoch, so the
+    statistics are checked against what every schedule must satisfy: each
+    reached vertex is visited at least once, a vertex h arcs from the source
+    is first visited in epoch h, every fork goes one level deeper (epoch i
+    runs at CEN i) and nothing joins."""
+    import oracle
+    g = job.graph
+    want = oracle.dijkstra(g.V, g.row_ptr, g.col_idx, job.weights, g.source)
+    bad = np.flatnonzero(job.out != want)
+    assert bad.size == 0, f"sssp: {bad.size} distances differ, first at {bad[:5]}: " \
+        f"got {job.out[bad[:5]]} want {want[bad[:5]]}"
+    hops = oracle.bfs_queue(g.V, g.row_ptr, g.col_idx, g.source)
+    s = job.stats
+    reached = int(np.count_nonzero(want != oracle.UNREACHED))
+    assert s.tasks >= reached, f"sssp: {s.tasks} visits for {reached} reached vertices"
+    assert s.epochs >= int(hops.max()) + 1
+    assert s.launched >= s.tasks
+    if job.trace is not None and len(job.trace) == s.epochs and s.epochs <= 256:
+        t = job.trace
+        assert np.array_equal(t["cen"], np.arange(s.epochs)), "sssp: an epoch not at its depth"
+        assert int(t["joins"].sum()) == 0
+        assert int(t["valid"].sum()) == s.tasks
+        assert int(t["forks"].sum()) == s.tasks - 1
+
+
 def assert_matches_oracle(job: Job, check_trace=True):
+    if job.kind == "sssp":
+        return check_sssp(job)
     want, out = oracle_run(job)
     s = job.stats
     got = (job.value if job.kind not in ("msort", "bfs", "postorder") else want.result, s.epochs, s.tasks,

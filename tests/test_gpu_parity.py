@@ -89,6 +89,64 @@ def test_bfs(sched):
         assert_matches_oracle(j)
 
 
+def sssp_jobs(lo=1, hi=100, seed=900):
+    """Each tiny graph and R-MAT graph with seeded arc weights on [lo, hi]
+    (in the graph's CSR order)."""
+    return [Job("sssp", graph=g, weights=inputs.arc_weights(g.E, seed + i, lo, hi))
+            for i, (name, g) in enumerate(tiny_graphs())]
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("lo,hi", [(1, 100), (0, 3), (7, 7)])
+def test_sssp(sched, lo, hi):
+    """Shortest distances equal Dijkstra's: weights 1..100, weights 0..3
+    (zero-weight arcs and many equal-length paths) and one weight for every
+    arc (distances are 7 x BFS depth)."""
+    for j in sssp_jobs(lo, hi):
+        run_alone(sched, [j])
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_sssp_batch(sched):
+    """16 weighted R-MAT graphs of scale 10..16 in one run."""
+    jobs = []
+    for g in range(16):
+        gr, w = inputs.sssp_graph(10 + g % 7, 700 + g)
+        jobs.append(Job("sssp", graph=gr, weights=w))
+    run_alone(sched, jobs, trace=False)
+    for j in jobs:
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_sssp_arena_overflow(sched):
+    """A tree whose visits outgrow its arena fails with OVERFLOW, and a tree
+    of another program in the same run is unaffected."""
+    import paper_1608_00571_amd as T
+    g, w = inputs.sssp_graph(10, 32)   # the source reaches 814 vertices in 2223 visits
+    bad = Job("sssp", graph=g, weights=w, cap=64)
+    ok = Job("fib64", 16)
+    with make_ctx(sched) as ctx:
+        register_all(ctx, [bad, ok])
+        bad.submit(ctx)
+        ok.submit(ctx)
+        ctx.run()
+        with pytest.raises(T.TreesError) as e:
+            ctx.results(bad.tree)
+        assert e.value.status == T.E_OVERFLOW
+        ok.collect(ctx, trace=True)
+    assert_matches_oracle(ok)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+def test_sssp_full_scale_graph(sched):
+    """One weighted graph of 2^20 vertices and 2^24 arcs."""
+    g, w = inputs.sssp_graph(20, 5)
+    (j,) = run_alone(sched, [Job("sssp", graph=g, weights=w)], trace=False)
+    assert_matches_oracle(j, check_trace=False)
+
+
 def bintree(left, right, root):
     return (np.asarray(left, dtype=np.int32), np.asarray(right, dtype=np.int32), root)
 
@@ -133,6 +191,8 @@ def test_mixed_batch_equals_alone(sched):
     jobs.append(Job("bfs", graph=inputs.rmat(9, 4)))
     jobs.append(Job("bfs", graph=inputs.csr_from_arcs(5, [(0, 1), (1, 2), (2, 3), (3, 4)], 0)))
     jobs.append(Job("postorder", bintree=bintree(*inputs.binary_tree(500, 11), 0)))
+    gs, ws = inputs.sssp_graph(9, 12)
+    jobs.append(Job("sssp", graph=gs, weights=ws))
     with make_ctx(sched) as ctx:
         register_all(ctx, jobs)
         for j in jobs:
