@@ -223,6 +223,13 @@ def bfs_batch_graph(g: int, scale: int) -> Graph:
     return rmat(scale, item_seed(4, g))
 
 
+def sssp_batch_graph(g: int, scale: int, lo: int = 1, hi: int = 100) -> tuple[Graph, np.ndarray]:
+    """Graph g of the weighted batch: the BFS batch's graph g with arc
+    weights uniform on [lo, hi]."""
+    G = bfs_batch_graph(g, scale)
+    return G, arc_weights(G.E, item_seed(7, g), lo, hi)
+
+
 # ----------------------------------------------------------------------------
 # Tree batches and request traces
 # ----------------------------------------------------------------------------

@@ -89,8 +89,9 @@ struct VisitLds {
   int32_t seg[kChunk];
   int32_t dv[kChunk];      // SSSP item: its vertex's distance when fetched; BFS item: -1
   int32_t qu[kClaimQ];     // claimed vertices waiting for their child entries
+  int32_t qd[kClaimQ];     // SSSP claim: the distance it set (the child's a1); BFS: -1
   int16_t qs[kClaimQ];     // their segment (< kChunk)
-  int32_t qo[kClaimQ];     // their offset inside the segment's block
+  int16_t qo[kClaimQ];     // their offset inside the segment's block (< kClaimQ)
   int32_t qn;
 };
 struct NoVisitLds {};
@@ -339,6 +340,7 @@ __device__ int publish_arcs(const DevCtx &C, Lds<WG> &L, VisitLds &V, int tot) {
     it[i] = V.pre[i];
     it[kChunk + i] = V.row[i];
     it[2 * kChunk + i] = V.seg[i];
+    it[3 * kChunk + i] = V.dv[i];
   }
   int32_t *sg = C.arc_seg + sbase;
   for (int q = tid; q < nseg; q += WG) {
@@ -820,12 +822,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   int arc_job = -1;   // >= 0: this chunk's arcs (and its retirement) went to that arc job
   if constexpr ((OPS & OPS_GRAPH) != 0) {
     constexpr bool kSssp = (OPS & OPS_SSSP) != 0;
-    bool anyv = false, anys = false;
+    bool anyv = false;
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT);
-      anys |= (op[k] == OP_SVISIT);
-    }
+    for (int k = 0; k < IT; ++k) anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT);
     if (__syncthreads_or(anyv)) {
       int32_t deg[IT], row[IT], dvs[IT];
       int dsum = 0;
@@ -837,9 +836,13 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
           const int32_t *rp = (const int32_t *)ST->ptr0;
           row[k] = rp[a0v[k]];
           deg[k] = rp[a0v[k] + 1] - row[k];
-          // SSSP: the vertex's distance as it stands now (a later, lower one
-          // makes another visit of it)
-          if (kSssp && op[k] == OP_SVISIT) dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
+          // SSSP: the vertex's distance as it stands now.  The entry's a1 is
+          // the distance that forked it; a lower one since then forked
+          // another visit, which relaxes the arcs instead (this one is stale)
+          if (kSssp && op[k] == OP_SVISIT) {
+            dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
+            if (dvs[k] < C.a1[idx[k]]) deg[k] = 0;
+          }
         }
         dsum += deg[k];
       }
@@ -854,12 +857,10 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         pre += deg[k];
       }
       if (tid == 0) V.qn = 0;
-      // many arcs: published as tiles for every work-group (batched forms;
-      // BFS chunks only: the arc phase claims by depth)
-      const bool with_sssp = kSssp && __syncthreads_or(anys);
+      // many arcs: published as tiles for every work-group (batched forms)
       __syncthreads();
       if constexpr (MULTI) {
-        if (tot > kArcLocal && !with_sssp) arc_job = publish_arcs<WG>(C, L, V, tot);
+        if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot);
       }
       // One arc per lane per step.  A claimed vertex is queued in LDS; the
       // queue is turned into child entries in bulk (one device atomic per
@@ -904,6 +905,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
             const int q = atomicAdd(&V.qn, 1);
             V.qu[q] = u[a];
             V.qs[q] = (int16_t)sseg[a];
+            if (kSssp) V.qd[q] = nd[a];
           }
         }
         __syncthreads();
@@ -912,7 +914,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
           for (int q0 = 0; q0 < qn; q0 += WG) {
             const int q = q0 + tid;
             const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
-            if (q < qn) V.qo[q] = o;
+            if (q < qn) V.qo[q] = (int16_t)o;
           }
           seg_commit<WG, MULTI>(C, L, P, false);
           for (int q = tid; q < qn; q += WG) {
@@ -922,6 +924,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
               const int64_t c = ((int64_t)L.seg_tb[sseg] << 6) + vb + V.qo[q];
               C.code[c] = (L.seg_cen[sseg] + 1) * ntt + (int32_t)(L.seg_tp[sseg] & 0xFF);
               C.a0[c] = V.qu[q];
+              if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
             }
           }
           __syncthreads();
@@ -1162,12 +1165,13 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
 
 // The arc phase: every work-group claims tiles of the epoch's arc jobs.  A
 // tile expands arcs [t * tile, (t + 1) * tile) of its job with the same
-// steps as a chunk's own expansion (probe, test-and-CAS claim, LDS queue,
-// child entries in bulk); the work-group that expands a job's last tile
-// retires the owner chunk's items, running Phase 3 of a tree whose last
-// items they were.
-template <int WG>
+// steps as a chunk's own expansion (probe, then a BFS claim by CAS or an
+// SSSP relaxation by atomic min, LDS queue, child entries in bulk); the
+// work-group that expands a job's last tile retires the owner chunk's items,
+// running Phase 3 of a tree whose last items they were.
+template <int WG, uint32_t OPS>
 __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
+  constexpr bool kSssp = (OPS & OPS_SSSP) != 0;
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
   const int32_t ntt = C.ntt;
@@ -1193,6 +1197,7 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
       V.pre[i] = it[i];
       V.row[i] = it[kChunk + i];
       V.seg[i] = it[2 * kChunk + i];
+      if (kSssp) V.dv[i] = it[3 * kChunk + i];
     }
     const int32_t *sg = C.arc_seg + J->sbase;
     for (int q = tid; q < nseg; q += WG) {
@@ -1210,29 +1215,38 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
       int32_t u[A], sseg[A];
       int32_t *dep[A];
       int32_t dv[A];
+      int32_t nd[A];   // SSSP arc: the distance it offers its head; BFS arc: -1
 #pragma unroll
       for (int a = 0; a < A; ++a) {
         const int e = e0 + a * WG + tid;
         sseg[a] = -1;
+        nd[a] = -1;
         if (e < e_hi) {
           int lo = from, hi = ihi + 1;   // last item with pre <= e
           while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
           from = lo;
           sseg[a] = V.seg[lo];
           const TreeStatic *ST = &C.ts[L.seg_slot[sseg[a]]];
-          u[a] = ((const int32_t *)ST->ptr1)[V.row[lo] + (e - V.pre[lo])];
+          const int32_t arc = V.row[lo] + (e - V.pre[lo]);
+          u[a] = ((const int32_t *)ST->ptr1)[arc];
           dep[a] = (int32_t *)ST->ptr2;
+          if (kSssp && V.dv[lo] >= 0) nd[a] = V.dv[lo] + ((const int32_t *)ST->ptr3)[arc];
         }
       }
 #pragma unroll
       for (int a = 0; a < A; ++a) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;   // probes issued together
 #pragma unroll
       for (int a = 0; a < A; ++a) {
-        if (sseg[a] >= 0 && dv[a] == -1 &&
-            atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1) {
+        bool won = false;
+        if (sseg[a] >= 0) {
+          if (kSssp && nd[a] >= 0) won = nd[a] < dv[a] && atomicMin(&dep[a][u[a]], nd[a]) > nd[a];
+          else won = dv[a] == -1 && atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1;
+        }
+        if (won) {
           const int q = atomicAdd(&V.qn, 1);
           V.qu[q] = u[a];
           V.qs[q] = (int16_t)sseg[a];
+          if (kSssp) V.qd[q] = nd[a];
         }
       }
       __syncthreads();
@@ -1241,7 +1255,7 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
         for (int q0 = 0; q0 < qn; q0 += WG) {
           const int q = q0 + tid;
           const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
-          if (q < qn) V.qo[q] = o;
+          if (q < qn) V.qo[q] = (int16_t)o;
         }
         seg_commit<WG, true>(C, L, P, false);
         for (int q = tid; q < qn; q += WG) {
@@ -1251,6 +1265,7 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
             const int64_t c = ((int64_t)L.seg_tb[ss] << 6) + vb + V.qo[q];
             C.code[c] = (L.seg_cen[ss] + 1) * ntt + (int32_t)(L.seg_tp[ss] & 0xFF);
             C.a0[c] = V.qu[q];
+            if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
           }
         }
         __syncthreads();
@@ -1443,14 +1458,14 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     settle(C, pend);
     phase_mark(C, L, 6);
     bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
-    if constexpr ((OPS & OPS_BFS) != 0) {
+    if constexpr ((OPS & OPS_GRAPH) != 0) {
       if (persistent && ok) {
         if (threadIdx.x == 0) s_hdr[4] = (uint32_t)H->arc_phase;
         __syncthreads();
         const bool arcs = s_hdr[4] != 0;
         __syncthreads();
         if (arcs) {
-          arc_phase<WG>(C, L, V);
+          arc_phase<WG, OPS>(C, L, V);
           ok = grid_barrier<WG>(C, L, true, true);
         }
       }
@@ -1463,7 +1478,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
 }
 
 // The arc phase of a captured chain: launched after each epoch launch of a
-// kernel with BFS; returns at once unless the epoch published arc jobs.  The
+// kernel with BFS or SSSP; returns at once unless the epoch published arc jobs.  The
 // last work-group to finish builds the next work list (the epoch launch left
 // it for this launch).
 template <int WG, uint32_t OPS>
@@ -1476,7 +1491,7 @@ __global__ __launch_bounds__(WG) void k_arcs(DevCtx C) {
   __syncthreads();
   if (!s_phase) return;
   lds_init<WG>(C, L);
-  arc_phase<WG>(C, L, V);
+  arc_phase<WG, OPS>(C, L, V);
   wait_vmem();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1523,7 +1538,6 @@ __global__ void k_admit(DevCtx C, const Admit *adm, int32_t n) {
   C.r[r0] = 0;
 }
 
-// BFS payload initialisation: depth = -1 everywhere, 0 at the source.
 // A graph program's per-vertex array before its first epoch: 0 at the
 // source, `fill` elsewhere (BFS depth: -1; SSSP distance: the largest int32).
 __global__ void k_depth_init(int32_t *depth, int32_t V, int32_t src, int32_t fill) {
@@ -1620,9 +1634,9 @@ hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int p
 hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s) {
   const void *fn = nullptr;
   switch (wg) {
-    case 256: fn = (const void *)&k_arcs<256, OPS_BFS>; break;
-    case 512: fn = (const void *)&k_arcs<512, OPS_BFS>; break;
-    case 1024: fn = (const void *)&k_arcs<1024, OPS_BFS>; break;
+    case 256: fn = (const void *)&k_arcs<256, OPS_GRAPH>; break;
+    case 512: fn = (const void *)&k_arcs<512, OPS_GRAPH>; break;
+    case 1024: fn = (const void *)&k_arcs<1024, OPS_GRAPH>; break;
     default: return hipErrorInvalidValue;
   }
   (void)need;

@@ -544,7 +544,7 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < c->chunk; ++k) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
-      if (e == hipSuccess && (need & OPS_BFS)) e = launch_arcs(c->dc, c->wg, need, grid, c->stream);
+      if (e == hipSuccess && (need & OPS_GRAPH)) e = launch_arcs(c->dc, c->wg, need, grid, c->stream);
       if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
         e = launch_map(c->dc, kMapWG, 0, 1, c->ncu * 8, c->ncu * 8, c->stream, nullptr);
       if (e != hipSuccess) {

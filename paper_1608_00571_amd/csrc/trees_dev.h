@@ -177,11 +177,11 @@ struct alignas(64) ArcJob {
   uint32_t sbase;    // first segment record of the job in the pool
   int32_t pad[9];
 };
-// Per job: item arrays pre, row, seg (kChunkItems each, lane-major order of
-// the owner chunk).  Per segment, a record in the pool's seven planes: slot,
+// Per job: item arrays pre, row, seg, dv (kChunkItems each, lane-major order
+// of the owner chunk; dv: an SSSP item's distance, -1 for BFS).  Per segment, a record in the pool's seven planes: slot,
 // cen, tb, tp, items (retired by the job), range (the segment's items this
 // epoch) and jv (joins | valid << 16).
-constexpr int kArcItemWords = 3 * kChunkItems;
+constexpr int kArcItemWords = 4 * kChunkItems;
 
 // Host-visible copy of one epoch's counters (host-mapped, coherent memory),
 // written after the epoch; `seq` is written last and names the launch, so

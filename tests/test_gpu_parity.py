@@ -258,6 +258,20 @@ def test_bfs_arc_phase(sched, wg):
 
 
 @pytest.mark.parametrize("sched", ["graph", "persistent"])
+@pytest.mark.parametrize("wg", [256, 512, 1024])
+def test_sssp_arc_phase(sched, wg):
+    """Relaxations in the arc phase: the hub graph with weights on [0, 9]
+    (many improvements of one vertex inside an epoch, so many stale visits),
+    beside a BFS tree of the same hub graph whose arcs share the phase."""
+    g = hub_graph()
+    jobs = [Job("sssp", graph=g, weights=inputs.arc_weights(g.E, 41, 0, 9)), Job("bfs", graph=g),
+            Job("sssp", graph=inputs.rmat(9, 4), weights=inputs.arc_weights(inputs.rmat(9, 4).E, 42))]
+    run_alone(sched, jobs, wg=wg)
+    for j in jobs:
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
 def test_bfs_full_scale_graph(sched):
     """One graph at the batch's largest scale (2^22 vertices, 2^26 arcs)."""
     g = inputs.bfs_batch_graph(0, 22)
