@@ -160,7 +160,8 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      shortest distances, 2^31 - 1 = unreachable.  A vertex is visited once
  *                      per improvement, so the task count depends on the schedule: the arena
  *                      holds max_entries entries (default 8 V) and a run that needs more
- *                      ends the tree with OVERFLOW.
+ *                      ends the tree with OVERFLOW.  A visit forked by a distance that has
+ *                      since dropped returns at once (a later visit relaxes the arcs).
  *   POSTORDER:         args = {n, root}, 1 <= n < 2^24, -1 <= root < n (-1: the empty tree);
  *                      bufs = {left[n], right[n], log[n+1] (out)} int32; left/right hold each
  *                      node's children, -1 = none.  postorder(node) forks postorder(right),
