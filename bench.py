@@ -35,12 +35,16 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "88ce0c09d066ee85", "fetch_bytes": 68793125, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "756cf794ed63fc61", "fetch_bytes": 2823055, "write_bytes": 3504857},
-    "k_plain<MS>": {"src": "756cf794ed63fc61", "fetch_bytes": 2239189, "write_bytes": 2354724},
+    "k_map_merge<1024,8192>": {"src": "42b2fdef583cc796", "fetch_bytes": 68794706, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "a171cc24fe32b582", "fetch_bytes": 2827079, "write_bytes": 3504283},
+    "k_plain<MS>": {"src": "a171cc24fe32b582", "fetch_bytes": 2244779, "write_bytes": 2354541},
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "b21b909592f34404", "wg": 512, "fetch_bytes": 10426047367,
-                         "write_bytes": 12485966464},
+    "k_epochs<FIB|NQ>": {"src": "a171cc24fe32b582", "wg": 512, "fetch_bytes": 10427244672,
+                         "write_bytes": 12478742432},
+    # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
+    # (profiles/sssp_64rmat_weighted.md)
+    "k_epochs<GRAPH> sssp": {"src": "a171cc24fe32b582", "wg": 256, "fetch_bytes": 179780440576 + 143272260224,
+                             "write_bytes": 3369959360 + 4423267424},
 }
 
 
@@ -523,6 +527,7 @@ def bench_cfg4(args):
     best = max(out, key=lambda k: out[k]["vertices_per_s"])
     b = out[best]
     ach = (tv + payload) / (b["ms"] * 1e-3) / 1e9
+    amp = (tv + payload + 60 * scanned) / (b["ms"] * 1e-3) / 1e9   # a depth probe moves a 64-B sector
     return {"metric": "tasks/s", "value": b["vertices_per_s"], "unit": "tasks/s (vertices visited)",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
@@ -533,7 +538,8 @@ def bench_cfg4(args):
             "schedulers": out,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                         "tv_bytes": tv, "payload_bytes": payload},
+                         "tv_bytes": tv, "payload_bytes": payload,
+                         "sector_amplified": {"achieved": round(amp, 1), "frac": round(amp / HBM_PEAK_GBS, 4)}},
             "setup_s": {"generate": round(gen_s, 1), "oracle_bfs": round(orc_s, 1)}}
 
 
@@ -605,6 +611,10 @@ def bench_cfg7(args):
     best = min(out, key=lambda k: out[k]["ms"])
     b = out[best]
     ach = b["alg_bytes"] / (b["ms"] * 1e-3) / 1e9
+    # random probes of a head's distance move a 64-B sector, not 4 B
+    amp = (b["alg_bytes"] + 60 * scanned) / (b["ms"] * 1e-3) / 1e9
+    m = MEASURED_TRAFFIC["k_epochs<GRAPH> sssp"]
+    traffic = traffic_for("k_epochs<GRAPH> sssp", 0) if (best == "graph" and args.wg == m["wg"]) else None
     return {"metric": "tasks/s", "value": b["tasks_per_s"], "unit": "tasks/s (vertex visits)",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
@@ -614,8 +624,12 @@ def bench_cfg7(args):
             "reached_vertices_per_s": b["reached_per_s"],
             "schedulers": out,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                         "note": "bytes of the visits made, with each reached vertex's arcs read once"},
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "note": "bytes of the visits made, with each reached vertex's arcs read once",
+                         "sector_amplified": {"achieved": round(amp, 1), "frac": round(amp / HBM_PEAK_GBS, 4)},
+                         "traffic_GBps": round(traffic / (b["ms"] * 1e-3) / 1e9, 1) if traffic else None,
+                         "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE of k_epochs and k_arcs per "
+                                         "graph-form run, work-groups of 256 (profiles/sssp_64rmat_weighted.md)"},
             "setup_s": {"generate": round(gen_s, 1), "oracle_dijkstra": round(orc_s, 1)}}
 
 
