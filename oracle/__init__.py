@@ -12,7 +12,7 @@ Thin ctypes wrapper over ``trees_oracle.c``:
   :func:`msort_rec`, :func:`bfs_queue`, :func:`dijkstra`;
 * the epoch-semantics emulator (Task Vector Machine, Section 4.3, in the
   TREES representation of Sections 5.1.2-5.2.4): :func:`fib`,
-  :func:`nqueens`, :func:`msort`, :func:`bfs`, :func:`sssp`, :func:`postorder`,
+  :func:`nqueens`, :func:`msort`, :func:`bfs`, :func:`sssp`, :func:`postorder`, :func:`preorder`,
   :func:`run_batch`, plus checkpoint / resume at an epoch boundary.
 
 Every function here is pinned by ``tests/test_oracle_*.py`` against closed
@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trees_oracle.c")
 LIB_PATH = os.path.join(_HERE, "libtrees_oracle.so")
 
-FIB32, FIB64, MSORT, NQUEENS, BFS, POSTORDER, SSSP = 1, 2, 3, 4, 5, 6, 7
+FIB32, FIB64, MSORT, NQUEENS, BFS, POSTORDER, SSSP, PREORDER = 1, 2, 3, 4, 5, 6, 7, 8
 UNREACHED = 2**31 - 1   # SSSP distance of a vertex the source does not reach
 E_OVERFLOW, E_ENCODING = -3, -8
 
@@ -285,6 +285,20 @@ def postorder(left, right, root: int, records: bool = True) -> tuple[np.ndarray,
     log = np.full(max(n, 1), -1, dtype=np.int32)
     ep = np.full(max(n, 1), -1, dtype=np.int32)
     em = Emulator(POSTORDER, root, ptrs=(L_, R_, log, ep), records=records)
+    em.run()
+    st = em.stats()
+    return log[: st.extra["nvisit"]], ep[:n], st
+
+
+def preorder(left, right, root: int, records: bool = True) -> tuple[np.ndarray, np.ndarray, Run]:
+    """Figure 2's preorder traversal; returns (visit order, epoch of each
+    node's visit, run statistics)."""
+    L_ = np.ascontiguousarray(left, dtype=np.int32)
+    R_ = np.ascontiguousarray(right, dtype=np.int32)
+    n = L_.shape[0]
+    log = np.full(max(n, 1), -1, dtype=np.int32)
+    ep = np.full(max(n, 1), -1, dtype=np.int32)
+    em = Emulator(PREORDER, root, ptrs=(L_, R_, log, ep), records=records)
     em.run()
     st = em.stats()
     return log[: st.extra["nvisit"]], ep[:n], st

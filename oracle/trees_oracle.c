@@ -178,7 +178,7 @@ void orc_dijkstra(int32_t V, const int32_t *row_ptr, const int32_t *col, const i
 /* ------------------------------------------------------------------------- */
 
 enum { ORC_FIB32 = 1, ORC_FIB64 = 2, ORC_MSORT = 3, ORC_NQUEENS = 4, ORC_BFS = 5, ORC_POSTORDER = 6,
-       ORC_SSSP = 7 };
+       ORC_SSSP = 7, ORC_PREORDER = 8 };
 enum { ORC_OK = 0, ORC_E_OVERFLOW = -3, ORC_E_ENCODING = -8, ORC_E_ARGS = -1 };
 
 typedef struct {
@@ -379,6 +379,20 @@ static void body_postorder(orc_tvm *m, int64_t i, int32_t type) {
     }
 }
 
+/* Figure 2: preorder(node) visits node, then forks preorder(right) and
+ * preorder(left); nothing joins. */
+static void body_preorder(orc_tvm *m, int64_t i) {
+    int32_t node = m->a0[i];
+    if (node >= 0) {
+        if (m->visit_log) m->visit_log[m->nvisit] = node;
+        if (m->visit_epoch) m->visit_epoch[node] = (int32_t)m->st.epochs;
+        m->nvisit++;
+        if (tv_fork(m, 1, m->right[node], 0, 0, 0) < 0) return;
+        if (tv_fork(m, 1, m->left[node], 0, 0, 0) < 0) return;
+    }
+    tv_finish(m, i);
+}
+
 /* Construction ---------------------------------------------------------------- */
 
 /*
@@ -387,7 +401,8 @@ static void body_postorder(orc_tvm *m, int64_t i, int32_t type) {
  *   NQUEENS:     p0 = n (1..31)
  *   MSORT:       p0 = N; ptr0 = keys (in/out), ptr1 = tmp (N entries)
  *   BFS:         p0 = V, p1 = source; ptr0 = row_ptr, ptr1 = col_idx, ptr2 = depth (out)
- *   POSTORDER:   p0 = root node (-1 = empty); ptr0 = left, ptr1 = right,
+ *   POSTORDER,
+ *   PREORDER:    p0 = root node (-1 = empty); ptr0 = left, ptr1 = right,
  *                ptr2 = visit log (optional), ptr3 = visit epoch per node (optional)
  * cap: task-vector capacity in entries (0 = unbounded).
  */
@@ -395,7 +410,7 @@ orc_tvm *orc_new(int32_t kind, int32_t p0, int32_t p1, void *ptr0, void *ptr1, v
                  void *ptr3, int64_t cap) {
     orc_tvm *m = (orc_tvm *)calloc(1, sizeof(orc_tvm));
     m->kind = kind;
-    m->ntt = (kind == ORC_BFS || kind == ORC_SSSP) ? 1 : 2;
+    m->ntt = (kind == ORC_BFS || kind == ORC_SSSP || kind == ORC_PREORDER) ? 1 : 2;
     m->cap = cap;
     m->p0 = p0; m->p1 = p1;
     if (!grow(m, 1)) { m->st.status = ORC_E_OVERFLOW; return m; }
@@ -414,7 +429,7 @@ orc_tvm *orc_new(int32_t kind, int32_t p0, int32_t p1, void *ptr0, void *ptr1, v
         m->depth[p1] = 0;
         m->a0[0] = p1;
         break;
-    case ORC_POSTORDER:
+    case ORC_POSTORDER: case ORC_PREORDER:
         m->left = (const int32_t *)ptr0; m->right = (const int32_t *)ptr1;
         m->visit_log = (int32_t *)ptr2; m->visit_epoch = (int32_t *)ptr3;
         m->a0[0] = p0;
@@ -474,6 +489,7 @@ int32_t orc_step(orc_tvm *m) {
         case ORC_BFS: body_bfs(m, i, type); break;
         case ORC_POSTORDER: body_postorder(m, i, type); break;
         case ORC_SSSP: body_sssp(m, i, type); break;
+        case ORC_PREORDER: body_preorder(m, i); break;
         }
         if (m->st.status < 0) return m->st.status;
     }
@@ -591,7 +607,7 @@ orc_tvm *orc_restore(const void *buf, void *ptr0, void *ptr1, void *ptr2, void *
     case ORC_BFS:
         m->row_ptr = (const int32_t *)ptr0; m->col = (const int32_t *)ptr1; m->depth = (int32_t *)ptr2;
         break;
-    case ORC_POSTORDER:
+    case ORC_POSTORDER: case ORC_PREORDER:
         m->left = (const int32_t *)ptr0; m->right = (const int32_t *)ptr1;
         m->visit_log = (int32_t *)ptr2; m->visit_epoch = (int32_t *)ptr3;
         break;
