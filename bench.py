@@ -717,28 +717,22 @@ def bench_cfg5(args):
             "p50_ms": l80["p50_ms"], "p99_ms": l80["p99_ms"], "serving": out}
 
 
-def bench_cfg6(args):
-    """Figure 2's postorder program over a random binary tree of 2^log2tree
-    nodes (a widening beyond the five configurations): every scheduler; each
-    run's visit log is checked against the tree (every node once, after its
-    children)."""
+def run_traversal(args, prog_kind, n, left, right, lt, rt, log):
+    """One traversal program over the bench tree under every scheduler; each
+    run's visit log is checked (every node once; postorder: after its
+    children; preorder: after its parent)."""
     import numpy as np
     import torch
 
-    import inputs
     import paper_1608_00571_amd as T
 
-    n = 1 << args.log2tree
-    left, right = inputs.postorder_tree(n)
-    lt, rt = torch.from_numpy(left).to("cuda"), torch.from_numpy(right).to("cuda")
-    log = torch.empty(n + 1, dtype=torch.int32, device="cuda")
-    arena = (T.tv_bound(T.POSTORDER, [n, 0]) + 64) * T.BYTES_PER_ENTRY
+    arena = (T.tv_bound(prog_kind, [n, 0]) + 64) * T.BYTES_PER_ENTRY
     pos = np.empty(n, dtype=np.int64)
     out = {}
     st = None
     for sched in ("graph", "persistent", "plain"):
         ctx = T.Context(arena, sched=sched, wg=args.wg, max_trees=2)
-        prog = ctx.register(T.POSTORDER)
+        prog = ctx.register(prog_kind)
         times = []
         for it in range(args.warmup + args.steps):
             t = ctx.submit(prog, [n, 0], [lt, rt, log])
@@ -751,15 +745,36 @@ def bench_cfg6(args):
                 times.append(dt)
         ctx.close()
         lg = log.cpu().numpy()
-        assert lg[n] == n, f"postorder {sched}: {lg[n]} visits of {n} nodes"
+        assert lg[n] == n, f"traversal {sched}: {lg[n]} visits of {n} nodes"
         pos[lg[:n]] = np.arange(n)
         for arr in (left, right):
             has = arr >= 0
-            assert np.all(pos[arr[has]] < pos[has]), f"postorder {sched}: a node visited before its child"
+            if prog_kind == T.POSTORDER:
+                assert np.all(pos[arr[has]] < pos[has]), f"postorder {sched}: a node visited before its child"
+            else:
+                assert np.all(pos[arr[has]] > pos[has]), f"preorder {sched}: a node visited before its parent"
         dt = sum(times) / len(times)
-        out[sched] = {"tasks_per_s": st.tasks / dt, "ms": round(dt * 1e3, 3),
-                      "epochs_per_s": st.epochs / dt}
+        out[sched] = {"tasks_per_s": st.tasks / dt, "ms": round(dt * 1e3, 3), "epochs_per_s": st.epochs / dt}
     best = max(("graph", "persistent"), key=lambda k: out[k]["tasks_per_s"])
+    return out, best, st
+
+
+def bench_cfg6(args):
+    """Figure 2's postorder program over a random binary tree of 2^log2tree
+    nodes (a widening beyond the five configurations), with the same tree's
+    preorder program beside it: every scheduler; each run's visit log is
+    checked against the tree."""
+    import torch
+
+    import inputs
+    import paper_1608_00571_amd as T
+
+    n = 1 << args.log2tree
+    left, right = inputs.postorder_tree(n)
+    lt, rt = torch.from_numpy(left).to("cuda"), torch.from_numpy(right).to("cuda")
+    log = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    out, best, st = run_traversal(args, T.POSTORDER, n, left, right, lt, rt, log)
+    pre, pbest, pst = run_traversal(args, T.PREORDER, n, left, right, lt, rt, log)
     return {
         "metric": "tasks/s", "value": out[best]["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[best]["ms"],
@@ -770,6 +785,7 @@ def bench_cfg6(args):
         "epochs_per_s": out[best]["epochs_per_s"],
         "schedulers": out,
         "batched_vs_plain_factor": round(out[best]["tasks_per_s"] / out["plain"]["tasks_per_s"], 2),
+        "preorder": {"tasks": pst.tasks, "epochs": pst.epochs, "sched": pbest, "schedulers": pre},
     }
 
 

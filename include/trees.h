@@ -94,7 +94,8 @@ typedef enum {
   TREES_PROG_NQUEENS = 4,   /* N-queens solution count, one task per partial placement (Section 6.5) */
   TREES_PROG_BFS_CSR = 5,   /* task-per-vertex breadth-first search over CSR (Section 6.3) */
   TREES_PROG_POSTORDER = 6, /* postorder traversal of a binary tree (Figure 2, Section 5.3) */
-  TREES_PROG_SSSP_CSR = 7   /* single-source shortest paths by relaxation over CSR (Section 6.3) */
+  TREES_PROG_SSSP_CSR = 7,  /* single-source shortest paths by relaxation over CSR (Section 6.3) */
+  TREES_PROG_PREORDER = 8   /* preorder traversal of a binary tree (Figure 2) */
 } trees_builtin;
 
 typedef struct {
@@ -170,6 +171,9 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      must form a tree under root (each reachable node has one parent).
  *                      The arena holds 2n+1 entries (every postorder task, null children
  *                      included).
+ *   PREORDER:          args and bufs as POSTORDER.  preorder(node) appends node to log, then
+ *                      forks preorder(right), preorder(left); nothing joins, so a node is
+ *                      visited in the epoch of its depth (the log goes level by level).
  * The arena is sized to the exact task-vector bound of the tree, rounded up to
  * a multiple of 64 entries (arenas start on 64-entry boundaries); if it does
  * not fit in the free budget the call returns NOMEM and changes nothing (the
@@ -205,8 +209,8 @@ trees_status trees_trace(trees_ctx *ctx, uint64_t tree, trees_epoch_rec *out, in
  * kind k (trees_builtin); out[0] accumulates batched launches (one graph
  * replay or one persistent launch each); out[6] and out[7] the plain
  * scheduler's map phase (Section 4.2): its partition-pass and merge-pass
- * launches; out[8] and out[9] the plain scheduler's POSTORDER and SSSP_CSR
- * epochs.  Copies min(n, 10) entries. */
+ * launches; out[8] and out[9] the plain scheduler's traversal (POSTORDER,
+ * PREORDER) and SSSP_CSR epochs.  Copies min(n, 10) entries. */
 typedef struct {
   double ms;           /* summed launch durations */
   uint64_t launches;   /* number of timed launches */

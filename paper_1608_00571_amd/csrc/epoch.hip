@@ -617,17 +617,33 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       case OP_PVISIT:
         act[k] = ACT_FINISH;   // the visit: appended to the tree's log below
         break;
+      case OP_PRE: {
+        // Figure 2: preorder(node) visits node (appended to the log below),
+        // then forks preorder(right), preorder(left); preorder(-1) ends.
+        const int32_t node = a0v[k], n = (int32_t)(tp[k] >> 8);
+        act[k] = ACT_FINISH;
+        if (node < 0) break;
+        if (node >= n) {
+          L.sink = or_agent(MULTI ? &C.hot[slot[k]].flags : &C.plain->flags[P.par], (int32_t)TF_ENCODING);
+          break;
+        }
+        const TreeStatic *T = &C.ts[slot[k]];
+        nk[k] = 2;
+        x1[k] = ((const int32_t *)T->ptr1)[node];
+        x2[k] = ((const int32_t *)T->ptr0)[node];
+      } break;
       default: break;
     }
   }
 
-  // ---- postorder visits: each appends its node to the tree's log, whose
-  // last word (log[n]) counts the visits; one atomic per wavefront when its
-  // visiting lanes share a tree
+  // ---- traversal visits (postorder's visit continuation, a preorder task
+  // with a node): each appends its node to the tree's log, whose last word
+  // (log[n]) counts the visits; one atomic per wavefront when its visiting
+  // lanes share a tree
   if constexpr ((OPS & OPS_PO) != 0) {
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-      const bool vis = op[k] == OP_PVISIT;
+      const bool vis = op[k] == OP_PVISIT || (op[k] == OP_PRE && nk[k] == 2);
       const uint64_t m = ballot64(vis);
       if (!m) continue;
       int32_t *log = vis ? (int32_t *)C.ts[slot[k]].ptr2 : nullptr;
@@ -795,7 +811,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         const int32_t mid = x0[k] + (x1[k] - x0[k]) / 2;
         C.code[c] = nxt; C.a0[c] = x0[k]; C.a1[c] = mid; C.a2[c] = x2[k] + 1;
         C.code[c + 1] = nxt; C.a0[c + 1] = mid; C.a1[c + 1] = x1[k]; C.a2[c + 1] = x2[k] + 1;
-      } else if (op[k] == OP_POST) {
+      } else if (op[k] == OP_POST || op[k] == OP_PRE) {
         C.code[c] = nxt; C.a0[c] = x1[k];
         C.code[c + 1] = nxt; C.a0[c + 1] = x2[k];
       }

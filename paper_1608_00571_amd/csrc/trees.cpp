@@ -69,6 +69,7 @@ uint32_t ops_of_kind(int kind) {
     case TREES_PROG_NQUEENS: return OPS_NQ;
     case TREES_PROG_BFS_CSR: return OPS_BFS;
     case TREES_PROG_POSTORDER: return OPS_PO;
+    case TREES_PROG_PREORDER: return OPS_PO;
     case TREES_PROG_SSSP_CSR: return OPS_SSSP;
   }
   return 0;
@@ -154,10 +155,11 @@ trees_status tv_bound(int kind, const int64_t *args, int nargs, int64_t *out, st
       *out = nargs >= 3 ? args[2] : std::min<int64_t>(8 * args[0], (1ll << 31) - 1);
       return TREES_OK;
     case TREES_PROG_POSTORDER:
-      // every postorder task (the root and two per node, null children
-      // included) holds one entry; a join reuses its own
+    case TREES_PROG_PREORDER:
+      // every traversal task (the root and two per node, null children
+      // included) holds one entry; a postorder join reuses its own
       if (nargs < 2 || args[0] < 1 || args[0] >= (1ll << 24) || args[1] < -1 || args[1] >= args[0])
-        return bad("postorder: need 1 <= n < 2^24 and -1 <= root < n");
+        return bad("traversal: need 1 <= n < 2^24 and -1 <= root < n");
       *out = 2 * args[0] + 1;
       return TREES_OK;
   }
@@ -395,7 +397,8 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     P.seq = ++c->plain_seq ? c->plain_seq : ++c->plain_seq;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     // (6 and 7 are the map passes)
-    const int kslot = t.kind == TREES_PROG_POSTORDER ? 8 : t.kind == TREES_PROG_SSSP_CSR ? 9 : t.kind;
+    const int kslot = (t.kind == TREES_PROG_POSTORDER || t.kind == TREES_PROG_PREORDER) ? 8
+                      : t.kind == TREES_PROG_SSSP_CSR ? 9 : t.kind;
     if (timed(c, kslot)) TRY(take_events(c, kslot, &e0, &e1));
     HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream, e0, e1));
     TRY(wait_mirror(c, P.seq));
@@ -785,7 +788,7 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
   if (c->frozen) return fail(c, TREES_E_STATE, "programs must be registered before the first submit");
   Prog p;
   p.kind = kind;
-  p.ntypes = (kind == TREES_PROG_BFS_CSR || kind == TREES_PROG_SSSP_CSR) ? 1 : 2;
+  p.ntypes = (kind == TREES_PROG_BFS_CSR || kind == TREES_PROG_SSSP_CSR || kind == TREES_PROG_PREORDER) ? 1 : 2;
   p.tbase = c->ntt + 1;
   p.ops = ops;
   if (c->ntt + p.ntypes > kMaxTypes) return fail(c, TREES_E_INVALID, "too many task types");
@@ -798,6 +801,7 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
     case TREES_PROG_NQUEENS: c->dc.op_of_type[p.tbase] = OP_Q; c->dc.op_of_type[p.tbase + 1] = OP_QSUM; break;
     case TREES_PROG_BFS_CSR: c->dc.op_of_type[p.tbase] = OP_VISIT; break;
     case TREES_PROG_POSTORDER: c->dc.op_of_type[p.tbase] = OP_POST; c->dc.op_of_type[p.tbase + 1] = OP_PVISIT; break;
+    case TREES_PROG_PREORDER: c->dc.op_of_type[p.tbase] = OP_PRE; break;
     case TREES_PROG_SSSP_CSR: c->dc.op_of_type[p.tbase] = OP_SVISIT; break;
   }
   c->dc.ntt = c->ntt;
@@ -867,7 +871,8 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       a.ts.ptr2 = (uint64_t)bufs[3].ptr;   // the per-vertex array (as BFS depth)
       a.ts.ptr3 = (uint64_t)bufs[2].ptr;   // arc weights
     } break;
-    case TREES_PROG_POSTORDER: {
+    case TREES_PROG_POSTORDER:
+    case TREES_PROG_PREORDER: {
       const int64_t n = args[0];
       if (nbufs < 3 || !bufs || !bufs[0].ptr || !bufs[1].ptr || !bufs[2].ptr ||
           bufs[0].bytes < (uint64_t)n * 4 || bufs[1].bytes < (uint64_t)n * 4 ||
@@ -903,7 +908,8 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   t.order = c->order++;
   // the kernels' per-tree parameter: nqueens n, or postorder's node count
   // (its visit counter sits at log[n])
-  const bool with_n = P.kind == TREES_PROG_NQUEENS || P.kind == TREES_PROG_POSTORDER;
+  const bool with_n = P.kind == TREES_PROG_NQUEENS || P.kind == TREES_PROG_POSTORDER ||
+                      P.kind == TREES_PROG_PREORDER;
   t.tp = (uint32_t)P.tbase | ((with_n ? (uint32_t)args[0] : 0u) << 8);
   a.ts.tp = t.tp;
   c->staged.push_back(a);

@@ -35,14 +35,15 @@ enum Op : int32_t {
   OP_VISIT = 9,
   OP_POST = 10, OP_PVISIT = 11,
   OP_SVISIT = 12,
-  OP_COUNT = 13
+  OP_PRE = 13,
+  OP_COUNT = 14
 };
 constexpr uint32_t opbit(int op) { return 1u << op; }
 constexpr uint32_t OPS_FIB = opbit(OP_FIB32) | opbit(OP_SUM32) | opbit(OP_FIB64) | opbit(OP_SUM64);
 constexpr uint32_t OPS_NQ = opbit(OP_Q) | opbit(OP_QSUM);
 constexpr uint32_t OPS_MS = opbit(OP_MS) | opbit(OP_MERGE);
 constexpr uint32_t OPS_BFS = opbit(OP_VISIT);
-constexpr uint32_t OPS_PO = opbit(OP_POST) | opbit(OP_PVISIT);
+constexpr uint32_t OPS_PO = opbit(OP_POST) | opbit(OP_PVISIT) | opbit(OP_PRE);   // tree traversals
 constexpr uint32_t OPS_SSSP = opbit(OP_SVISIT);
 constexpr uint32_t OPS_GRAPH = OPS_BFS | OPS_SSSP;   // kernels with the co-operative arc expansion
 constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS | OPS_PO | OPS_SSSP;

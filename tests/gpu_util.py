@@ -6,7 +6,7 @@ import numpy as np
 
 SCHEDS = ["plain", "graph", "persistent"]
 
-KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6, "sssp": 7}
+KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6, "sssp": 7, "preorder": 8}
 
 
 def to_dev_u32(a: np.ndarray):
@@ -74,7 +74,7 @@ class Job:
             self.bufs = (rp, ci, w, d)
             args = [g.V, g.source] + ([self.cap] if self.cap else [])
             self.tree = ctx.submit(prog, args, [rp, ci, w, d])
-        elif self.kind == "postorder":
+        elif self.kind in ("postorder", "preorder"):
             left, right, root = self.bintree
             lt, rt = to_dev_i32(left), to_dev_i32(right)
             log = torch.full((left.shape[0] + 1,), -7, dtype=torch.int32, device="cuda")
@@ -94,7 +94,7 @@ class Job:
             self.out = self.bufs[2].cpu().numpy()
         elif self.kind == "sssp":
             self.out = self.bufs[3].cpu().numpy()
-        elif self.kind == "postorder":
+        elif self.kind in ("postorder", "preorder"):
             self.out = self.bufs[2].cpu().numpy()   # visit log, then the visit count
         return self
 
@@ -119,6 +119,10 @@ def oracle_run(job: Job):
         left, right, root = job.bintree
         log, _, r = oracle.postorder(left, right, root, records=True)
         return r, log
+    if job.kind == "preorder":
+        left, right, root = job.bintree
+        log, ep, r = oracle.preorder(left, right, root, records=True)
+        return r, (log, ep)
     raise ValueError(job.kind)
 
 
@@ -166,17 +170,32 @@ def check_sssp(job: Job):
         assert int(t["forks"].sum()) == s.tasks - 1
 
 
+def check_preorder_log(job: Job, want):
+    """The GPU's visit log holds the oracle's visited nodes once each, in
+    nondecreasing visit epoch (a node's epoch is its depth; the order within
+    an epoch is not unique)."""
+    want_log, want_ep = want
+    n = job.bintree[0].shape[0]
+    cnt = int(job.out[n])
+    assert cnt == len(want_log), f"preorder: {cnt} visits, oracle {len(want_log)}"
+    log = job.out[:cnt]
+    assert np.array_equal(np.sort(log), np.sort(want_log)), "preorder: visited nodes differ"
+    assert np.all(np.diff(want_ep[log]) >= 0), "preorder: a node visited before a shallower one"
+
+
 def assert_matches_oracle(job: Job, check_trace=True):
     if job.kind == "sssp":
         return check_sssp(job)
     want, out = oracle_run(job)
     s = job.stats
-    got = (job.value if job.kind not in ("msort", "bfs", "postorder") else want.result, s.epochs, s.tasks,
+    got = (job.value if job.kind not in ("msort", "bfs", "postorder", "preorder") else want.result, s.epochs, s.tasks,
            s.launched, s.peak_entries)
     exp = (want.result, want.epochs, want.tasks, want.launched, want.peak)
     assert got == exp, f"{job.kind} {job.n}: got {got} want {exp}"
     if job.kind == "postorder":
         check_postorder_log(job, out)
+    elif job.kind == "preorder":
+        check_preorder_log(job, out)
     elif out is not None:
         assert np.array_equal(job.out, out), f"{job.kind}: output differs"
     if check_trace and job.trace is not None and want.records is not None:

@@ -178,6 +178,22 @@ def test_postorder_random_trees(sched):
         assert_matches_oracle(j)
 
 
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_preorder_trees(sched, golden_dir):
+    """Figure 2's preorder program: Figure 3's tree, random binary trees up
+    to 20,000 nodes, a subtree root, a one-node tree and the empty tree; the
+    per-epoch trace equals the oracle's (epoch k runs depth k)."""
+    from tests.test_oracle_tvm import read_fig3
+    left, right, _ = read_fig3(golden_dir)
+    jobs = [Job("preorder", bintree=bintree(left, right, 0))]
+    jobs += [Job("preorder", bintree=bintree(*inputs.binary_tree(n, seed), root))
+             for n, seed, root in [(1, 0, 0), (2, 5, 0), (300, 3, 0), (300, 3, 17), (20000, 7, 0)]]
+    jobs.append(Job("preorder", bintree=bintree([-1], [-1], -1)))
+    for j in jobs:
+        (j,) = run_alone(sched, [j])
+        assert_matches_oracle(j)
+
+
 @pytest.mark.parametrize("sched", ["graph", "persistent"])
 def test_mixed_batch_equals_alone(sched):
     """Independent trees of every program share epochs; each tree's result,
@@ -191,6 +207,7 @@ def test_mixed_batch_equals_alone(sched):
     jobs.append(Job("bfs", graph=inputs.rmat(9, 4)))
     jobs.append(Job("bfs", graph=inputs.csr_from_arcs(5, [(0, 1), (1, 2), (2, 3), (3, 4)], 0)))
     jobs.append(Job("postorder", bintree=bintree(*inputs.binary_tree(500, 11), 0)))
+    jobs.append(Job("preorder", bintree=bintree(*inputs.binary_tree(700, 13), 0)))
     gs, ws = inputs.sssp_graph(9, 12)
     jobs.append(Job("sssp", graph=gs, weights=ws))
     with make_ctx(sched) as ctx:
