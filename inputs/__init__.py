@@ -120,6 +120,15 @@ def arc_weights(E: int, seed: int, lo: int = 1, hi: int = 100) -> np.ndarray:
     return (lo + ((k * np.uint64(hi - lo + 1)) >> np.uint64(32))).astype(np.int32)
 
 
+def complex_signal(n: int, seed: int) -> np.ndarray:
+    """n complex64 values whose real and imaginary parts are uniform on
+    [-1, 1) in steps of 2^-23 (exact in fp32 and fp64): part t of value i is
+    (draw(seed, 2i + t) >> 40) * 2^-23 - 1."""
+    k = keys_u32(2 * n, seed) >> np.uint32(8)
+    v = (k.astype(np.float64) * 2.0 ** -23 - 1.0).astype(np.float32)
+    return (v[0::2] + 1j * v[1::2]).astype(np.complex64)
+
+
 def sssp_graph(scale: int, seed: int, lo: int = 1, hi: int = 100) -> tuple[Graph, np.ndarray]:
     """An R-MAT graph (as for BFS) with arc weights uniform on [lo, hi]."""
     g = rmat(scale, seed)

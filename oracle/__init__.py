@@ -9,10 +9,11 @@ Thin ctypes wrapper over ``trees_oracle.c``:
 
 * plain sequential evaluators (the results the method must reach):
   :func:`fib_iter`, :func:`fib_rec`, :func:`nqueens_rec`, :func:`sort_u32`,
-  :func:`msort_rec`, :func:`bfs_queue`, :func:`dijkstra`;
+  :func:`msort_rec`, :func:`bfs_queue`, :func:`dijkstra`, :func:`dft`;
 * the epoch-semantics emulator (Task Vector Machine, Section 4.3, in the
   TREES representation of Sections 5.1.2-5.2.4): :func:`fib`,
   :func:`nqueens`, :func:`msort`, :func:`bfs`, :func:`sssp`, :func:`postorder`, :func:`preorder`,
+  :func:`fft`,
   :func:`run_batch`, plus checkpoint / resume at an epoch boundary.
 
 Every function here is pinned by ``tests/test_oracle_*.py`` against closed
@@ -32,7 +33,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trees_oracle.c")
 LIB_PATH = os.path.join(_HERE, "libtrees_oracle.so")
 
-FIB32, FIB64, MSORT, NQUEENS, BFS, POSTORDER, SSSP, PREORDER = 1, 2, 3, 4, 5, 6, 7, 8
+FIB32, FIB64, MSORT, NQUEENS, BFS, POSTORDER, SSSP, PREORDER, FFT = 1, 2, 3, 4, 5, 6, 7, 8, 9
+FFT_LEAF = 64   # FFT tasks of at most this many points are leaves
 UNREACHED = 2**31 - 1   # SSSP distance of a vertex the source does not reach
 E_OVERFLOW, E_ENCODING = -3, -8
 
@@ -50,7 +52,7 @@ class _Stats(ctypes.Structure):
 def build_lib() -> str:
     """Compile the oracle with gcc (plain C, -O2)."""
     tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", _SRC, "-o", tmp])
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -75,6 +77,7 @@ def lib():
         L.orc_msort_rec.argtypes = [vp, vp, i64]
         L.orc_bfs_queue.argtypes = [i32, vp, vp, i32, vp]
         L.orc_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
+        L.orc_dft.argtypes = [i64, vp, vp]
         L.orc_new.restype = vp
         L.orc_new.argtypes = [i32, i32, i32, vp, vp, vp, vp, i64]
         L.orc_free.argtypes = [vp]
@@ -145,6 +148,14 @@ def dijkstra(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, weights: np.ndarr
     d = np.empty(V, dtype=np.int32)
     lib().orc_dijkstra(V, rp.ctypes.data, ci.ctypes.data, w.ctypes.data, source, d.ctypes.data)
     return d
+
+
+def dft(x: np.ndarray) -> np.ndarray:
+    """The DFT of x (complex, fp64) by its defining sum, O(n^2)."""
+    xx = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(xx)
+    lib().orc_dft(xx.shape[0], xx.ctypes.data, y.ctypes.data)
+    return y
 
 
 def bfs_queue(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, source: int) -> np.ndarray:
@@ -302,6 +313,19 @@ def preorder(left, right, root: int, records: bool = True) -> tuple[np.ndarray, 
     em.run()
     st = em.stats()
     return log[: st.extra["nvisit"]], ep[:n], st
+
+
+def fft(x: np.ndarray, records: bool = False) -> tuple[np.ndarray, Run]:
+    """The FFT program (radix-2 decimation in time, leaves of FFT_LEAF points
+    by the defining sum) in the epoch emulator, fp64; len(x) a power of two."""
+    xx = np.ascontiguousarray(x, dtype=np.complex128)
+    n = xx.shape[0]
+    m = n.bit_length() - 1
+    assert n >= 1 and n == 1 << m, "fft: the length must be a power of two"
+    y = np.zeros_like(xx)
+    em = Emulator(FFT, m, ptrs=(xx, y, None, None), records=records)
+    em.run()
+    return y, em.stats()
 
 
 def run_batch(emulators: list[Emulator]) -> int:

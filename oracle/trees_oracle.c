@@ -10,7 +10,9 @@
  *  1. Plain sequential evaluators of what each workload computes: Fibonacci
  *     by iteration and by naive recursion, the N-queens solution count by
  *     backtracking, sorting (the C library qsort, plus a sequential
- *     recursive merge sort), and breadth-first search with a FIFO queue.
+ *     recursive merge sort), breadth-first search with a FIFO queue,
+ *     Dijkstra's shortest paths, and the discrete Fourier transform by its
+ *     defining sum (fp64).
  *
  *  2. A step-by-step emulator of the epoch semantics: the Task Vector
  *     Machine of Section 4.3 in the representation TREES uses on the GPU
@@ -36,6 +38,7 @@
  *  - tasks = valid entry executions, join continuations included; idle
  *    (invalid) lanes in a launched range are counted as launched only.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -178,7 +181,7 @@ void orc_dijkstra(int32_t V, const int32_t *row_ptr, const int32_t *col, const i
 /* ------------------------------------------------------------------------- */
 
 enum { ORC_FIB32 = 1, ORC_FIB64 = 2, ORC_MSORT = 3, ORC_NQUEENS = 4, ORC_BFS = 5, ORC_POSTORDER = 6,
-       ORC_SSSP = 7, ORC_PREORDER = 8 };
+       ORC_SSSP = 7, ORC_PREORDER = 8, ORC_FFT = 9 };
 enum { ORC_OK = 0, ORC_E_OVERFLOW = -3, ORC_E_ENCODING = -8, ORC_E_ARGS = -1 };
 
 typedef struct {
@@ -210,6 +213,8 @@ typedef struct orc_tvm {
     const int32_t *left, *right;
     int32_t *visit_log, *visit_epoch;
     int64_t nvisit;
+    const double *fx;     /* FFT input, interleaved (re, im) */
+    double *fy;           /* FFT output */
     orc_stats st;
     orc_rec *recs;
     int64_t nrecs, recs_cap;
@@ -393,6 +398,62 @@ static void body_preorder(orc_tvm *m, int64_t i) {
     tv_finish(m, i);
 }
 
+/* FFT (Section 6.2): recursive radix-2 decimation in time over N = 2^p0
+ * complex values.  FFT(lo, o, ls) transforms the n = N >> ls inputs
+ * x[o + j * 2^ls], j < n (the subsequence that recursion level ls reaches),
+ * into y[lo, lo + n).  A leaf (n <= 64) writes the DFT of its inputs from the
+ * defining sum; otherwise the task forks the even-index half into
+ * y[lo, lo + n/2) and the odd-index half into y[lo + n/2, lo + n) and joins
+ * COMB(lo, ls), which combines them with one butterfly per k < n/2:
+ * y[lo + k] +- exp(-2 pi i k / n) * y[lo + n/2 + k]. */
+#define ORC_FFT_LEAF 64
+static void dft_strided(const double *x, int64_t o, int64_t s, int64_t n, double *y) {
+    for (int64_t k = 0; k < n; ++k) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double a = -2.0 * M_PI * (double)((j * k) % n) / (double)n;
+            const double c = cos(a), sn = sin(a);
+            const double xr = x[2 * (o + j * s)], xi = x[2 * (o + j * s) + 1];
+            sr += xr * c - xi * sn;
+            si += xr * sn + xi * c;
+        }
+        y[2 * k] = sr;
+        y[2 * k + 1] = si;
+    }
+}
+
+static void body_fft(orc_tvm *m, int64_t i, int32_t type) {
+    const int32_t lo = m->a0[i], o = m->a1[i], ls = m->a2[i];
+    const int64_t n = (int64_t)1 << (m->p0 - ls);
+    if (type == 1) {
+        if (n <= ORC_FFT_LEAF) {
+            dft_strided(m->fx, o, (int64_t)1 << ls, n, m->fy + 2 * (int64_t)lo);
+            tv_finish(m, i);
+            return;
+        }
+        if (tv_fork(m, 1, lo, o, ls + 1, 0) < 0) return;
+        if (tv_fork(m, 1, (int32_t)(lo + n / 2), o + (1 << ls), ls + 1, 0) < 0) return;
+        tv_join(m, i, 2, lo, o, ls, 0);
+    } else {
+        double *y = m->fy + 2 * (int64_t)lo;
+        const int64_t h = n / 2;
+        for (int64_t k = 0; k < h; ++k) {
+            const double a = -2.0 * M_PI * (double)k / (double)n;
+            const double c = cos(a), sn = sin(a);
+            const double br = y[2 * (h + k)], bi = y[2 * (h + k) + 1];
+            const double tr = br * c - bi * sn, ti = br * sn + bi * c;
+            const double ur = y[2 * k], ui = y[2 * k + 1];
+            y[2 * k] = ur + tr;           y[2 * k + 1] = ui + ti;
+            y[2 * (h + k)] = ur - tr;     y[2 * (h + k) + 1] = ui - ti;
+        }
+        tv_finish(m, i);
+    }
+}
+
+/* The DFT of n complex values by its defining sum (the plain definition the
+ * FFT program reaches). */
+void orc_dft(int64_t n, const double *x, double *y) { dft_strided(x, 0, 1, n, y); }
+
 /* Construction ---------------------------------------------------------------- */
 
 /*
@@ -404,6 +465,7 @@ static void body_preorder(orc_tvm *m, int64_t i) {
  *   POSTORDER,
  *   PREORDER:    p0 = root node (-1 = empty); ptr0 = left, ptr1 = right,
  *                ptr2 = visit log (optional), ptr3 = visit epoch per node (optional)
+ *   FFT:         p0 = log2 N (0..24); ptr0 = x, ptr1 = y (2N doubles each)
  * cap: task-vector capacity in entries (0 = unbounded).
  */
 orc_tvm *orc_new(int32_t kind, int32_t p0, int32_t p1, void *ptr0, void *ptr1, void *ptr2,
@@ -440,6 +502,11 @@ orc_tvm *orc_new(int32_t kind, int32_t p0, int32_t p1, void *ptr0, void *ptr1, v
         for (int32_t v = 0; v < p0; ++v) m->depth[v] = INT32_MAX;
         m->depth[p1] = 0;
         m->a0[0] = p1;
+        break;
+    case ORC_FFT:
+        if (p0 < 0 || p0 > 24) { m->st.status = ORC_E_ARGS; return m; }
+        m->fx = (const double *)ptr0; m->fy = (double *)ptr1;
+        m->a0[0] = 0; m->a1[0] = 0; m->a2[0] = 0;
         break;
     default: m->st.status = ORC_E_ARGS; return m;
     }
@@ -490,6 +557,7 @@ int32_t orc_step(orc_tvm *m) {
         case ORC_POSTORDER: body_postorder(m, i, type); break;
         case ORC_SSSP: body_sssp(m, i, type); break;
         case ORC_PREORDER: body_preorder(m, i); break;
+        case ORC_FFT: body_fft(m, i, type); break;
         }
         if (m->st.status < 0) return m->st.status;
     }
@@ -615,6 +683,7 @@ orc_tvm *orc_restore(const void *buf, void *ptr0, void *ptr1, void *ptr2, void *
         m->row_ptr = (const int32_t *)ptr0; m->col = (const int32_t *)ptr1;
         m->wts = (const int32_t *)ptr2; m->depth = (int32_t *)ptr3;
         break;
+    case ORC_FFT: m->fx = (const double *)ptr0; m->fy = (double *)ptr1; break;
     default: break;
     }
     return m;
