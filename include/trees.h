@@ -95,7 +95,8 @@ typedef enum {
   TREES_PROG_BFS_CSR = 5,   /* task-per-vertex breadth-first search over CSR (Section 6.3) */
   TREES_PROG_POSTORDER = 6, /* postorder traversal of a binary tree (Figure 2, Section 5.3) */
   TREES_PROG_SSSP_CSR = 7,  /* single-source shortest paths by relaxation over CSR (Section 6.3) */
-  TREES_PROG_PREORDER = 8   /* preorder traversal of a binary tree (Figure 2) */
+  TREES_PROG_PREORDER = 8,  /* preorder traversal of a binary tree (Figure 2) */
+  TREES_PROG_FFT = 9        /* radix-2 FFT of complex fp32 data (Section 6.2) */
 } trees_builtin;
 
 typedef struct {
@@ -174,6 +175,15 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *   PREORDER:          args and bufs as POSTORDER.  preorder(node) appends node to log, then
  *                      forks preorder(right), preorder(left); nothing joins, so a node is
  *                      visited in the epoch of its depth (the log goes level by level).
+ *   FFT:               args = {log2 N}, 0 <= log2 N <= 20; bufs = {x[N], y[N] (out)}, complex
+ *                      fp32 interleaved (re, im), distinct.  y receives the DFT of x,
+ *                      y[k] = sum_j x[j] exp(-2 pi i jk / N) (no scaling), by recursive radix-2
+ *                      decimation in time: FFT(lo, o, ls) transforms x[o + j 2^ls], j < n =
+ *                      N / 2^ls, into y[lo, lo + n); n <= 64 is a leaf (a wavefront runs its
+ *                      butterflies), otherwise it forks the even and odd halves and joins a
+ *                      combine of n/2 butterflies with twiddles exp(-2 pi i k / n), which the
+ *                      work-groups expand co-operatively.  x is not modified.  The arena holds
+ *                      2 max(1, N/64) - 1 entries.
  * The arena is sized to the exact task-vector bound of the tree, rounded up to
  * a multiple of 64 entries (arenas start on 64-entry boundaries); if it does
  * not fit in the free budget the call returns NOMEM and changes nothing (the
@@ -209,8 +219,8 @@ trees_status trees_trace(trees_ctx *ctx, uint64_t tree, trees_epoch_rec *out, in
  * kind k (trees_builtin); out[0] accumulates batched launches (one graph
  * replay or one persistent launch each); out[6] and out[7] the plain
  * scheduler's map phase (Section 4.2): its partition-pass and merge-pass
- * launches; out[8] and out[9] the plain scheduler's traversal (POSTORDER,
- * PREORDER) and SSSP_CSR epochs.  Copies min(n, 10) entries. */
+ * launches; out[8], out[9] and out[10] the plain scheduler's traversal
+ * (POSTORDER, PREORDER), SSSP_CSR and FFT epochs.  Copies min(n, 11) entries. */
 typedef struct {
   double ms;           /* summed launch durations */
   uint64_t launches;   /* number of timed launches */
@@ -218,7 +228,7 @@ typedef struct {
 trees_status trees_kernel_times(trees_ctx *ctx, trees_ktime *out, int32_t n);
 
 /* Choose which launches trees_kernel_times covers: bit k set = time the
- * launches that accumulate in out[k] (all ten by default).  Each timed
+ * launches that accumulate in out[k] (all eleven by default).  Each timed
  * launch carries two HIP events, which cost host time per launch, so a
  * throughput measurement times only the launches it reports.  STATE if the
  * context was created without TREES_F_PROFILE. */

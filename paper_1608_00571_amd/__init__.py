@@ -30,9 +30,9 @@ PLAIN, GRAPH, PERSISTENT, AUTO = 0, 1, 2, 3
 SCHEDS = {"plain": PLAIN, "graph": GRAPH, "persistent": PERSISTENT, "auto": AUTO}
 
 # built-in programs
-FIB_I32, FIB_I64, MSORT_U32, NQUEENS, BFS_CSR, POSTORDER, SSSP_CSR, PREORDER = 1, 2, 3, 4, 5, 6, 7, 8
+FIB_I32, FIB_I64, MSORT_U32, NQUEENS, BFS_CSR, POSTORDER, SSSP_CSR, PREORDER, FFT = range(1, 10)
 PROGRAMS = {"fib32": FIB_I32, "fib64": FIB_I64, "msort": MSORT_U32, "nqueens": NQUEENS, "bfs": BFS_CSR,
-            "postorder": POSTORDER, "sssp": SSSP_CSR, "preorder": PREORDER}
+            "postorder": POSTORDER, "sssp": SSSP_CSR, "preorder": PREORDER, "fft": FFT}
 SSSP_UNREACHED = 2**31 - 1   # distance of a vertex the source does not reach
 
 F_TRACE, F_DEBUG, F_PROFILE, F_NOMAP = 1, 2, 4, 8
@@ -311,10 +311,10 @@ class Context:
         """{kind: (ms, launches)}: HIP-event timed epoch launches; kind 0 =
         batched launches, kinds 1..5 = the plain scheduler's epochs per
         program kind, 6 and 7 = its map phase (partition pass, merge pass),
-        8 and 9 = its traversal (postorder, preorder) and sssp epochs."""
-        arr = (_KTime * 10)()
-        self._check(lib().trees_kernel_times(self.h, arr, 10), "kernel_times")
-        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(10)}
+        8, 9 and 10 = its traversal (postorder, preorder), sssp and fft epochs."""
+        arr = (_KTime * 11)()
+        self._check(lib().trees_kernel_times(self.h, arr, 11), "kernel_times")
+        return {k: (float(arr[k].ms), int(arr[k].launches)) for k in range(11)}
 
     def epoch_times(self) -> np.ndarray:
         """Per-epoch device-clock durations (us) of the last batched run."""

@@ -377,7 +377,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   // the previous chunk already loaded this chunk's entries (same tree, same
   // window); kernels with merge sort or BFS do not prefetch (their register
   // budget is spent on leaf sorts and arc expansion)
-  constexpr bool kPrefetch = MULTI && (OPS & (OPS_MS | OPS_GRAPH)) == 0;
+  constexpr bool kPrefetch = MULTI && (OPS & (OPS_MS | OPS_EXPAND)) == 0;
   const bool hit = kPrefetch && follows && pf.w0 == w0;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -476,7 +476,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   int32_t code[IT], a0v[IT];
   // a1..a3: loaded with code and a0 when the item's program reads them
   // (the program is known from the tree before the entry's type is)
-  constexpr bool kWide = (OPS & (OPS_NQ | OPS_MS)) != 0;
+  constexpr bool kWide = (OPS & (OPS_NQ | OPS_MS | OPS_FFT)) != 0;
   int32_t a1v[IT], a2v[IT], a3v[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
@@ -505,7 +505,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         a0v[k] = C.a0[idx[k]];
         if (kWide) {
           const int pop = L.op_tab[tp[k] & 0xFF];   // the program's first operation
-          if (pop == OP_Q || pop == OP_MS) { a1v[k] = C.a1[idx[k]]; a2v[k] = C.a2[idx[k]]; }
+          if (pop == OP_Q || pop == OP_MS || pop == OP_FFT) { a1v[k] = C.a1[idx[k]]; a2v[k] = C.a2[idx[k]]; }
           if (pop == OP_Q) a3v[k] = C.a3[idx[k]];
         }
       }
@@ -531,12 +531,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   int nk[IT], act[IT];
   int64_t val[IT];
   int32_t x0[IT], x1[IT], x2[IT], x3[IT];
-  bool want_map[IT], leaf[IT];
+  bool want_map[IT], leaf[IT], fleaf[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     nk[k] = 0; act[k] = ACT_NONE; val[k] = 0;
     x0[k] = x1[k] = x2[k] = x3[k] = 0;
-    want_map[k] = false; leaf[k] = false;
+    want_map[k] = false; leaf[k] = false; fleaf[k] = false;
     if (op[k] == OP_NONE) continue;
     const int64_t i = idx[k];
     switch (op[k]) {
@@ -617,6 +617,17 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       case OP_PVISIT:
         act[k] = ACT_FINISH;   // the visit: appended to the tree's log below
         break;
+      case OP_FFT: {
+        // FFT(lo, o, ls): n = 2^(log2 N - ls) points; a leaf is transformed
+        // by a wavefront below; otherwise fork the even and odd halves and
+        // join the combine (which keeps lo, o, ls)
+        const int lg = (int)(tp[k] >> 8) - a2v[k];
+        if (lg <= kFftLeafLog) { act[k] = ACT_FINISH; fleaf[k] = true; }
+        else { act[k] = ACT_JOIN; nk[k] = 2; x0[k] = a0v[k]; x1[k] = a1v[k]; x2[k] = a2v[k]; }
+      } break;
+      case OP_COMB:
+        act[k] = ACT_FINISH;   // its butterflies are expanded co-operatively below
+        break;
       case OP_PRE: {
         // Figure 2: preorder(node) visits node (appended to the log below),
         // then forks preorder(right), preorder(left); preorder(-1) ends.
@@ -659,6 +670,44 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         pos = atomicAdd(&log[n], 1);
       }
       if (vis && pos < n) log[pos] = a0v[k];   // (more visits than nodes: the input was no tree)
+    }
+  }
+
+  // ---- FFT leaves (at most 64 points): each is transformed by a whole
+  // wavefront, lane j holding point j; the lanes load their inputs in
+  // bit-reversed order and run the radix-2 butterfly stages across lanes
+  if constexpr ((OPS & OPS_FFT) != 0) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      uint64_t lm = ballot64(fleaf[k]);
+      while (lm) {
+        const int src = __ffsll((unsigned long long)lm) - 1;
+        lm &= lm - 1;
+        const int32_t lo = __shfl(a0v[k], src, 64), o = __shfl(a1v[k], src, 64);
+        const int32_t ls = __shfl(a2v[k], src, 64), sl = __shfl(slot[k], src, 64);
+        const int lg = (int)(__shfl((int32_t)tp[k], src, 64) >> 8) - ls;   // log2 of the leaf's points
+        const TreeStatic *T = &C.ts[sl];
+        const float2 *x = (const float2 *)T->ptr0;
+        float2 *y = (float2 *)T->ptr1;
+        const int n = 1 << lg;
+        const int j = lg > 0 ? (int)(__builtin_bitreverse32((uint32_t)lane) >> (32 - lg)) : 0;
+        float2 v = make_float2(0.f, 0.f);
+        if (lane < n) v = x[o + (j << ls)];
+        for (int st = 0; st < lg; ++st) {
+          const int h = 1 << st;
+          const float pr = __shfl(v.x, lane ^ h, 64), pi = __shfl(v.y, lane ^ h, 64);
+          float sn, cs;
+          sincospif((float)(lane & (h - 1)) / (float)h, &sn, &cs);   // w = exp(-i pi k / h)
+          if (lane & h) {          // b: the partner holds a; b' = a - w b
+            const float tr = cs * v.x + sn * v.y, ti = cs * v.y - sn * v.x;
+            v = make_float2(pr - tr, pi - ti);
+          } else {                 // a: the partner holds b; a' = a + w b
+            const float tr = cs * pr + sn * pi, ti = cs * pi - sn * pr;
+            v = make_float2(v.x + tr, v.y + ti);
+          }
+        }
+        if (lane < n) y[lo + lane] = v;
+      }
     }
   }
 
@@ -814,6 +863,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       } else if (op[k] == OP_POST || op[k] == OP_PRE) {
         C.code[c] = nxt; C.a0[c] = x1[k];
         C.code[c + 1] = nxt; C.a0[c + 1] = x2[k];
+      } else if (op[k] == OP_FFT) {
+        // even-index half into [lo, lo + n/2), odd-index half after it
+        const int32_t h = 1 << ((int)(tp[k] >> 8) - x2[k] - 1);
+        C.code[c] = nxt; C.a0[c] = x0[k]; C.a1[c] = x1[k]; C.a2[c] = x2[k] + 1;
+        C.code[c + 1] = nxt; C.a0[c + 1] = x0[k] + h; C.a1[c + 1] = x1[k] + (1 << x2[k]);
+        C.a2[c + 1] = x2[k] + 1;
       }
     }
     // ---- join / emit: writes to the item's own entry ----------------------
@@ -825,7 +880,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       C.code[i] = 0;
     } else if (act[k] == ACT_JOIN) {
       C.code[i] = cen[k] * ntt + (int32_t)(tp[k] & 0xFF) + 1;   // local type 2: SUM / QSUM / MERGE / visit
-      if (op[k] != OP_MS && op[k] != OP_POST) {   // (their joins keep their own arguments)
+      if (op[k] != OP_MS && op[k] != OP_POST && op[k] != OP_FFT) {   // (their joins keep their own arguments)
         C.a0[i] = cb;
         if (op[k] == OP_Q) C.a1[i] = nk[k];
       }
@@ -834,13 +889,17 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
 
   __syncthreads();
   phase_mark(C, L, 3);
-  // ---- BFS and SSSP: co-operative expansion of the VISIT items' arcs -------
-  int arc_job = -1;   // >= 0: this chunk's arcs (and its retirement) went to that arc job
-  if constexpr ((OPS & OPS_GRAPH) != 0) {
+  // ---- co-operative expansion: the arcs of BFS and SSSP visits, the
+  // butterflies of FFT combines (units of work spread over the work-group's
+  // lanes after a scan of the items' unit counts)
+  int arc_job = -1;   // >= 0: this chunk's units (and its retirement) went to that job
+  if constexpr ((OPS & OPS_EXPAND) != 0) {
     constexpr bool kSssp = (OPS & OPS_SSSP) != 0;
+    constexpr bool kArcs = (OPS & OPS_GRAPH) != 0;
+    constexpr bool kFft = (OPS & OPS_FFT) != 0;
     bool anyv = false;
 #pragma unroll
-    for (int k = 0; k < IT; ++k) anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT);
+    for (int k = 0; k < IT; ++k) anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT || op[k] == OP_COMB);
     if (__syncthreads_or(anyv)) {
       int32_t deg[IT], row[IT], dvs[IT];
       int dsum = 0;
@@ -859,6 +918,11 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
             dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
             if (dvs[k] < C.a1[idx[k]]) deg[k] = 0;
           }
+        } else if (kFft && op[k] == OP_COMB) {
+          // COMB(lo, ls): n/2 butterflies over outputs [lo, lo + n)
+          row[k] = a0v[k];
+          deg[k] = 1 << ((int)(tp[k] >> 8) - a2v[k] - 1);
+          dvs[k] = -(a2v[k] + 2);
         }
         dsum += deg[k];
       }
@@ -869,11 +933,11 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         V.row[tid * IT + k] = row[k];
         V.pre[tid * IT + k] = pre;
         V.seg[tid * IT + k] = seg[k];
-        if (kSssp) V.dv[tid * IT + k] = dvs[k];
+        if (kSssp || kFft) V.dv[tid * IT + k] = dvs[k];
         pre += deg[k];
       }
       if (tid == 0) V.qn = 0;
-      // many arcs: published as tiles for every work-group (batched forms)
+      // many units: published as tiles for every work-group (batched forms)
       __syncthreads();
       if constexpr (MULTI) {
         if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot);
@@ -885,67 +949,90 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       static_assert(WG * A <= kClaimQ / 2, "claim queue too small for one step");
       int from = 0;   // arcs are visited in increasing order: item searches only move forward
       for (int e0 = 0; e0 < (arc_job >= 0 ? 0 : tot); e0 += WG * A) {
-        int32_t u[A], sseg[A];
+        int32_t u[A], sseg[A];   // arc: head vertex; butterfly: k
         int32_t *dep[A];
-        int32_t dv[A];
+        int32_t dv[A];   // arc: the head's depth or distance as probed; butterfly: log2 of n/2
         int32_t nd[A];   // SSSP arc: the distance it offers its head; BFS arc: -1
+        float2 *fy[A];   // butterfly: the combine's first output
+        float2 bu[A], bb[A];
+        bool bf[A];
 #pragma unroll
         for (int a = 0; a < A; ++a) {
           const int e = e0 + a * WG + tid;
           sseg[a] = -1;
           nd[a] = -1;
+          bf[a] = false;
           if (e < tot) {
             int lo = from, hi = kChunk;   // last item with pre <= e
             while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
             from = lo;
             sseg[a] = V.seg[lo];
             const TreeStatic *ST = &C.ts[L.seg_slot[sseg[a]]];
-            const int32_t arc = V.row[lo] + (e - V.pre[lo]);
-            u[a] = ((const int32_t *)ST->ptr1)[arc];
-            dep[a] = (int32_t *)ST->ptr2;
-            if (kSssp && V.dv[lo] >= 0) nd[a] = V.dv[lo] + ((const int32_t *)ST->ptr3)[arc];
+            if (kFft && V.dv[lo] <= -2) {
+              bf[a] = true;
+              fy[a] = (float2 *)ST->ptr1 + V.row[lo];
+              u[a] = e - V.pre[lo];
+              dv[a] = (int)(L.seg_tp[sseg[a]] >> 8) + V.dv[lo] + 1;   // log2 N - ls - 1
+            } else if (kArcs) {
+              const int32_t arc = V.row[lo] + (e - V.pre[lo]);
+              u[a] = ((const int32_t *)ST->ptr1)[arc];
+              dep[a] = (int32_t *)ST->ptr2;
+              if (kSssp && V.dv[lo] >= 0) nd[a] = V.dv[lo] + ((const int32_t *)ST->ptr3)[arc];
+            }
           }
         }
 #pragma unroll
-        for (int a = 0; a < A; ++a) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;   // probes issued together
+        for (int a = 0; a < A; ++a) {   // probes and butterfly inputs issued together
+          if (kFft && bf[a]) { bu[a] = fy[a][u[a]]; bb[a] = fy[a][u[a] + (1 << dv[a])]; }
+          else if (kArcs) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;
+        }
 #pragma unroll
         for (int a = 0; a < A; ++a) {
-          // BFS: test, then claim an unreached vertex; SSSP: test, then lower
-          // the head's distance; either way the winner forks a visit of it
+          // butterfly k: y[k], y[k + n/2] = y[k] +- exp(-2 pi i k / n) y[k + n/2].
+          // BFS arc: test, then claim an unreached vertex; SSSP arc: test, then
+          // lower the head's distance; either way the winner forks a visit of it
           bool won = false;
-          if (sseg[a] >= 0) {
+          if (kFft && bf[a]) {
+            float sn, cs;
+            sincospif((float)u[a] / (float)(1 << dv[a]), &sn, &cs);
+            const float tr = cs * bb[a].x + sn * bb[a].y, ti = cs * bb[a].y - sn * bb[a].x;
+            fy[a][u[a]] = make_float2(bu[a].x + tr, bu[a].y + ti);
+            fy[a][u[a] + (1 << dv[a])] = make_float2(bu[a].x - tr, bu[a].y - ti);
+          } else if (kArcs && sseg[a] >= 0) {
             if (kSssp && nd[a] >= 0) won = nd[a] < dv[a] && atomicMin(&dep[a][u[a]], nd[a]) > nd[a];
             else won = dv[a] == -1 && atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1;
           }
-          if (won) {
+          if (kArcs && won) {
             const int q = atomicAdd(&V.qn, 1);
             V.qu[q] = u[a];
             V.qs[q] = (int16_t)sseg[a];
             if (kSssp) V.qd[q] = nd[a];
           }
         }
-        __syncthreads();
-        const int qn = V.qn;
-        if (qn > kClaimQ - WG * A || e0 + WG * A >= tot) {
-          for (int q0 = 0; q0 < qn; q0 += WG) {
-            const int q = q0 + tid;
-            const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
-            if (q < qn) V.qo[q] = (int16_t)o;
-          }
-          seg_commit<WG, MULTI>(C, L, P, false);
-          for (int q = tid; q < qn; q += WG) {
-            const int sseg = V.qs[q];
-            const int32_t vb = L.seg_base[sseg];
-            if (vb >= 0) {
-              const int64_t c = ((int64_t)L.seg_tb[sseg] << 6) + vb + V.qo[q];
-              C.code[c] = (L.seg_cen[sseg] + 1) * ntt + (int32_t)(L.seg_tp[sseg] & 0xFF);
-              C.a0[c] = V.qu[q];
-              if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
+        if constexpr (kArcs) {
+          __syncthreads();
+          const int qn = V.qn;
+          if (qn > kClaimQ - WG * A || e0 + WG * A >= tot) {
+            for (int q0 = 0; q0 < qn; q0 += WG) {
+              const int q = q0 + tid;
+              const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
+              if (q < qn) V.qo[q] = (int16_t)o;
             }
+            seg_commit<WG, MULTI>(C, L, P, false);
+            for (int q = tid; q < qn; q += WG) {
+              const int sseg = V.qs[q];
+              const int32_t vb = L.seg_base[sseg];
+              if (vb >= 0) {
+                const int64_t c = ((int64_t)L.seg_tb[sseg] << 6) + vb + V.qo[q];
+                C.code[c] = (L.seg_cen[sseg] + 1) * ntt + (int32_t)(L.seg_tp[sseg] & 0xFF);
+                C.a0[c] = V.qu[q];
+                if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
+              }
+            }
+            __syncthreads();
+            if (tid == 0) V.qn = 0;
+            __syncthreads();
           }
-          __syncthreads();
-          if (tid == 0) V.qn = 0;
-          __syncthreads();
         }
       }
     }
@@ -1142,7 +1229,7 @@ __device__ void publish(const DevCtx &C, int32_t par, uint32_t seq) {
 
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
-  using VL = typename std::conditional<(OPS & OPS_GRAPH) != 0, VisitLds, NoVisitLds>::type;
+  using VL = typename std::conditional<(OPS & OPS_EXPAND) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG, 1> L;   // one tree: one segment
   __shared__ VL V;
   lds_init<WG>(C, L);
@@ -1179,15 +1266,18 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   }
 }
 
-// The arc phase: every work-group claims tiles of the epoch's arc jobs.  A
-// tile expands arcs [t * tile, (t + 1) * tile) of its job with the same
-// steps as a chunk's own expansion (probe, then a BFS claim by CAS or an
-// SSSP relaxation by atomic min, LDS queue, child entries in bulk); the
-// work-group that expands a job's last tile retires the owner chunk's items,
-// running Phase 3 of a tree whose last items they were.
+// The arc phase: every work-group claims tiles of the epoch's expansion
+// jobs.  A tile expands units [t * tile, (t + 1) * tile) of its job with the
+// same steps as a chunk's own expansion (arcs: probe, then a BFS claim by CAS
+// or an SSSP relaxation by atomic min, LDS queue, child entries in bulk; FFT
+// butterflies: load, combine, store); the work-group that expands a job's
+// last tile retires the owner chunk's items, running Phase 3 of a tree whose
+// last items they were.
 template <int WG, uint32_t OPS>
 __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
   constexpr bool kSssp = (OPS & OPS_SSSP) != 0;
+  constexpr bool kArcs = (OPS & OPS_GRAPH) != 0;
+  constexpr bool kFft = (OPS & OPS_FFT) != 0;
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
   const int32_t ntt = C.ntt;
@@ -1213,7 +1303,7 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
       V.pre[i] = it[i];
       V.row[i] = it[kChunk + i];
       V.seg[i] = it[2 * kChunk + i];
-      if (kSssp) V.dv[i] = it[3 * kChunk + i];
+      if (kSssp || kFft) V.dv[i] = it[3 * kChunk + i];
     }
     const int32_t *sg = C.arc_seg + J->sbase;
     for (int q = tid; q < nseg; q += WG) {
@@ -1232,61 +1322,83 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
       int32_t *dep[A];
       int32_t dv[A];
       int32_t nd[A];   // SSSP arc: the distance it offers its head; BFS arc: -1
+      float2 *fy[A];
+      float2 bu[A], bb[A];
+      bool bf[A];
 #pragma unroll
       for (int a = 0; a < A; ++a) {
         const int e = e0 + a * WG + tid;
         sseg[a] = -1;
         nd[a] = -1;
+        bf[a] = false;
         if (e < e_hi) {
           int lo = from, hi = ihi + 1;   // last item with pre <= e
           while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
           from = lo;
           sseg[a] = V.seg[lo];
           const TreeStatic *ST = &C.ts[L.seg_slot[sseg[a]]];
-          const int32_t arc = V.row[lo] + (e - V.pre[lo]);
-          u[a] = ((const int32_t *)ST->ptr1)[arc];
-          dep[a] = (int32_t *)ST->ptr2;
-          if (kSssp && V.dv[lo] >= 0) nd[a] = V.dv[lo] + ((const int32_t *)ST->ptr3)[arc];
+          if (kFft && V.dv[lo] <= -2) {
+            bf[a] = true;
+            fy[a] = (float2 *)ST->ptr1 + V.row[lo];
+            u[a] = e - V.pre[lo];
+            dv[a] = (int)(L.seg_tp[sseg[a]] >> 8) + V.dv[lo] + 1;   // log2 N - ls - 1
+          } else if (kArcs) {
+            const int32_t arc = V.row[lo] + (e - V.pre[lo]);
+            u[a] = ((const int32_t *)ST->ptr1)[arc];
+            dep[a] = (int32_t *)ST->ptr2;
+            if (kSssp && V.dv[lo] >= 0) nd[a] = V.dv[lo] + ((const int32_t *)ST->ptr3)[arc];
+          }
         }
       }
 #pragma unroll
-      for (int a = 0; a < A; ++a) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;   // probes issued together
+      for (int a = 0; a < A; ++a) {   // probes and butterfly inputs issued together
+        if (kFft && bf[a]) { bu[a] = fy[a][u[a]]; bb[a] = fy[a][u[a] + (1 << dv[a])]; }
+        else if (kArcs) dv[a] = sseg[a] >= 0 ? dep[a][u[a]] : 0;
+      }
 #pragma unroll
       for (int a = 0; a < A; ++a) {
         bool won = false;
-        if (sseg[a] >= 0) {
+        if (kFft && bf[a]) {
+          float sn, cs;
+          sincospif((float)u[a] / (float)(1 << dv[a]), &sn, &cs);
+          const float tr = cs * bb[a].x + sn * bb[a].y, ti = cs * bb[a].y - sn * bb[a].x;
+          fy[a][u[a]] = make_float2(bu[a].x + tr, bu[a].y + ti);
+          fy[a][u[a] + (1 << dv[a])] = make_float2(bu[a].x - tr, bu[a].y - ti);
+        } else if (kArcs && sseg[a] >= 0) {
           if (kSssp && nd[a] >= 0) won = nd[a] < dv[a] && atomicMin(&dep[a][u[a]], nd[a]) > nd[a];
           else won = dv[a] == -1 && atomicCAS(&dep[a][u[a]], -1, L.seg_cen[sseg[a]] + 1) == -1;
         }
-        if (won) {
+        if (kArcs && won) {
           const int q = atomicAdd(&V.qn, 1);
           V.qu[q] = u[a];
           V.qs[q] = (int16_t)sseg[a];
           if (kSssp) V.qd[q] = nd[a];
         }
       }
-      __syncthreads();
-      const int qn = V.qn;
-      if (qn > kClaimQ - WG * A || e0 + WG * A >= e_hi) {
-        for (int q0 = 0; q0 < qn; q0 += WG) {
-          const int q = q0 + tid;
-          const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
-          if (q < qn) V.qo[q] = (int16_t)o;
-        }
-        seg_commit<WG, true>(C, L, P, false);
-        for (int q = tid; q < qn; q += WG) {
-          const int ss = V.qs[q];
-          const int32_t vb = L.seg_base[ss];
-          if (vb >= 0) {
-            const int64_t c = ((int64_t)L.seg_tb[ss] << 6) + vb + V.qo[q];
-            C.code[c] = (L.seg_cen[ss] + 1) * ntt + (int32_t)(L.seg_tp[ss] & 0xFF);
-            C.a0[c] = V.qu[q];
-            if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
+      if constexpr (kArcs) {
+        __syncthreads();
+        const int qn = V.qn;
+        if (qn > kClaimQ - WG * A || e0 + WG * A >= e_hi) {
+          for (int q0 = 0; q0 < qn; q0 += WG) {
+            const int q = q0 + tid;
+            const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
+            if (q < qn) V.qo[q] = (int16_t)o;
           }
+          seg_commit<WG, true>(C, L, P, false);
+          for (int q = tid; q < qn; q += WG) {
+            const int ss = V.qs[q];
+            const int32_t vb = L.seg_base[ss];
+            if (vb >= 0) {
+              const int64_t c = ((int64_t)L.seg_tb[ss] << 6) + vb + V.qo[q];
+              C.code[c] = (L.seg_cen[ss] + 1) * ntt + (int32_t)(L.seg_tp[ss] & 0xFF);
+              C.a0[c] = V.qu[q];
+              if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
+            }
+          }
+          __syncthreads();
+          if (tid == 0) V.qn = 0;
+          __syncthreads();
         }
-        __syncthreads();
-        if (tid == 0) V.qn = 0;
-        __syncthreads();
       }
     }
     // the tile's forks are performed before the tile counts as done
@@ -1413,7 +1525,7 @@ template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
   using MapL = typename std::conditional<kMap, MapLds<kMapTile>, NoMapLds>::type;
-  using VL = typename std::conditional<(OPS & OPS_GRAPH) != 0, VisitLds, NoVisitLds>::type;
+  using VL = typename std::conditional<(OPS & OPS_EXPAND) != 0, VisitLds, NoVisitLds>::type;
   __shared__ Lds<WG> L;
   __shared__ MapL M;
   __shared__ VL V;
@@ -1451,7 +1563,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     // a work-group that drew expensive chunks takes fewer.  The others take
     // one even share each.
     const uint32_t nchunks = (S + kChunk - 1) / kChunk;
-    constexpr bool kGuided = (OPS & OPS_GRAPH) != 0;
+    constexpr bool kGuided = (OPS & OPS_EXPAND) != 0;
     const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
     PendingFinish pend;
     Prefetch<kChunk / WG> pf;
@@ -1474,7 +1586,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     settle(C, pend);
     phase_mark(C, L, 6);
     bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
-    if constexpr ((OPS & OPS_GRAPH) != 0) {
+    if constexpr ((OPS & OPS_EXPAND) != 0) {
       if (persistent && ok) {
         if (threadIdx.x == 0) s_hdr[4] = (uint32_t)H->arc_phase;
         __syncthreads();
@@ -1494,7 +1606,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
 }
 
 // The arc phase of a captured chain: launched after each epoch launch of a
-// kernel with BFS or SSSP; returns at once unless the epoch published arc jobs.  The
+// kernel with BFS, SSSP or FFT; returns at once unless the epoch published arc jobs.  The
 // last work-group to finish builds the next work list (the epoch launch left
 // it for this launch).
 template <int WG, uint32_t OPS>
@@ -1578,10 +1690,11 @@ __global__ void k_release(DevCtx C, int32_t slot) {
   M(WG, OPS_FIB | OPS_NQ)         \
   M(WG, OPS_MS)                   \
   M(WG, OPS_GRAPH)                \
+  M(WG, OPS_FFT)                  \
   M(WG, OPS_ALL)
 
 static uint32_t pick_ops(uint32_t need) {
-  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_GRAPH, OPS_ALL};
+  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_GRAPH, OPS_FFT, OPS_ALL};
   for (uint32_t s : sets)
     if ((need & ~s) == 0) return s;
   return OPS_ALL;
@@ -1650,9 +1763,9 @@ hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int p
 hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s) {
   const void *fn = nullptr;
   switch (wg) {
-    case 256: fn = (const void *)&k_arcs<256, OPS_GRAPH>; break;
-    case 512: fn = (const void *)&k_arcs<512, OPS_GRAPH>; break;
-    case 1024: fn = (const void *)&k_arcs<1024, OPS_GRAPH>; break;
+    case 256: fn = (const void *)&k_arcs<256, OPS_EXPAND>; break;
+    case 512: fn = (const void *)&k_arcs<512, OPS_EXPAND>; break;
+    case 1024: fn = (const void *)&k_arcs<1024, OPS_EXPAND>; break;
     default: return hipErrorInvalidValue;
   }
   (void)need;

@@ -70,6 +70,7 @@ uint32_t ops_of_kind(int kind) {
     case TREES_PROG_BFS_CSR: return OPS_BFS;
     case TREES_PROG_POSTORDER: return OPS_PO;
     case TREES_PROG_PREORDER: return OPS_PO;
+    case TREES_PROG_FFT: return OPS_FFT;
     case TREES_PROG_SSSP_CSR: return OPS_SSSP;
   }
   return 0;
@@ -154,6 +155,15 @@ trees_status tv_bound(int kind, const int64_t *args, int nargs, int64_t *out, st
       if (nargs >= 3 && (args[2] < 1 || args[2] >= (1ll << 31))) return bad("sssp: need 1 <= max_entries < 2^31");
       *out = nargs >= 3 ? args[2] : std::min<int64_t>(8 * args[0], (1ll << 31) - 1);
       return TREES_OK;
+    case TREES_PROG_FFT: {
+      // the binary tree of FFT tasks down to 64-point leaves: its nodes
+      // (a combine reuses its own entry)
+      if (nargs < 1 || args[0] < 0 || args[0] > kFftMaxLog)
+        return bad("fft: need 0 <= log2 N <= 20");
+      const int64_t leaves = args[0] > kFftLeafLog ? (1ll << (args[0] - kFftLeafLog)) : 1;
+      *out = 2 * leaves - 1;
+      return TREES_OK;
+    }
     case TREES_PROG_POSTORDER:
     case TREES_PROG_PREORDER:
       // every traversal task (the root and two per node, null children
@@ -213,8 +223,8 @@ struct trees_ctx {
   // last epoch, so timing adds no synchronisation per epoch
   std::vector<hipEvent_t> evpool;
   std::vector<std::pair<int, size_t>> evpend;   // (ktime slot, first event of the pair)
-  trees_ktime ktime[10] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes, 8/9 plain postorder/sssp
-  uint32_t prof_mask = 0x3FFu;  // which of the slots above are timed
+  trees_ktime ktime[11] = {};  // 1..5 plain epochs per kind, 0 batched, 6/7 map passes, 8/9/10 plain traversal/sssp/fft
+  uint32_t prof_mask = 0x7FFu;  // which of the slots above are timed
   double clock_hz = 1e8;
   double timeout_s = 60.0;   // host and device waits give up after this long
   bool running = false;
@@ -398,7 +408,7 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
     hipEvent_t e0 = nullptr, e1 = nullptr;
     // (6 and 7 are the map passes)
     const int kslot = (t.kind == TREES_PROG_POSTORDER || t.kind == TREES_PROG_PREORDER) ? 8
-                      : t.kind == TREES_PROG_SSSP_CSR ? 9 : t.kind;
+                      : t.kind == TREES_PROG_SSSP_CSR ? 9 : t.kind == TREES_PROG_FFT ? 10 : t.kind;
     if (timed(c, kslot)) TRY(take_events(c, kslot, &e0, &e1));
     HIPCHK(c, launch_plain(c->dc, P, c->wg, need, c->stream, e0, e1));
     TRY(wait_mirror(c, P.seq));
@@ -547,7 +557,7 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < c->chunk; ++k) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
-      if (e == hipSuccess && (need & OPS_GRAPH)) e = launch_arcs(c->dc, c->wg, need, grid, c->stream);
+      if (e == hipSuccess && (need & OPS_EXPAND)) e = launch_arcs(c->dc, c->wg, need, grid, c->stream);
       if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
         e = launch_map(c->dc, kMapWG, 0, 1, c->ncu * 8, c->ncu * 8, c->stream, nullptr);
       if (e != hipSuccess) {
@@ -802,6 +812,7 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
     case TREES_PROG_BFS_CSR: c->dc.op_of_type[p.tbase] = OP_VISIT; break;
     case TREES_PROG_POSTORDER: c->dc.op_of_type[p.tbase] = OP_POST; c->dc.op_of_type[p.tbase + 1] = OP_PVISIT; break;
     case TREES_PROG_PREORDER: c->dc.op_of_type[p.tbase] = OP_PRE; break;
+    case TREES_PROG_FFT: c->dc.op_of_type[p.tbase] = OP_FFT; c->dc.op_of_type[p.tbase + 1] = OP_COMB; break;
     case TREES_PROG_SSSP_CSR: c->dc.op_of_type[p.tbase] = OP_SVISIT; break;
   }
   c->dc.ntt = c->ntt;
@@ -871,6 +882,16 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       a.ts.ptr2 = (uint64_t)bufs[3].ptr;   // the per-vertex array (as BFS depth)
       a.ts.ptr3 = (uint64_t)bufs[2].ptr;   // arc weights
     } break;
+    case TREES_PROG_FFT: {
+      const uint64_t bytes = (uint64_t)8 << args[0];
+      if (nbufs < 2 || !bufs || !bufs[0].ptr || !bufs[1].ptr || bufs[0].bytes < bytes || bufs[1].bytes < bytes ||
+          bufs[0].ptr == bufs[1].ptr)
+        return fail(c, TREES_E_INVALID, "fft: need bufs {x[N], y[N]} of complex fp32, distinct");
+      a.a0 = 0; a.a1 = 0; a.a2 = 0;   // FFT(lo = 0, o = 0, ls = 0): the whole input
+      a.ts.p0 = (int32_t)args[0];
+      a.ts.ptr0 = (uint64_t)bufs[0].ptr;
+      a.ts.ptr1 = (uint64_t)bufs[1].ptr;
+    } break;
     case TREES_PROG_POSTORDER:
     case TREES_PROG_PREORDER: {
       const int64_t n = args[0];
@@ -909,7 +930,7 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   // the kernels' per-tree parameter: nqueens n, or postorder's node count
   // (its visit counter sits at log[n])
   const bool with_n = P.kind == TREES_PROG_NQUEENS || P.kind == TREES_PROG_POSTORDER ||
-                      P.kind == TREES_PROG_PREORDER;
+                      P.kind == TREES_PROG_PREORDER || P.kind == TREES_PROG_FFT;
   t.tp = (uint32_t)P.tbase | ((with_n ? (uint32_t)args[0] : 0u) << 8);
   a.ts.tp = t.tp;
   c->staged.push_back(a);
@@ -1059,7 +1080,7 @@ trees_status trees_profile_mask(trees_ctx *c, uint32_t mask) {
   if (!c) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
-  c->prof_mask = mask & 0x3FFu;
+  c->prof_mask = mask & 0x7FFu;
   return TREES_OK;
 }
 
@@ -1067,7 +1088,7 @@ trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
   if (!c || !out) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->profile) return fail(c, TREES_E_STATE, "context created without TREES_F_PROFILE");
-  for (int k = 0; k < n && k < 10; ++k) out[k] = c->ktime[k];
+  for (int k = 0; k < n && k < 11; ++k) out[k] = c->ktime[k];
   return TREES_OK;
 }
 

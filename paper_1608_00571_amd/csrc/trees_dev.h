@@ -36,7 +36,8 @@ enum Op : int32_t {
   OP_POST = 10, OP_PVISIT = 11,
   OP_SVISIT = 12,
   OP_PRE = 13,
-  OP_COUNT = 14
+  OP_FFT = 14, OP_COMB = 15,
+  OP_COUNT = 16
 };
 constexpr uint32_t opbit(int op) { return 1u << op; }
 constexpr uint32_t OPS_FIB = opbit(OP_FIB32) | opbit(OP_SUM32) | opbit(OP_FIB64) | opbit(OP_SUM64);
@@ -45,8 +46,12 @@ constexpr uint32_t OPS_MS = opbit(OP_MS) | opbit(OP_MERGE);
 constexpr uint32_t OPS_BFS = opbit(OP_VISIT);
 constexpr uint32_t OPS_PO = opbit(OP_POST) | opbit(OP_PVISIT) | opbit(OP_PRE);   // tree traversals
 constexpr uint32_t OPS_SSSP = opbit(OP_SVISIT);
-constexpr uint32_t OPS_GRAPH = OPS_BFS | OPS_SSSP;   // kernels with the co-operative arc expansion
-constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS | OPS_PO | OPS_SSSP;
+constexpr uint32_t OPS_GRAPH = OPS_BFS | OPS_SSSP;   // arcs
+constexpr uint32_t OPS_FFT = opbit(OP_FFT) | opbit(OP_COMB);
+constexpr uint32_t OPS_EXPAND = OPS_GRAPH | OPS_FFT;   // kernels with the co-operative expansion
+constexpr uint32_t OPS_ALL = OPS_FIB | OPS_NQ | OPS_MS | OPS_BFS | OPS_PO | OPS_SSSP | OPS_FFT;
+constexpr int kFftLeafLog = 6;      // FFT tasks of at most 2^6 points are leaves (one wavefront)
+constexpr int kFftMaxLog = 20;      // largest FFT: 2^20 points (a chunk's butterflies stay below 2^31)
 
 // Tree status values (TreeState::status).
 enum : int32_t { TS_FREE = 0, TS_LIVE = 1, TS_DONE = 2, TS_PAUSED = 3 };
@@ -179,7 +184,8 @@ struct alignas(64) ArcJob {
   int32_t pad[9];
 };
 // Per job: item arrays pre, row, seg, dv (kChunkItems each, lane-major order
-// of the owner chunk; dv: an SSSP item's distance, -1 for BFS).  Per segment, a record in the pool's seven planes: slot,
+// of the owner chunk; dv: an SSSP item's distance, -1 for BFS, -(ls + 2) for
+// an FFT combine of level ls, whose row is its first output).  Per segment, a record in the pool's seven planes: slot,
 // cen, tb, tp, items (retired by the job), range (the segment's items this
 // epoch) and jv (joins | valid << 16).
 constexpr int kArcItemWords = 4 * kChunkItems;

@@ -6,7 +6,8 @@ import numpy as np
 
 SCHEDS = ["plain", "graph", "persistent"]
 
-KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6, "sssp": 7, "preorder": 8}
+KIND_OF = {"fib32": 1, "fib64": 2, "msort": 3, "nqueens": 4, "bfs": 5, "postorder": 6, "sssp": 7, "preorder": 8,
+           "fft": 9}
 
 
 def to_dev_u32(a: np.ndarray):
@@ -32,12 +33,14 @@ def register_all(ctx, jobs):
 class Job:
     """One tree: its spec, payload tensors and, after collect(), its outputs."""
 
-    def __init__(self, kind: str, n=None, keys=None, graph=None, bintree=None, weights=None, cap=None):
+    def __init__(self, kind: str, n=None, keys=None, graph=None, bintree=None, weights=None, cap=None,
+                 signal=None):
         # bintree (postorder): (left, right, root) int32 child arrays, -1 = none
         # weights (sssp): int32 arc weights in the graph's CSR order; cap: the
         # tree's task-vector entries (default 8 V)
         self.kind, self.n, self.keys, self.graph, self.bintree = kind, n, keys, graph, bintree
         self.weights, self.cap = weights, cap
+        self.signal = signal   # fft: complex64 input, a power-of-two length
         self.tree = None
         self.value = None
         self.stats = None
@@ -74,6 +77,12 @@ class Job:
             self.bufs = (rp, ci, w, d)
             args = [g.V, g.source] + ([self.cap] if self.cap else [])
             self.tree = ctx.submit(prog, args, [rp, ci, w, d])
+        elif self.kind == "fft":
+            x = np.ascontiguousarray(self.signal, dtype=np.complex64)
+            xt = torch.from_numpy(x.view(np.float32).copy()).to("cuda")
+            y = torch.full_like(xt, float("nan"))
+            self.bufs = (xt, y)
+            self.tree = ctx.submit(prog, [x.shape[0].bit_length() - 1], [xt, y])
         elif self.kind in ("postorder", "preorder"):
             left, right, root = self.bintree
             lt, rt = to_dev_i32(left), to_dev_i32(right)
@@ -96,6 +105,10 @@ class Job:
             self.out = self.bufs[3].cpu().numpy()
         elif self.kind in ("postorder", "preorder"):
             self.out = self.bufs[2].cpu().numpy()   # visit log, then the visit count
+        elif self.kind == "fft":
+            self.out = self.bufs[1].cpu().numpy().view(np.complex64)
+            assert np.array_equal(self.bufs[0].cpu().numpy().view(np.complex64),
+                                  np.asarray(self.signal, dtype=np.complex64)), "fft: the input was modified"
         return self
 
 
@@ -119,6 +132,9 @@ def oracle_run(job: Job):
         left, right, root = job.bintree
         log, _, r = oracle.postorder(left, right, root, records=True)
         return r, log
+    if job.kind == "fft":
+        y, r = oracle.fft(np.asarray(job.signal, dtype=np.complex128), records=True)
+        return r, y
     if job.kind == "preorder":
         left, right, root = job.bintree
         log, ep, r = oracle.preorder(left, right, root, records=True)
@@ -183,12 +199,33 @@ def check_preorder_log(job: Job, want):
     assert np.all(np.diff(want_ep[log]) >= 0), "preorder: a node visited before a shallower one"
 
 
+def fft_tolerance(n: int) -> float:
+    """Norm-wise relative error bound of a radix-2 FFT in fp32 against the
+    exact DFT: log2(n) * eta / (1 - log2(n) * eta), eta = mu + gamma_4 (sqrt 2 + mu)
+    (Higham, Accuracy and Stability of Numerical Algorithms, Thm 24.2), with
+    the twiddle error mu taken as 4u and u = 2^-24; about 10 u log2 n."""
+    u = 2.0 ** -24
+    mu = 4 * u
+    eta = mu + (4 * u / (1 - 4 * u)) * (np.sqrt(2) + mu)
+    t = max(1, int(n).bit_length() - 1) * eta
+    return t / (1 - t)
+
+
+def check_fft(job: Job, want_y: np.ndarray):
+    got = job.out.astype(np.complex128)
+    assert np.all(np.isfinite(got)), "fft: outputs not written"
+    err = np.linalg.norm(got - want_y) / max(np.linalg.norm(want_y), 1e-30)
+    tol = fft_tolerance(want_y.shape[0])
+    assert err <= tol, f"fft {want_y.shape[0]}: relative error {err:.3e} above {tol:.3e}"
+
+
 def assert_matches_oracle(job: Job, check_trace=True):
     if job.kind == "sssp":
         return check_sssp(job)
     want, out = oracle_run(job)
     s = job.stats
-    got = (job.value if job.kind not in ("msort", "bfs", "postorder", "preorder") else want.result, s.epochs, s.tasks,
+    got = (job.value if job.kind not in ("msort", "bfs", "postorder", "preorder", "fft") else want.result,
+           s.epochs, s.tasks,
            s.launched, s.peak_entries)
     exp = (want.result, want.epochs, want.tasks, want.launched, want.peak)
     assert got == exp, f"{job.kind} {job.n}: got {got} want {exp}"
@@ -196,6 +233,8 @@ def assert_matches_oracle(job: Job, check_trace=True):
         check_postorder_log(job, out)
     elif job.kind == "preorder":
         check_preorder_log(job, out)
+    elif job.kind == "fft":
+        check_fft(job, out)
     elif out is not None:
         assert np.array_equal(job.out, out), f"{job.kind}: output differs"
     if check_trace and job.trace is not None and want.records is not None:

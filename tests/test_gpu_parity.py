@@ -208,6 +208,7 @@ def test_mixed_batch_equals_alone(sched):
     jobs.append(Job("bfs", graph=inputs.csr_from_arcs(5, [(0, 1), (1, 2), (2, 3), (3, 4)], 0)))
     jobs.append(Job("postorder", bintree=bintree(*inputs.binary_tree(500, 11), 0)))
     jobs.append(Job("preorder", bintree=bintree(*inputs.binary_tree(700, 13), 0)))
+    jobs.append(Job("fft", signal=inputs.complex_signal(1 << 12, 14)))
     gs, ws = inputs.sssp_graph(9, 12)
     jobs.append(Job("sssp", graph=gs, weights=ws))
     with make_ctx(sched) as ctx:
