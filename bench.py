@@ -15,7 +15,7 @@ Prints one JSON line: tasks/s over the whole step (the metric), epochs/s,
 the roofline of the dominant epoch kernel (algorithmic bytes / HIP-event
 kernel time, against 8 TB/s HBM), and the CPU oracle timed on this host.
 
-    python bench.py [--steps K] [--warmup W] [--config 2|1|3|4|5|6|7] [--sched plain|graph|persistent]
+    python bench.py [--steps K] [--warmup W] [--config 2|1|3|4|5|6|7|8] [--sched plain|graph|persistent]
 """
 from __future__ import annotations
 
@@ -633,6 +633,96 @@ def bench_cfg7(args):
             "setup_s": {"generate": round(gen_s, 1), "oracle_dijkstra": round(orc_s, 1)}}
 
 
+def fft_bytes(m: int) -> int:
+    """Algorithmic payload bytes of one FFT of 2^m complex fp32 points: the
+    leaves read x and write y (8 + 8 B a point), and every combine level reads
+    and writes y once more (16 B a point)."""
+    n = 1 << m
+    return 16 * n * (1 + max(0, m - 6))
+
+
+def bench_cfg8(args):
+    """The FFT program (a widening beyond the five configurations): one
+    transform of 2^20 complex fp32 points under every scheduler, and a batch
+    of 64 transforms of 2^18 points in shared epochs (plain: one after
+    another).  Every output is checked against numpy's fp64 FFT within the
+    fp32 error bound of a radix-2 FFT."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1608_00571_amd as T
+
+    def tol(m):
+        u = 2.0 ** -24
+        eta = 4 * u + (4 * u / (1 - 4 * u)) * (np.sqrt(2) + 4 * u)
+        t = max(1, m) * eta
+        return t / (1 - t)
+
+    def make(m, count, seed):
+        xs, ys, want = [], [], []
+        for g in range(count):
+            x = inputs.complex_signal(1 << m, seed + g)
+            xs.append(torch.from_numpy(x.view(np.float32).copy()).to("cuda"))
+            ys.append(torch.empty_like(xs[-1]))
+            want.append(np.fft.fft(x.astype(np.complex128)) if g < 4 else None)
+        return xs, ys, want
+
+    def run(sched, m, xs, ys, want, wg):
+        arena = (len(xs) * (T.tv_bound(T.FFT, [m]) + 64) + 4096) * T.BYTES_PER_ENTRY
+        ctx = T.Context(arena, sched=sched, wg=wg, max_trees=len(xs))
+        p = ctx.register(T.FFT)
+        best, st = None, None
+        for it in range(args.warmup + args.steps):
+            ids = [ctx.submit(p, [m], [x, y]) for x, y in zip(xs, ys)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = ctx.run()
+            dt = time.perf_counter() - t0
+            st = [ctx.results(t)[1] for t in ids]
+            for y, w in zip(ys, want):
+                if w is not None:
+                    got = y.cpu().numpy().view(np.complex64).astype(np.complex128)
+                    err = np.linalg.norm(got - w) / np.linalg.norm(w)
+                    assert err <= tol(m), f"fft {sched}: relative error {err:.2e}"
+            if it >= args.warmup and (best is None or dt < best[0]):
+                best = (dt, rs)
+        ctx.close()
+        dt, rs = best
+        tasks = sum(s.tasks for s in st)
+        pts = len(xs) << m
+        return {"ms": round(dt * 1e3, 3), "tasks_per_s": tasks / dt, "tasks": tasks,
+                "gflops": 5.0 * pts * m / dt / 1e9, "GBps": len(xs) * fft_bytes(m) / dt / 1e9,
+                "global_epochs": rs.global_epochs}
+
+    one = make(20, 1, 800)
+    single = {s: run(s, 20, *one, 1024 if s == "plain" else args.wg) for s in ("plain", "graph", "persistent")}
+    bm, bn = 18, 64
+    batch_in = make(bm, bn, 900)
+    batch = {s: run(s, bm, *batch_in, args.wg) for s in ("graph", "persistent")}
+    batch["plain_one_at_a_time"] = run("plain", bm, batch_in[0][:16], batch_in[1][:16], batch_in[2][:16], 1024)
+    bbest = max(("graph", "persistent"), key=lambda k: batch[k]["tasks_per_s"])
+    sbest = min(single, key=lambda k: single[k]["ms"])
+    b = batch[bbest]
+    ach = bn * fft_bytes(bm) / (b["ms"] * 1e-3) / 1e9
+    return {
+        "metric": "tasks/s", "value": b["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32)",
+        "data": "synthetic",
+        "config": {"workload": f"{bn} FFTs of 2^{bm} complex fp32 points in shared epochs; "
+                               "one FFT of 2^20 points beside it",
+                   "sched": bbest, "wg": args.wg, "tasks": b["tasks"]},
+        "gflops": b["gflops"],
+        "batch": batch,
+        "batched_vs_plain_factor": round(b["tasks_per_s"] / batch["plain_one_at_a_time"]["tasks_per_s"], 2),
+        "single_2e20": {"best": sbest, **{k: v for k, v in single.items()}},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_run": bn * fft_bytes(bm)},
+    }
+
+
 def serving_workload(nreq, rate, seed=0, pool_scales=range(12, 21)):
     """Requests of the serving mix plus their host payloads (one R-MAT graph
     per scale, shared by the requests that draw that scale)."""
@@ -881,6 +971,8 @@ def main():
         line = bench_cfg6(args)
     elif args.config == 7:
         line = bench_cfg7(args)
+    elif args.config == 8:
+        line = bench_cfg8(args)
     elif args.config == 2:
         line = bench_cfg2(args)
         if not args.no_cpu:

@@ -302,10 +302,10 @@ __device__ __forceinline__ int last_le(const int32_t *pre, int e) {
 // Plain stores: the arc phase reads them after a grid barrier or a kernel
 // boundary.
 template <int WG>
-__device__ int publish_arcs(const DevCtx &C, Lds<WG> &L, VisitLds &V, int tot) {
+__device__ int publish_arcs(const DevCtx &C, Lds<WG> &L, VisitLds &V, int tot, int max_tiles) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
-  const int tile = max(kArcTile, (tot + kArcTilesMax - 1) / kArcTilesMax);
+  const int tile = max(kArcTile, (tot + max_tiles - 1) / max_tiles);
   const int ntiles = (tot + tile - 1) / tile;
   const int nseg = L.nseg;
   if (tid == 0) {
@@ -897,9 +897,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
     constexpr bool kSssp = (OPS & OPS_SSSP) != 0;
     constexpr bool kArcs = (OPS & OPS_GRAPH) != 0;
     constexpr bool kFft = (OPS & OPS_FFT) != 0;
-    bool anyv = false;
+    bool anyv = false, anyc = false;
 #pragma unroll
-    for (int k = 0; k < IT; ++k) anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT || op[k] == OP_COMB);
+    for (int k = 0; k < IT; ++k) {
+      anyv |= (op[k] == OP_VISIT || op[k] == OP_SVISIT || op[k] == OP_COMB);
+      anyc |= (op[k] == OP_COMB);
+    }
     if (__syncthreads_or(anyv)) {
       int32_t deg[IT], row[IT], dvs[IT];
       int dsum = 0;
@@ -937,10 +940,12 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         pre += deg[k];
       }
       if (tid == 0) V.qn = 0;
-      // many units: published as tiles for every work-group (batched forms)
+      // many units: published as tiles for every work-group (batched forms;
+      // butterflies, cheap and uniform, in smaller tiles than arcs)
+      const bool bfly = kFft && __syncthreads_or(anyc);
       __syncthreads();
       if constexpr (MULTI) {
-        if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot);
+        if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot, bfly ? kBflyTilesMax : kArcTilesMax);
       }
       // One arc per lane per step.  A claimed vertex is queued in LDS; the
       // queue is turned into child entries in bulk (one device atomic per

@@ -169,7 +169,8 @@ struct PlainCounters {
 // arcs come from.
 constexpr int kArcJobs = 8192;      // jobs per epoch (beyond: the owner expands locally)
 constexpr int kArcTile = 2048;      // arcs per tile (larger jobs use larger tiles)
-constexpr int kArcTilesMax = 64;    // tiles per job
+constexpr int kArcTilesMax = 64;    // tiles per job of arcs
+constexpr int kBflyTilesMax = 1024; // tiles per job with FFT butterflies (cheap, uniform units)
 constexpr int kArcTilesAll = 1 << 18;   // tiles per epoch
 constexpr int kArcSegPool = 1 << 16;    // segment records per epoch
 constexpr int kArcLocal = 16384;    // chunks with at most this many arcs expand locally
