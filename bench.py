@@ -686,14 +686,17 @@ def bench_cfg8(args):
                     err = np.linalg.norm(got - w) / np.linalg.norm(w)
                     assert err <= tol(m), f"fft {sched}: relative error {err:.2e}"
             if it >= args.warmup and (best is None or dt < best[0]):
-                best = (dt, rs)
+                best = (dt, rs, ctx.epoch_times() if sched != "plain" else None)
         ctx.close()
-        dt, rs = best
+        dt, rs, et = best
         tasks = sum(s.tasks for s in st)
         pts = len(xs) << m
-        return {"ms": round(dt * 1e3, 3), "tasks_per_s": tasks / dt, "tasks": tasks,
-                "gflops": 5.0 * pts * m / dt / 1e9, "GBps": len(xs) * fft_bytes(m) / dt / 1e9,
-                "global_epochs": rs.global_epochs}
+        out = {"ms": round(dt * 1e3, 3), "tasks_per_s": tasks / dt, "tasks": tasks,
+               "gflops": 5.0 * pts * m / dt / 1e9, "GBps": len(xs) * fft_bytes(m) / dt / 1e9,
+               "global_epochs": rs.global_epochs}
+        if et is not None and len(et):
+            out["epoch_us"] = [round(float(x), 1) for x in et]
+        return out
 
     one = make(20, 1, 800)
     single = {s: run(s, 20, *one, 1024 if s == "plain" else args.wg) for s in ("plain", "graph", "persistent")}
@@ -932,7 +935,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--sched", default="plain")
     ap.add_argument("--wg", type=int, default=0,
-                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler, 256 batched)")
+                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler, 256 batched, "
+                         "512 for the FFT configuration)")
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--log2tree", type=int, default=22, help="config 6: postorder tree of 2^k nodes")
     ap.add_argument("--no-cpu", action="store_true")
@@ -952,7 +956,7 @@ def main():
     ap.add_argument("--calib-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.wg == 0:
-        args.wg = 1024 if args.config in (1, 2) and args.sched == "plain" else 256
+        args.wg = 1024 if args.config in (1, 2) and args.sched == "plain" else (512 if args.config == 8 else 256)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)

@@ -675,38 +675,56 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
 
   // ---- FFT leaves (at most 64 points): each is transformed by a whole
   // wavefront, lane j holding point j; the lanes load their inputs in
-  // bit-reversed order and run the radix-2 butterfly stages across lanes
+  // bit-reversed order and run the radix-2 butterfly stages across lanes.
+  // Leaves go G at a time, their gathers in flight together (G = 4 in the
+  // kernel for FFT alone, 2 where other programs' registers are live too).
   if constexpr ((OPS & OPS_FFT) != 0) {
+    constexpr int G = OPS == OPS_FFT ? 4 : 2;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       uint64_t lm = ballot64(fleaf[k]);
       while (lm) {
-        const int src = __ffsll((unsigned long long)lm) - 1;
-        lm &= lm - 1;
-        const int32_t lo = __shfl(a0v[k], src, 64), o = __shfl(a1v[k], src, 64);
-        const int32_t ls = __shfl(a2v[k], src, 64), sl = __shfl(slot[k], src, 64);
-        const int lg = (int)(__shfl((int32_t)tp[k], src, 64) >> 8) - ls;   // log2 of the leaf's points
-        const TreeStatic *T = &C.ts[sl];
-        const float2 *x = (const float2 *)T->ptr0;
-        float2 *y = (float2 *)T->ptr1;
-        const int n = 1 << lg;
-        const int j = lg > 0 ? (int)(__builtin_bitreverse32((uint32_t)lane) >> (32 - lg)) : 0;
-        float2 v = make_float2(0.f, 0.f);
-        if (lane < n) v = x[o + (j << ls)];
-        for (int st = 0; st < lg; ++st) {
-          const int h = 1 << st;
-          const float pr = __shfl(v.x, lane ^ h, 64), pi = __shfl(v.y, lane ^ h, 64);
-          float sn, cs;
-          sincospif((float)(lane & (h - 1)) / (float)h, &sn, &cs);   // w = exp(-i pi k / h)
-          if (lane & h) {          // b: the partner holds a; b' = a - w b
-            const float tr = cs * v.x + sn * v.y, ti = cs * v.y - sn * v.x;
-            v = make_float2(pr - tr, pi - ti);
-          } else {                 // a: the partner holds b; a' = a + w b
-            const float tr = cs * pr + sn * pi, ti = cs * pi - sn * pr;
-            v = make_float2(v.x + tr, v.y + ti);
+        // the next leaves' parameters, read from their lanes into scalar
+        // registers (lg = -1: no such leaf)
+        int32_t lo[G], ls[G], sl[G], lg[G];
+        float2 v[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          lg[g] = -1; lo[g] = ls[g] = sl[g] = 0;
+          v[g] = make_float2(0.f, 0.f);
+          if (lm) {
+            const int src = __ffsll((unsigned long long)lm) - 1;
+            lm &= lm - 1;
+            lo[g] = __builtin_amdgcn_readlane(a0v[k], src);
+            const int32_t o = __builtin_amdgcn_readlane(a1v[k], src);
+            ls[g] = __builtin_amdgcn_readlane(a2v[k], src);
+            sl[g] = __builtin_amdgcn_readlane(slot[k], src);
+            lg[g] = (int)((uint32_t)__builtin_amdgcn_readlane((int32_t)tp[k], src) >> 8) - ls[g];
+            if (lane < (1 << lg[g])) {
+              const int j = lg[g] > 0 ? (int)(__builtin_bitreverse32((uint32_t)lane) >> (32 - lg[g])) : 0;
+              v[g] = ((const float2 *)C.ts[sl[g]].ptr0)[o + (j << ls[g])];
+            }
           }
         }
-        if (lane < n) y[lo + lane] = v;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (lg[g] < 0) continue;   // (uniform across the wavefront)
+          float2 x = v[g];
+          for (int st = 0; st < lg[g]; ++st) {
+            const int h = 1 << st;
+            const float pr = __shfl(x.x, lane ^ h, 64), pi = __shfl(x.y, lane ^ h, 64);
+            float sn, cs;
+            sincospif((float)(lane & (h - 1)) / (float)h, &sn, &cs);   // w = exp(-i pi k / h)
+            if (lane & h) {          // b: the partner holds a; b' = a - w b
+              const float tr = cs * x.x + sn * x.y, ti = cs * x.y - sn * x.x;
+              x = make_float2(pr - tr, pi - ti);
+            } else {                 // a: the partner holds b; a' = a + w b
+              const float tr = cs * pr + sn * pi, ti = cs * pi - sn * pr;
+              x = make_float2(x.x + tr, x.y + ti);
+            }
+          }
+          if (lane < (1 << lg[g])) ((float2 *)C.ts[sl[g]].ptr1)[lo[g] + lane] = x;
+        }
       }
     }
   }
