@@ -78,6 +78,7 @@ def lib():
         L.orc_bfs_queue.argtypes = [i32, vp, vp, i32, vp]
         L.orc_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
         L.orc_dft.argtypes = [i64, vp, vp]
+        L.orc_set_delta.argtypes = [vp, i32]
         L.orc_new.restype = vp
         L.orc_new.argtypes = [i32, i32, i32, vp, vp, vp, vp, i64]
         L.orc_free.argtypes = [vp]
@@ -274,15 +275,18 @@ def bfs(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, source: int, records: 
 
 
 def sssp(V: int, row_ptr: np.ndarray, col_idx: np.ndarray, weights: np.ndarray, source: int,
-         records: bool = False, cap: int = 0) -> tuple[np.ndarray, Run]:
+         records: bool = False, cap: int = 0, delta: int = 0) -> tuple[np.ndarray, Run]:
     """The relaxation program in the epoch emulator: distances (UNREACHED
     for unreachable vertices) and the statistics of this one schedule (task
-    counts depend on the order of relaxations inside an epoch)."""
+    counts depend on the order of relaxations inside an epoch).  delta > 0:
+    a visit whose distance is at least (CEN + 1) * delta waits an epoch."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     w = np.ascontiguousarray(weights, dtype=np.int32)
     d = np.empty(V, dtype=np.int32)
     em = Emulator(SSSP, V, source, ptrs=(rp, ci, w, d), cap=cap, records=records)
+    if delta:
+        lib().orc_set_delta(em.h, delta)
     em.run()
     return d, em.stats()
 

@@ -207,6 +207,7 @@ typedef struct orc_tvm {
     int32_t cen;
     /* program parameters and payloads (caller-owned) */
     int32_t p0, p1;
+    int32_t p2;           /* SSSP: the bucket width delta (0: none) */
     uint32_t *buf[2];
     const int32_t *row_ptr, *col, *wts;
     int32_t *depth;       /* BFS depth / SSSP distance */
@@ -356,17 +357,28 @@ static void body_bfs(orc_tvm *m, int64_t i, int32_t type) {
 static void body_sssp(orc_tvm *m, int64_t i, int32_t type) {
     (void)type;
     int32_t v = m->a0[i];
+    /* With a bucket width delta > 0, a visit whose distance (the one that
+     * forked it, a1) is at least (CEN + 1) * delta is not due yet: it forks
+     * itself into the next epoch unchanged and relaxes nothing. */
+    if (m->p2 > 0 && (int64_t)m->a1[i] >= (int64_t)(m->cen + 1) * m->p2) {
+        if (tv_fork(m, 1, v, m->a1[i], 0, 0) < 0) return;
+        tv_finish(m, i);
+        return;
+    }
     const int64_t d = m->depth[v];
     for (int32_t k = m->row_ptr[v]; k < m->row_ptr[v + 1]; ++k) {
         int32_t u = m->col[k];
         const int64_t nd = d + m->wts[k];
         if (nd < m->depth[u]) {
             m->depth[u] = (int32_t)nd;
-            if (tv_fork(m, 1, u, 0, 0, 0) < 0) return;
+            if (tv_fork(m, 1, u, (int32_t)nd, 0, 0) < 0) return;
         }
     }
     tv_finish(m, i);
 }
+
+/* SSSP's bucket width (before the first epoch; 0 = the plain program). */
+void orc_set_delta(orc_tvm *m, int32_t delta) { m->p2 = delta; }
 
 /* Figure 2: postorder(node) forks right then left and joins visitAfter(node). */
 static void body_postorder(orc_tvm *m, int64_t i, int32_t type) {
@@ -623,7 +635,7 @@ int64_t orc_num_visits(const orc_tvm *m) { return m->nvisit; }
  * 4.4.2); the payload arrays are the caller's and are passed again on
  * restore. */
 typedef struct {
-    int32_t kind, ntt, p0, p1, sp, cen;
+    int32_t kind, ntt, p0, p1, sp, cen, p2, pad;
     int64_t cap, hw, nfc, nvisit;
     orc_stats st;
 } snap_hdr;
@@ -636,7 +648,7 @@ int64_t orc_snapshot_size(const orc_tvm *m) {
 int64_t orc_snapshot(const orc_tvm *m, void *buf) {
     snap_hdr h;
     memset(&h, 0, sizeof h);
-    h.kind = m->kind; h.ntt = m->ntt; h.p0 = m->p0; h.p1 = m->p1; h.sp = m->sp; h.cen = m->cen;
+    h.kind = m->kind; h.ntt = m->ntt; h.p0 = m->p0; h.p1 = m->p1; h.sp = m->sp; h.cen = m->cen; h.p2 = m->p2;
     h.cap = m->cap; h.hw = m->st.peak; h.nfc = m->nfc; h.nvisit = m->nvisit; h.st = m->st;
     char *p = (char *)buf;
     memcpy(p, &h, sizeof h); p += sizeof h;
@@ -656,7 +668,7 @@ orc_tvm *orc_restore(const void *buf, void *ptr0, void *ptr1, void *ptr2, void *
     const char *p = (const char *)buf;
     memcpy(&h, p, sizeof h); p += sizeof h;
     orc_tvm *m = (orc_tvm *)calloc(1, sizeof(orc_tvm));
-    m->kind = h.kind; m->ntt = h.ntt; m->p0 = h.p0; m->p1 = h.p1; m->cen = h.cen;
+    m->kind = h.kind; m->ntt = h.ntt; m->p0 = h.p0; m->p1 = h.p1; m->cen = h.cen; m->p2 = h.p2;
     m->cap = h.cap; m->nfc = h.nfc; m->nvisit = h.nvisit; m->st = h.st;
     grow(m, h.hw > 0 ? h.hw : 1);
     size_t n4 = (size_t)h.hw * 4;

@@ -108,3 +108,31 @@ def test_sssp_source_only():
     g = inputs.csr_from_arcs(3, [], 0)
     d, r = oracle.sssp(g.V, g.row_ptr, g.col_idx, np.zeros(0, np.int32), g.source)
     assert d.tolist() == [0, INF, INF] and r.tasks == 1 and r.epochs == 1
+
+
+@pytest.mark.parametrize("delta", [1, 3, 16, 100])
+@pytest.mark.parametrize("scale,seed,lo,hi", [(8, 5, 1, 100), (10, 6, 0, 9)])
+def test_bucketed_program_reaches_dijkstra(delta, scale, seed, lo, hi):
+    """With a bucket width, a visit waits (re-forks itself unchanged) until
+    (CEN + 1) * delta exceeds its distance: the distances are still
+    Dijkstra's, and a vertex at distance d is relaxed no earlier than epoch
+    floor(d / delta), so the run has at least floor(max d / delta) + 1 epochs."""
+    g, w = inputs.sssp_graph(scale, seed, lo, hi)
+    want = oracle.dijkstra(g.V, g.row_ptr, g.col_idx, w, g.source)
+    d, r = oracle.sssp(g.V, g.row_ptr, g.col_idx, w, g.source, delta=delta)
+    assert np.array_equal(d, want)
+    reached = want[want != INF]
+    assert r.epochs >= int(reached.max()) // delta + 1
+    assert r.tasks >= reached.size
+
+
+def test_bucket_wider_than_every_distance_changes_nothing():
+    """A bucket wider than any distance never delays a visit: the run is the
+    plain program's, epoch for epoch."""
+    g, w = inputs.sssp_graph(9, 7)
+    d0, r0 = oracle.sssp(g.V, g.row_ptr, g.col_idx, w, g.source, records=True)
+    d1, r1 = oracle.sssp(g.V, g.row_ptr, g.col_idx, w, g.source, records=True, delta=1 << 30)
+    assert np.array_equal(d0, d1)
+    assert (r0.tasks, r0.epochs, r0.peak) == (r1.tasks, r1.epochs, r1.peak)
+    assert np.array_equal(r0.records, r1.records)
+
