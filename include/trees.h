@@ -155,15 +155,20 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      (the pointers may be NULL when N = 0).
  *   BFS_CSR:           args = {V, source}; bufs = {row_ptr[V+1], col_idx[E], depth[V] (out)}
  *                      int32 CSR; depth receives hop counts, -1 = unreachable.
- *   SSSP_CSR:          args = {V, source[, max_entries]}; bufs = {row_ptr[V+1], col_idx[E],
+ *   SSSP_CSR:          args = {V, source[, max_entries[, delta]]}; bufs = {row_ptr[V+1], col_idx[E],
  *                      weights[E], dist[V] (out)} int32, weights >= 0 and every distance
  *                      below 2^31 - 1.  visit(v) lowers the distance of each out-neighbour
  *                      it improves (atomic min) and forks a visit of it; dist receives the
  *                      shortest distances, 2^31 - 1 = unreachable.  A vertex is visited once
  *                      per improvement, so the task count depends on the schedule: the arena
  *                      holds max_entries entries (default 8 V) and a run that needs more
- *                      ends the tree with OVERFLOW.  A visit forked by a distance that has
- *                      since dropped returns at once (a later visit relaxes the arcs).
+ *                      ends the tree with OVERFLOW (max_entries 0: the default).  A visit
+ *                      forked by a distance that has since dropped returns at once (a later
+ *                      visit relaxes the arcs).  delta > 0 (< 2^24) sets a bucket width: a
+ *                      visit forked with distance d runs only in an epoch whose CEN satisfies
+ *                      d < (CEN + 1) * delta, and until then forks itself unchanged (fewer
+ *                      repeated relaxations for more, cheap, waiting tasks; the arena must
+ *                      then hold the waiting copies too).
  *   POSTORDER:         args = {n, root}, 1 <= n < 2^24, -1 <= root < n (-1: the empty tree);
  *                      bufs = {left[n], right[n], log[n+1] (out)} int32; left/right hold each
  *                      node's children, -1 = none.  postorder(node) forks postorder(right),

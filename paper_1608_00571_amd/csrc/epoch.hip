@@ -296,6 +296,36 @@ __device__ __forceinline__ int last_le(const int32_t *pre, int e) {
   return lo;
 }
 
+// Turns the claim queue (V.qn vertices with their segment and, for SSSP,
+// the distance that forked them) into entries of the next epoch: offsets from
+// the LDS segment counters, one device atomic per segment (seg_commit), then
+// code, a0 and, for an SSSP entry, a1.  Every thread of the work-group calls
+// it after a barrier that follows the last push; it empties the queue.
+template <int WG, bool MULTI, bool SSSP, int NS>
+__device__ void flush_claims(const DevCtx &C, Lds<WG, NS> &L, VisitLds &V, const PlainArgs &P) {
+  const int tid = threadIdx.x;
+  const int qn = V.qn;
+  for (int q0 = 0; q0 < qn; q0 += WG) {
+    const int q = q0 + tid;
+    const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
+    if (q < qn) V.qo[q] = (int16_t)o;
+  }
+  seg_commit<WG, MULTI>(C, L, P, false);
+  for (int q = tid; q < qn; q += WG) {
+    const int ss = V.qs[q];
+    const int32_t vb = L.seg_base[ss];
+    if (vb >= 0) {
+      const int64_t c = ((int64_t)L.seg_tb[ss] << 6) + vb + V.qo[q];
+      C.code[c] = (L.seg_cen[ss] + 1) * C.ntt + (int32_t)(L.seg_tp[ss] & 0xFF);
+      C.a0[c] = V.qu[q];
+      if (SSSP && V.qd[q] >= 0) C.a1[c] = V.qd[q];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) V.qn = 0;
+  __syncthreads();
+}
+
 // Publishes the chunk's VISIT arcs (V: lane-major degree prefix, first arcs,
 // segments; tot arcs in all) as a job of tiles.  Returns the job number, or
 // -1 when the epoch's job table is full (the chunk then expands locally).
@@ -923,21 +953,32 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
     }
     if (__syncthreads_or(anyv)) {
       int32_t deg[IT], row[IT], dvs[IT];
+      int32_t offer[IT];   // SSSP: the distance that forked the visit (its a1)
+      bool wait[IT];       // SSSP with buckets: the visit is not due this epoch
+      bool anyw = false;
       int dsum = 0;
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
-        deg[k] = 0; row[k] = 0; dvs[k] = -1;
-        if (op[k] == OP_VISIT || op[k] == OP_SVISIT) {
+        deg[k] = 0; row[k] = 0; dvs[k] = -1; offer[k] = 0; wait[k] = false;
+        if (kSssp && op[k] == OP_SVISIT) {
+          // with a bucket width delta (> 0), a visit whose distance is at
+          // least (CEN + 1) * delta waits: it forks itself unchanged
+          offer[k] = C.a1[idx[k]];
+          const int32_t delta = (int32_t)(tp[k] >> 8);
+          wait[k] = delta > 0 && (int64_t)offer[k] >= (int64_t)(cen[k] + 1) * delta;
+          anyw |= wait[k];
+        }
+        if ((op[k] == OP_VISIT || op[k] == OP_SVISIT) && !wait[k]) {
           const TreeStatic *ST = &C.ts[slot[k]];
           const int32_t *rp = (const int32_t *)ST->ptr0;
           row[k] = rp[a0v[k]];
           deg[k] = rp[a0v[k] + 1] - row[k];
-          // SSSP: the vertex's distance as it stands now.  The entry's a1 is
-          // the distance that forked it; a lower one since then forked
-          // another visit, which relaxes the arcs instead (this one is stale)
+          // SSSP: the vertex's distance as it stands now.  If a lower one
+          // than the entry's has been set since, it forked another visit,
+          // which relaxes the arcs instead (this one is stale)
           if (kSssp && op[k] == OP_SVISIT) {
             dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
-            if (dvs[k] < C.a1[idx[k]]) deg[k] = 0;
+            if (dvs[k] < offer[k]) deg[k] = 0;
           }
         } else if (kFft && op[k] == OP_COMB) {
           // COMB(lo, ls): n/2 butterflies over outputs [lo, lo + n)
@@ -962,6 +1003,20 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       // butterflies, cheap and uniform, in smaller tiles than arcs)
       const bool bfly = kFft && __syncthreads_or(anyc);
       __syncthreads();
+      if constexpr (kSssp) {   // waiting visits: their copies in the next epoch
+        if (__syncthreads_or(anyw)) {
+#pragma unroll
+          for (int k = 0; k < IT; ++k) {
+            if (!wait[k]) continue;
+            const int q = atomicAdd(&V.qn, 1);
+            V.qu[q] = a0v[k];
+            V.qs[q] = (int16_t)seg[k];
+            V.qd[q] = offer[k];
+          }
+          __syncthreads();
+          flush_claims<WG, MULTI, true>(C, L, V, P);
+        }
+      }
       if constexpr (MULTI) {
         if (tot > kArcLocal) arc_job = publish_arcs<WG>(C, L, V, tot, bfly ? kBflyTilesMax : kArcTilesMax);
       }
@@ -1034,28 +1089,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         }
         if constexpr (kArcs) {
           __syncthreads();
-          const int qn = V.qn;
-          if (qn > kClaimQ - WG * A || e0 + WG * A >= tot) {
-            for (int q0 = 0; q0 < qn; q0 += WG) {
-              const int q = q0 + tid;
-              const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
-              if (q < qn) V.qo[q] = (int16_t)o;
-            }
-            seg_commit<WG, MULTI>(C, L, P, false);
-            for (int q = tid; q < qn; q += WG) {
-              const int sseg = V.qs[q];
-              const int32_t vb = L.seg_base[sseg];
-              if (vb >= 0) {
-                const int64_t c = ((int64_t)L.seg_tb[sseg] << 6) + vb + V.qo[q];
-                C.code[c] = (L.seg_cen[sseg] + 1) * ntt + (int32_t)(L.seg_tp[sseg] & 0xFF);
-                C.a0[c] = V.qu[q];
-                if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
-              }
-            }
-            __syncthreads();
-            if (tid == 0) V.qn = 0;
-            __syncthreads();
-          }
+          if (V.qn > kClaimQ - WG * A || e0 + WG * A >= tot) flush_claims<WG, MULTI, kSssp>(C, L, V, P);
         }
       }
     }
@@ -1400,28 +1434,7 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
       }
       if constexpr (kArcs) {
         __syncthreads();
-        const int qn = V.qn;
-        if (qn > kClaimQ - WG * A || e0 + WG * A >= e_hi) {
-          for (int q0 = 0; q0 < qn; q0 += WG) {
-            const int q = q0 + tid;
-            const int o = lds_reserve(L.seg_cnt, q < qn ? V.qs[q] : -1, q < qn ? 1 : 0);
-            if (q < qn) V.qo[q] = (int16_t)o;
-          }
-          seg_commit<WG, true>(C, L, P, false);
-          for (int q = tid; q < qn; q += WG) {
-            const int ss = V.qs[q];
-            const int32_t vb = L.seg_base[ss];
-            if (vb >= 0) {
-              const int64_t c = ((int64_t)L.seg_tb[ss] << 6) + vb + V.qo[q];
-              C.code[c] = (L.seg_cen[ss] + 1) * ntt + (int32_t)(L.seg_tp[ss] & 0xFF);
-              C.a0[c] = V.qu[q];
-              if (kSssp && V.qd[q] >= 0) C.a1[c] = V.qd[q];
-            }
-          }
-          __syncthreads();
-          if (tid == 0) V.qn = 0;
-          __syncthreads();
-        }
+        if (V.qn > kClaimQ - WG * A || e0 + WG * A >= e_hi) flush_claims<WG, true, kSssp>(C, L, V, P);
       }
     }
     // the tile's forks are performed before the tile counts as done

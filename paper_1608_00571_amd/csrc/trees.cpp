@@ -152,8 +152,10 @@ trees_status tv_bound(int kind, const int64_t *args, int nargs, int64_t *out, st
       // (default 8 V) and a run that needs more fails with OVERFLOW
       if (nargs < 2 || args[0] < 1 || args[0] >= (1ll << 31) || args[1] < 0 || args[1] >= args[0])
         return bad("sssp: need V >= 1 and 0 <= source < V");
-      if (nargs >= 3 && (args[2] < 1 || args[2] >= (1ll << 31))) return bad("sssp: need 1 <= max_entries < 2^31");
-      *out = nargs >= 3 ? args[2] : std::min<int64_t>(8 * args[0], (1ll << 31) - 1);
+      if (nargs >= 3 && (args[2] < 0 || args[2] >= (1ll << 31)))
+        return bad("sssp: need 0 <= max_entries < 2^31 (0: the default)");
+      if (nargs >= 4 && (args[3] < 0 || args[3] >= (1ll << 24))) return bad("sssp: need 0 <= delta < 2^24");
+      *out = (nargs >= 3 && args[2] > 0) ? args[2] : std::min<int64_t>(8 * args[0], (1ll << 31) - 1);
       return TREES_OK;
     case TREES_PROG_FFT: {
       // the binary tree of FFT tasks down to 64-point leaves: its nodes
@@ -931,7 +933,10 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
   // (its visit counter sits at log[n])
   const bool with_n = P.kind == TREES_PROG_NQUEENS || P.kind == TREES_PROG_POSTORDER ||
                       P.kind == TREES_PROG_PREORDER || P.kind == TREES_PROG_FFT;
-  t.tp = (uint32_t)P.tbase | ((with_n ? (uint32_t)args[0] : 0u) << 8);
+  // (SSSP: its bucket width)
+  const uint32_t param = with_n ? (uint32_t)args[0]
+                         : (P.kind == TREES_PROG_SSSP_CSR && nargs >= 4) ? (uint32_t)args[3] : 0u;
+  t.tp = (uint32_t)P.tbase | (param << 8);
   a.ts.tp = t.tp;
   c->staged.push_back(a);
   if (P.kind == TREES_PROG_BFS_CSR)

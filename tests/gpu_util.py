@@ -34,13 +34,14 @@ class Job:
     """One tree: its spec, payload tensors and, after collect(), its outputs."""
 
     def __init__(self, kind: str, n=None, keys=None, graph=None, bintree=None, weights=None, cap=None,
-                 signal=None):
+                 signal=None, delta=0):
         # bintree (postorder): (left, right, root) int32 child arrays, -1 = none
         # weights (sssp): int32 arc weights in the graph's CSR order; cap: the
         # tree's task-vector entries (default 8 V)
         self.kind, self.n, self.keys, self.graph, self.bintree = kind, n, keys, graph, bintree
         self.weights, self.cap = weights, cap
         self.signal = signal   # fft: complex64 input, a power-of-two length
+        self.delta = delta     # sssp: bucket width (0: the plain program)
         self.tree = None
         self.value = None
         self.stats = None
@@ -75,7 +76,7 @@ class Job:
                 w = torch.zeros(1, dtype=torch.int32, device="cuda")
             d = torch.empty(g.V, dtype=torch.int32, device="cuda")
             self.bufs = (rp, ci, w, d)
-            args = [g.V, g.source] + ([self.cap] if self.cap else [])
+            args = [g.V, g.source] + ([self.cap or 0, self.delta] if (self.cap or self.delta) else [])
             self.tree = ctx.submit(prog, args, [rp, ci, w, d])
         elif self.kind == "fft":
             x = np.ascontiguousarray(self.signal, dtype=np.complex64)
@@ -177,6 +178,8 @@ def check_sssp(job: Job):
     reached = int(np.count_nonzero(want != oracle.UNREACHED))
     assert s.tasks >= reached, f"sssp: {s.tasks} visits for {reached} reached vertices"
     assert s.epochs >= int(hops.max()) + 1
+    if job.delta:   # a vertex at distance d is relaxed no earlier than epoch d // delta
+        assert s.epochs >= int(want[want != oracle.UNREACHED].max()) // job.delta + 1
     assert s.launched >= s.tasks
     if job.trace is not None and len(job.trace) == s.epochs and s.epochs <= 256:
         t = job.trace

@@ -108,6 +108,19 @@ def test_sssp(sched, lo, hi):
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("delta", [1, 16, 1 << 20])
+def test_sssp_buckets(sched, delta):
+    """With a bucket width, visits that are not due wait (fork themselves
+    unchanged): the distances are still Dijkstra's, every epoch is at its
+    depth, and the run spans at least max distance // delta + 1 epochs."""
+    for j in sssp_jobs(1, 100, seed=950):
+        j.delta = delta
+        j.cap = 256 * j.graph.V + 4096
+        run_alone(sched, [j])
+        assert_matches_oracle(j)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
 def test_sssp_batch(sched):
     """16 weighted R-MAT graphs of scale 10..16 in one run."""
     jobs = []
