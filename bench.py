@@ -35,16 +35,16 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "42b2fdef583cc796", "fetch_bytes": 68794706, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "a171cc24fe32b582", "fetch_bytes": 2827079, "write_bytes": 3504283},
-    "k_plain<MS>": {"src": "a171cc24fe32b582", "fetch_bytes": 2244779, "write_bytes": 2354541},
+    "k_map_merge<1024,8192>": {"src": "9a0406df40452cb9", "fetch_bytes": 68792745, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "ae79d2e20f885b57", "fetch_bytes": 2827597, "write_bytes": 3504869},
+    "k_plain<MS>": {"src": "ae79d2e20f885b57", "fetch_bytes": 2252802, "write_bytes": 2354663},
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "a171cc24fe32b582", "wg": 512, "fetch_bytes": 10427244672,
-                         "write_bytes": 12478742432},
+    "k_epochs<FIB|NQ>": {"src": "ae79d2e20f885b57", "wg": 512, "fetch_bytes": 10429836920,
+                         "write_bytes": 12476154592},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "a171cc24fe32b582", "wg": 256, "fetch_bytes": 179780440576 + 143272260224,
-                             "write_bytes": 3369959360 + 4423267424},
+    "k_epochs<GRAPH> sssp": {"src": "ae79d2e20f885b57", "wg": 256, "fetch_bytes": 180098608190 + 141806226358,
+                             "write_bytes": 3384812096 + 4364299264},
 }
 
 
