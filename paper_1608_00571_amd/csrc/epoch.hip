@@ -736,25 +736,32 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
             }
           }
         }
+        // stage by stage across the group, so that the leaves' cross-lane
+        // exchanges overlap; a stage's twiddle is the same for every leaf
+        int lgmax = lg[0];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          if (lg[g] < 0) continue;   // (uniform across the wavefront)
-          float2 x = v[g];
-          for (int st = 0; st < lg[g]; ++st) {
-            const int h = 1 << st;
-            const float pr = __shfl(x.x, lane ^ h, 64), pi = __shfl(x.y, lane ^ h, 64);
-            float sn, cs;
-            sincospif((float)(lane & (h - 1)) / (float)h, &sn, &cs);   // w = exp(-i pi k / h)
-            if (lane & h) {          // b: the partner holds a; b' = a - w b
-              const float tr = cs * x.x + sn * x.y, ti = cs * x.y - sn * x.x;
-              x = make_float2(pr - tr, pi - ti);
-            } else {                 // a: the partner holds b; a' = a + w b
+        for (int g = 1; g < G; ++g) lgmax = max(lgmax, lg[g]);
+        for (int st = 0; st < lgmax; ++st) {
+          const int h = 1 << st;
+          float sn, cs;
+          sincospif((float)(lane & (h - 1)) / (float)h, &sn, &cs);   // w = exp(-i pi k / h)
+          const bool hi = (lane & h) != 0;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            if (st >= lg[g]) continue;   // (uniform across the wavefront)
+            const float pr = __shfl(v[g].x, lane ^ h, 64), pi = __shfl(v[g].y, lane ^ h, 64);
+            if (hi) {          // b: the partner holds a; b' = a - w b
+              const float tr = cs * v[g].x + sn * v[g].y, ti = cs * v[g].y - sn * v[g].x;
+              v[g] = make_float2(pr - tr, pi - ti);
+            } else {           // a: the partner holds b; a' = a + w b
               const float tr = cs * pr + sn * pi, ti = cs * pi - sn * pr;
-              x = make_float2(x.x + tr, x.y + ti);
+              v[g] = make_float2(v[g].x + tr, v[g].y + ti);
             }
           }
-          if (lane < (1 << lg[g])) ((float2 *)C.ts[sl[g]].ptr1)[lo[g] + lane] = x;
         }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (lg[g] >= 0 && lane < (1 << lg[g])) ((float2 *)C.ts[sl[g]].ptr1)[lo[g] + lane] = v[g];
       }
     }
   }
