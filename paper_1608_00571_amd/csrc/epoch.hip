@@ -709,7 +709,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   // Leaves go G at a time, their gathers in flight together (G = 4 in the
   // kernel for FFT alone, 2 where other programs' registers are live too).
   if constexpr ((OPS & OPS_FFT) != 0) {
-    constexpr int G = OPS == OPS_FFT ? 4 : 2;
+    constexpr int G = OPS == OPS_FFT ? 8 : 2;
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
       uint64_t lm = ballot64(fleaf[k]);
