@@ -788,7 +788,7 @@ def bench_cfg5(args):
     n = args.requests
     reqs, pool, jobs = serving_workload(n + args.serve_warmup, 1.0)
     arena = args.serve_arena_gib << 30
-    srv = Server(arena, sched=args.sched if args.sched != "plain" else "graph", burst=args.burst)
+    srv = Server(arena, sched=args.sched if args.sched != "plain" else "graph", burst=args.burst, wg=args.wg)
     # warm-up, then the closed batch: saturation throughput
     srv.serve(jobs[: args.serve_warmup], realtime=False)
     sat = srv.serve(jobs[args.serve_warmup:], realtime=False)
@@ -946,8 +946,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--sched", default="plain")
     ap.add_argument("--wg", type=int, default=0,
-                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler, 256 batched, "
-                         "1024 for the FFT configuration)")
+                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler and the FFT "
+                         "configuration, 512 for BFS, SSSP and serving, 256 otherwise)")
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--log2tree", type=int, default=22, help="config 6: postorder tree of 2^k nodes")
     ap.add_argument("--sssp-deltas", type=lambda t: [int(x) for x in t.split(",") if x], default=[],
@@ -969,7 +969,8 @@ def main():
     ap.add_argument("--calib-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.wg == 0:
-        args.wg = 1024 if args.config in (1, 2) and args.sched == "plain" else (1024 if args.config == 8 else 256)
+        args.wg = (1024 if args.config in (1, 2, 8) and (args.sched == "plain" or args.config == 8)
+                   else 512 if args.config in (4, 5, 7) else 256)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)

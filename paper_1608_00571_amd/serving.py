@@ -75,7 +75,7 @@ class Server:
     """Serves jobs through one context.  `burst` epochs run per device call."""
 
     def __init__(self, arena_bytes: int, *, sched: str = "graph", burst: int = 8, skip_ahead: int = 8,
-                 payload_budget: int = 16 << 30, wg: int = 256, max_trees: int = 4096):
+                 payload_budget: int = 16 << 30, wg: int = 512, max_trees: int = 4096):
         import torch
         self.torch = torch
         self.ctx = Context(arena_bytes, sched=sched, wg=wg, graph_chunk=burst, max_trees=max_trees)
