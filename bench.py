@@ -947,7 +947,7 @@ def main():
     ap.add_argument("--sched", default="plain")
     ap.add_argument("--wg", type=int, default=0,
                     help="epoch-kernel work-group size (default: 1024 for the plain scheduler and the FFT "
-                         "configuration, 512 for BFS, SSSP and serving, 256 otherwise)")
+                         "configuration, 512 for BFS, SSSP, serving and the traversals, 256 otherwise)")
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--log2tree", type=int, default=22, help="config 6: postorder tree of 2^k nodes")
     ap.add_argument("--sssp-deltas", type=lambda t: [int(x) for x in t.split(",") if x], default=[],
@@ -970,7 +970,7 @@ def main():
     args = ap.parse_args()
     if args.wg == 0:
         args.wg = (1024 if args.config in (1, 2, 8) and (args.sched == "plain" or args.config == 8)
-                   else 512 if args.config in (4, 5, 7) else 256)
+                   else 512 if args.config in (4, 5, 6, 7) else 256)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)

@@ -1734,10 +1734,11 @@ __global__ void k_release(DevCtx C, int32_t slot) {
   M(WG, OPS_MS)                   \
   M(WG, OPS_GRAPH)                \
   M(WG, OPS_FFT)                  \
+  M(WG, OPS_PO)                   \
   M(WG, OPS_ALL)
 
 static uint32_t pick_ops(uint32_t need) {
-  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_GRAPH, OPS_FFT, OPS_ALL};
+  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_GRAPH, OPS_FFT, OPS_PO, OPS_ALL};
   for (uint32_t s : sets)
     if ((need & ~s) == 0) return s;
   return OPS_ALL;
