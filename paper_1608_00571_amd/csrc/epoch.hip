@@ -959,33 +959,37 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       anyc |= (op[k] == OP_COMB);
     }
     if (__syncthreads_or(anyv)) {
+      // deg: units of the item; -1: an SSSP visit that waits (dvs then holds
+      // the distance that forked it)
       int32_t deg[IT], row[IT], dvs[IT];
-      int32_t offer[IT];   // SSSP: the distance that forked the visit (its a1)
-      bool wait[IT];       // SSSP with buckets: the visit is not due this epoch
       bool anyw = false;
       int dsum = 0;
 #pragma unroll
       for (int k = 0; k < IT; ++k) {
-        deg[k] = 0; row[k] = 0; dvs[k] = -1; offer[k] = 0; wait[k] = false;
-        if (kSssp && op[k] == OP_SVISIT) {
-          // with a bucket width delta (> 0), a visit whose distance is at
-          // least (CEN + 1) * delta waits: it forks itself unchanged
-          offer[k] = C.a1[idx[k]];
-          const int32_t delta = (int32_t)(tp[k] >> 8);
-          wait[k] = delta > 0 && (int64_t)offer[k] >= (int64_t)(cen[k] + 1) * delta;
-          anyw |= wait[k];
-        }
-        if ((op[k] == OP_VISIT || op[k] == OP_SVISIT) && !wait[k]) {
-          const TreeStatic *ST = &C.ts[slot[k]];
-          const int32_t *rp = (const int32_t *)ST->ptr0;
-          row[k] = rp[a0v[k]];
-          deg[k] = rp[a0v[k] + 1] - row[k];
-          // SSSP: the vertex's distance as it stands now.  If a lower one
-          // than the entry's has been set since, it forked another visit,
-          // which relaxes the arcs instead (this one is stale)
+        deg[k] = 0; row[k] = 0; dvs[k] = -1;
+        if (op[k] == OP_VISIT || op[k] == OP_SVISIT) {
+          int32_t off = 0;     // SSSP: the distance that forked the visit (its a1)
+          bool waits = false;  // with a bucket width delta (> 0), a visit whose distance
+                               // is at least (CEN + 1) * delta waits: it forks itself unchanged
           if (kSssp && op[k] == OP_SVISIT) {
-            dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
-            if (dvs[k] < offer[k]) deg[k] = 0;
+            off = C.a1[idx[k]];
+            const int32_t delta = (int32_t)(tp[k] >> 8);
+            waits = delta > 0 && (int64_t)off >= (int64_t)(cen[k] + 1) * delta;
+          }
+          if (waits) {
+            deg[k] = -1; dvs[k] = off; anyw = true;
+          } else {
+            const TreeStatic *ST = &C.ts[slot[k]];
+            const int32_t *rp = (const int32_t *)ST->ptr0;
+            row[k] = rp[a0v[k]];
+            deg[k] = rp[a0v[k] + 1] - row[k];
+            // SSSP: the vertex's distance as it stands now.  If a lower one
+            // than the entry's has been set since, it forked another visit,
+            // which relaxes the arcs instead (this one is stale)
+            if (kSssp && op[k] == OP_SVISIT) {
+              dvs[k] = ld_agent((const int32_t *)ST->ptr2 + a0v[k]);
+              if (dvs[k] < off) deg[k] = 0;
+            }
           }
         } else if (kFft && op[k] == OP_COMB) {
           // COMB(lo, ls): n/2 butterflies over outputs [lo, lo + n)
@@ -993,7 +997,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
           deg[k] = 1 << ((int)(tp[k] >> 8) - a2v[k] - 1);
           dvs[k] = -(a2v[k] + 2);
         }
-        dsum += deg[k];
+        dsum += max(deg[k], 0);
       }
       int tot;
       int pre = wg_excl_scan<WG>(dsum, L.scan_tmp, &tot);
@@ -1003,25 +1007,29 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         V.pre[tid * IT + k] = pre;
         V.seg[tid * IT + k] = seg[k];
         if (kSssp || kFft) V.dv[tid * IT + k] = dvs[k];
-        pre += deg[k];
+        pre += max(deg[k], 0);
       }
       if (tid == 0) V.qn = 0;
       // many units: published as tiles for every work-group (batched forms;
       // butterflies, cheap and uniform, in smaller tiles than arcs)
       const bool bfly = kFft && __syncthreads_or(anyc);
       __syncthreads();
-      if constexpr (kSssp) {   // waiting visits: their copies in the next epoch
-        if (__syncthreads_or(anyw)) {
+      // waiting visits: queued as their own copies for the next epoch (at
+      // most kChunk, so the queue keeps room for one step's claims); the
+      // expansion below flushes them with its first step
+      bool waits = false;
+      if constexpr (kSssp) {
+        waits = __syncthreads_or(anyw);
+        if (waits) {
 #pragma unroll
           for (int k = 0; k < IT; ++k) {
-            if (!wait[k]) continue;
+            if (deg[k] >= 0) continue;
             const int q = atomicAdd(&V.qn, 1);
             V.qu[q] = a0v[k];
             V.qs[q] = (int16_t)seg[k];
-            V.qd[q] = offer[k];
+            V.qd[q] = dvs[k];
           }
           __syncthreads();
-          flush_claims<WG, MULTI, true>(C, L, V, P);
         }
       }
       if constexpr (MULTI) {
@@ -1033,7 +1041,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       constexpr int A = arcs_per_lane<WG>();
       static_assert(WG * A <= kClaimQ / 2, "claim queue too small for one step");
       int from = 0;   // arcs are visited in increasing order: item searches only move forward
-      for (int e0 = 0; e0 < (arc_job >= 0 ? 0 : tot); e0 += WG * A) {
+      static_assert(kChunk <= kClaimQ - WG * A, "claim queue too small for a chunk's waits and a step");
+      const int lim = arc_job >= 0 ? 0 : tot;   // units this work-group expands itself
+      for (int e0 = 0; e0 < lim || (waits && e0 == 0); e0 += WG * A) {
         int32_t u[A], sseg[A];   // arc: head vertex; butterfly: k
         int32_t *dep[A];
         int32_t dv[A];   // arc: the head's depth or distance as probed; butterfly: log2 of n/2
@@ -1047,7 +1057,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
           sseg[a] = -1;
           nd[a] = -1;
           bf[a] = false;
-          if (e < tot) {
+          if (e < lim) {
             int lo = from, hi = kChunk;   // last item with pre <= e
             while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (V.pre[mid] <= e) lo = mid; else hi = mid; }
             from = lo;
@@ -1096,7 +1106,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         }
         if constexpr (kArcs) {
           __syncthreads();
-          if (V.qn > kClaimQ - WG * A || e0 + WG * A >= tot) flush_claims<WG, MULTI, kSssp>(C, L, V, P);
+          if (V.qn > kClaimQ - WG * A || e0 + WG * A >= lim) flush_claims<WG, MULTI, kSssp>(C, L, V, P);
         }
       }
     }
