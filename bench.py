@@ -35,16 +35,16 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "9a0406df40452cb9", "fetch_bytes": 68792745, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "ae79d2e20f885b57", "fetch_bytes": 2827597, "write_bytes": 3504869},
-    "k_plain<MS>": {"src": "ae79d2e20f885b57", "fetch_bytes": 2252802, "write_bytes": 2354663},
+    "k_map_merge<1024,8192>": {"src": "9a0406df40452cb9", "fetch_bytes": 68792944, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "927fbc08d238babe", "fetch_bytes": 2830364, "write_bytes": 3504699},
+    "k_plain<MS>": {"src": "927fbc08d238babe", "fetch_bytes": 2243771, "write_bytes": 2354629},
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "ae79d2e20f885b57", "wg": 512, "fetch_bytes": 10429836920,
-                         "write_bytes": 12476154592},
+    "k_epochs<FIB|NQ>": {"src": "927fbc08d238babe", "wg": 512, "fetch_bytes": 10429911261,
+                         "write_bytes": 12475180544},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "ae79d2e20f885b57", "wg": 256, "fetch_bytes": 180098608190 + 141806226358,
-                             "write_bytes": 3384812096 + 4364299264},
+    "k_epochs<GRAPH> sssp": {"src": "927fbc08d238babe", "wg": 512, "fetch_bytes": 180322258355 + 142755389740,
+                             "write_bytes": 3391097728 + 4361410976},
 }
 
 
@@ -640,7 +640,7 @@ def bench_cfg7(args):
                          "sector_amplified": {"achieved": round(amp, 1), "frac": round(amp / HBM_PEAK_GBS, 4)},
                          "traffic_GBps": round(traffic / (b["ms"] * 1e-3) / 1e9, 1) if traffic else None,
                          "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE of k_epochs and k_arcs per "
-                                         "graph-form run, work-groups of 256 (profiles/sssp_64rmat_weighted.md)"},
+                                         "graph-form run, work-groups of 512 (profiles/sssp_64rmat_weighted.md)"},
             "setup_s": {"generate": round(gen_s, 1), "oracle_dijkstra": round(orc_s, 1)}}
 
 
