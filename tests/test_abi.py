@@ -51,6 +51,38 @@ def test_tv_bound_on_host():
         T.tv_bound(T.NQUEENS, [15])
 
 
+def test_tv_bound_of_the_widened_programs():
+    """Arena sizes of BFS, SSSP, the traversals and the FFT against the
+    emulator's peaks (traversals, FFT) or their stated rules (BFS: V; SSSP:
+    8 V unless the caller sets it), and their argument checks."""
+    import numpy as np
+
+    import inputs
+    import oracle
+    import paper_1608_00571_amd as T
+    if not os.path.exists(T.LIB_PATH):
+        pytest.skip("libtrees.so not built")
+    for n, seed in [(1, 0), (6, 1), (300, 2), (5000, 3)]:
+        left, right = inputs.binary_tree(n, seed)
+        _, _, rp = oracle.postorder(left, right, 0, records=False)
+        _, _, rq = oracle.preorder(left, right, 0, records=False)
+        assert T.tv_bound(T.POSTORDER, [n, 0]) >= rp.peak
+        assert T.tv_bound(T.PREORDER, [n, 0]) == rq.peak == 2 * n + 1
+    for m in (0, 3, 6, 7, 12, 20):
+        if m <= 12:
+            _, r = oracle.fft(np.zeros(1 << m, dtype=np.complex128))
+            assert T.tv_bound(T.FFT, [m]) == r.peak
+        assert T.tv_bound(T.FFT, [m]) == 2 * max(1, (1 << m) // 64) - 1
+    assert T.tv_bound(T.BFS_CSR, [1000, 3]) == 1000
+    assert T.tv_bound(T.SSSP_CSR, [1000, 3]) == 8000
+    assert T.tv_bound(T.SSSP_CSR, [1000, 3, 123]) == 123
+    assert T.tv_bound(T.SSSP_CSR, [1000, 3, 0, 16]) == 8000      # 0: the default, with a bucket width
+    for kind, args in [(T.FFT, [21]), (T.FFT, [-1]), (T.PREORDER, [5, 5]), (T.PREORDER, [0, -1]),
+                       (T.SSSP_CSR, [10, 10]), (T.SSSP_CSR, [10, 0, -1]), (T.SSSP_CSR, [10, 0, 0, 1 << 24])]:
+        with pytest.raises(T.TreesError):
+            T.tv_bound(kind, args)
+
+
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     import paper_1608_00571_amd as T
     monkeypatch.setattr(T, "LIB_PATH", str(tmp_path / "missing.so"))
