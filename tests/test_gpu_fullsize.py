@@ -63,3 +63,46 @@ def test_tree_batch_full_size(sched):
         assert (value, st.tasks, st.epochs, st.peak_entries, st.launched) == want, (k, n)
     assert rs.global_epochs == max(expected(k, n)[2] for k, n in mix)
     assert np.isfinite(rs.seconds)
+
+
+def test_graph_batches_full_size():
+    """The 64 R-MAT graphs of the BFS and SSSP configurations (scale 16..22,
+    E = 16 V; SSSP weights 1..100), in shared epochs under the graph form at
+    512 lanes: every depth equals the queue BFS's, every distance Dijkstra's,
+    and each BFS tree visits each reached vertex once in max depth + 1 epochs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    import oracle
+    import paper_1608_00571_amd as T
+    scales = inputs.bfs_batch_scales(64)
+    gs = [inputs.sssp_batch_graph(g, sc) for g, sc in enumerate(scales)]
+    with ThreadPoolExecutor(8) as ex:
+        want_d = list(ex.map(lambda gw: oracle.bfs_queue(gw[0].V, gw[0].row_ptr, gw[0].col_idx, gw[0].source), gs))
+        want_s = list(ex.map(lambda gw: oracle.dijkstra(gw[0].V, gw[0].row_ptr, gw[0].col_idx, gw[1],
+                                                        gw[0].source), gs))
+    V = sum(G.V for G, _ in gs)
+    dev = [(torch.from_numpy(G.row_ptr).cuda(), torch.from_numpy(G.col_idx).cuda(), torch.from_numpy(w).cuda())
+           for G, w in gs]
+    for kind in (T.BFS_CSR, T.SSSP_CSR):
+        cap = sum(T.tv_bound(kind, [G.V, G.source]) + 64 for G, _ in gs)
+        outs = [torch.empty(G.V, dtype=torch.int32, device="cuda") for G, _ in gs]
+        with make_ctx("graph", (cap + 4096) * T.BYTES_PER_ENTRY, wg=512, max_trees=64) as ctx:
+            p = ctx.register(kind)
+            ids = []
+            for (G, _), (rp, ci, wt), o in zip(gs, dev, outs):
+                bufs = [rp, ci, o] if kind == T.BFS_CSR else [rp, ci, wt, o]
+                ids.append(ctx.submit(p, [G.V, G.source], bufs))
+            ctx.run()
+            stats = [ctx.results(t)[1] for t in ids]
+        for o, wd, ws, st in zip(outs, want_d, want_s, stats):
+            got = o.cpu().numpy()
+            if kind == T.BFS_CSR:
+                assert np.array_equal(got, wd)
+                assert st.tasks == int((wd >= 0).sum()) and st.epochs == int(wd.max()) + 1
+            else:
+                assert np.array_equal(got, ws)
+                assert st.tasks >= int((ws != oracle.UNREACHED).sum())
+        del outs
+    assert V > 7 * 10**7
