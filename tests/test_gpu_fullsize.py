@@ -106,3 +106,34 @@ def test_graph_batches_full_size():
                 assert st.tasks >= int((ws != oracle.UNREACHED).sum())
         del outs
     assert V > 7 * 10**7
+
+
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+def test_fft_batch_full_size(sched):
+    """The FFT configuration's batch, 64 transforms of 2^18 complex fp32
+    points in shared epochs at 1024 lanes: every tree's statistics equal the
+    oracle's, and a sample of four transforms is compared with the oracle's
+    fp64 run within the radix-2 error bound (the others against numpy's FFT
+    with the same bound)."""
+    import torch
+
+    import oracle
+    import paper_1608_00571_amd as T
+    from tests.gpu_util import fft_tolerance
+    m, n = 18, 64
+    xs = [inputs.complex_signal(1 << m, 900 + g) for g in range(n)]
+    xt = [torch.from_numpy(x.view(np.float32).copy()).cuda() for x in xs]
+    ys = [torch.empty_like(t) for t in xt]
+    arena = (n * (T.tv_bound(T.FFT, [m]) + 64) + 4096) * T.BYTES_PER_ENTRY
+    with make_ctx(sched, arena, wg=1024, max_trees=n) as ctx:
+        p = ctx.register(T.FFT)
+        ids = [ctx.submit(p, [m], [a, b]) for a, b in zip(xt, ys)]
+        ctx.run()
+        stats = [ctx.results(t)[1] for t in ids]
+    _, r = oracle.fft(np.zeros(1 << m, dtype=np.complex128))
+    tol = fft_tolerance(1 << m)
+    for g, (x, y, st) in enumerate(zip(xs, ys, stats)):
+        assert (st.tasks, st.epochs, st.peak_entries, st.launched) == (r.tasks, r.epochs, r.peak, r.launched)
+        got = y.cpu().numpy().view(np.complex64).astype(np.complex128)
+        want = oracle.fft(x.astype(np.complex128))[0] if g % 16 == 0 else np.fft.fft(x.astype(np.complex128))
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) <= tol, g
