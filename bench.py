@@ -35,16 +35,16 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "9a0406df40452cb9", "fetch_bytes": 68792944, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "927fbc08d238babe", "fetch_bytes": 2830364, "write_bytes": 3504699},
-    "k_plain<MS>": {"src": "927fbc08d238babe", "fetch_bytes": 2243771, "write_bytes": 2354629},
+    "k_map_merge<1024,8192>": {"src": "a39e3a83f295935a", "fetch_bytes": 68792867, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "5d34e8d915231878", "fetch_bytes": 2830514, "write_bytes": 3504698},
+    "k_plain<MS>": {"src": "5d34e8d915231878", "fetch_bytes": 2243764, "write_bytes": 2354595},
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "927fbc08d238babe", "wg": 512, "fetch_bytes": 10429911261,
-                         "write_bytes": 12475180544},
+    "k_epochs<FIB|NQ>": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 10429604027,
+                         "write_bytes": 12474202208},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "927fbc08d238babe", "wg": 512, "fetch_bytes": 180322258355 + 142755389740,
-                             "write_bytes": 3391097728 + 4361410976},
+    "k_epochs<GRAPH> sssp": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 180044801134 + 141456997183,
+                             "write_bytes": 3365986048 + 4415063936},
 }
 
 

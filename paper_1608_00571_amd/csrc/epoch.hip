@@ -568,7 +568,6 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
     x0[k] = x1[k] = x2[k] = x3[k] = 0;
     want_map[k] = false; leaf[k] = false; fleaf[k] = false;
     if (op[k] == OP_NONE) continue;
-    const int64_t i = idx[k];
     switch (op[k]) {
       case OP_FIB32:
       case OP_FIB64: {
@@ -1354,7 +1353,6 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
   constexpr bool kFft = (OPS & OPS_FFT) != 0;
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
-  const int32_t ntt = C.ntt;
   const PlainArgs P{};
   const uint32_t T = min(ld_agent(&H->arc_tiles), (uint32_t)kArcTilesAll);
   constexpr int A = arcs_per_lane<WG>();

@@ -413,7 +413,7 @@ __device__ __forceinline__ void merge_out(MapLds<TILE> &M, int tl) {
 // software pipeline over several tiles per work-group slower than one tile
 // per work-group with many work-groups in flight.)
 template <int WG, int TILE, bool FAST>
-__device__ __forceinline__ void map_merge(const MapView &C, MapLds<TILE> &M, uint32_t J, uint64_t U) {
+__device__ __forceinline__ void map_merge(const MapView &C, MapLds<TILE> &M, uint32_t /*jobs*/, uint64_t U) {
   const uint64_t ntiles = (U + TILE - 1) / TILE;
   const int tid = threadIdx.x;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {

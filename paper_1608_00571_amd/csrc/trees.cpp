@@ -404,7 +404,7 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
   while (true) {
     if (*budget == 0 || *(volatile int32_t *)c->abort_flag) break;
     // Phase 1 happened when the range was popped; launch Phase 2.
-    PlainArgs P{slot, st.cen, st.b, st.e, st.old, par, 0, (uint32_t)(t.base >> 6), t.tp};
+    PlainArgs P{slot, st.cen, st.b, st.e, st.old, par, 0, (uint32_t)(t.base >> 6), t.tp, 0u /* nwg: the launcher's */};
     if (st.start_gepoch < 0) st.start_gepoch = (int64_t)*gepochs;
     P.seq = ++c->plain_seq ? c->plain_seq : ++c->plain_seq;
     hipEvent_t e0 = nullptr, e1 = nullptr;
