@@ -308,3 +308,32 @@ def test_bfs_full_scale_graph(sched):
     g = inputs.bfs_batch_graph(0, 22)
     (j,) = run_alone(sched, [Job("bfs", graph=g)], trace=False)
     assert_matches_oracle(j, check_trace=False)
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+def test_arena_reuse_across_runs(sched):
+    """Three rounds on one context whose arena fits about one round: every
+    program's trees reuse the task-vector entries earlier trees left behind
+    (stale codes and arguments), and each result still equals its oracle's."""
+    import paper_1608_00571_amd as T
+
+    def round_jobs(r):
+        g, w = inputs.sssp_graph(9, 60 + r)
+        return [Job("fib64", 17 + r), Job("nqueens", 6 + r), Job("msort", keys=inputs.keys_u32(5000 + r, 70 + r)),
+                Job("bfs", graph=inputs.rmat(9, 80 + r)), Job("sssp", graph=g, weights=w),
+                Job("postorder", bintree=bintree(*inputs.binary_tree(900, 90 + r), 0)),
+                Job("preorder", bintree=bintree(*inputs.binary_tree(700, 95 + r), 0)),
+                Job("fft", signal=inputs.complex_signal(1 << (10 + r), 99 + r))]
+
+    rounds = [round_jobs(r) for r in range(3)]
+    with make_ctx(sched, trace=True) as ctx:
+        register_all(ctx, [j for jobs in rounds for j in jobs])
+        for jobs in rounds:
+            for j in jobs:
+                j.submit(ctx)
+            ctx.run()
+            for j in jobs:
+                j.collect(ctx, trace=True)
+            for j in jobs:
+                assert_matches_oracle(j)
+        assert ctx.num_trees == 0
