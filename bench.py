@@ -171,9 +171,18 @@ def cpu_baseline_cfg2(sample_keys_log2: int = 24, min_seconds: float = 10.0):
         dt += time.perf_counter() - t0
         tasks += r.tasks + m.tasks
         steps += 1
+    # the sequential recursive evaluators (the T1 baseline): the same work
+    # (fib(32)'s calls, the sort's tasks) without the epoch machinery
+    t0 = time.perf_counter()
+    _, calls = oracle.fib_rec(32)
+    oracle.msort_rec(keys)
+    dr = time.perf_counter() - t0
     return {"value": tasks / dt, "unit": "tasks/s", "cores": 1, "kind": "oracle",
             "sample": f"epoch emulator: {steps} whole steps of fib(32) + msort 2^{sample_keys_log2} "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "recursive": {"tasks_per_s": (tasks / steps) / dr, "seconds_per_step": round(dr, 3),
+                          "kind": "sequential recursive evaluators (fib by naive recursion, "
+                                  "recursive merge sort), one core"}}
 
 
 def run_cfg2(args, sched, steps, warmup, nomap=False, key_bufs=None, keys_np=None, timed_kinds=()):
