@@ -156,6 +156,15 @@ def nqueens_shape(n: int):
 
 
 # ---------------------------------------------------------------------------
+def host_cpu() -> str:
+    """The host's CPU model and logical core count (from /proc/cpuinfo)."""
+    try:
+        names = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")]
+        return f"{names[0]} ({len(names)} logical cores)" if names else "unknown"
+    except OSError:
+        return "unknown"
+
+
 def cpu_baseline_cfg2(sample_keys_log2: int = 24, min_seconds: float = 10.0):
     """The oracle's epoch emulator on this host's cores: fib(32) and a merge
     sort of 2^k keys (single-threaded C), whole steps repeated until at least
@@ -180,6 +189,7 @@ def cpu_baseline_cfg2(sample_keys_log2: int = 24, min_seconds: float = 10.0):
     return {"value": tasks / dt, "unit": "tasks/s", "cores": 1, "kind": "oracle",
             "sample": f"epoch emulator: {steps} whole steps of fib(32) + msort 2^{sample_keys_log2} "
                       f"({dt:.1f} s)",
+            "host_cpu": host_cpu(),
             "recursive": {"tasks_per_s": (tasks / steps) / dr, "seconds_per_step": round(dr, 3),
                           "kind": "sequential recursive evaluators (fib by naive recursion, "
                                   "recursive merge sort), one core"}}
