@@ -41,6 +41,10 @@ MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
     "k_epochs<FIB|NQ>": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 10429604027,
                          "write_bytes": 12474202208},
+    # one graph-form run of the 64-graph BFS batch, k_epochs and k_arcs together
+    # (profiles/batched_64rmat_bfs.md)
+    "k_epochs<GRAPH> bfs": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 19532886380 + 79275849928,
+                            "write_bytes": 463671200 + 2487117888},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
     "k_epochs<GRAPH> sssp": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 180044801134 + 141456997183,
@@ -552,6 +556,8 @@ def bench_cfg4(args):
     b = out[best]
     ach = (tv + payload) / (b["ms"] * 1e-3) / 1e9
     amp = (tv + payload + 60 * scanned) / (b["ms"] * 1e-3) / 1e9   # a depth probe moves a 64-B sector
+    m = MEASURED_TRAFFIC["k_epochs<GRAPH> bfs"]
+    traffic = traffic_for("k_epochs<GRAPH> bfs", 0) if (best == "graph" and args.wg == m["wg"]) else None
     return {"metric": "tasks/s", "value": b["vertices_per_s"], "unit": "tasks/s (vertices visited)",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
@@ -561,7 +567,10 @@ def bench_cfg4(args):
             "edges_per_s": b["edges_per_s"], "epochs_per_s": b["global_epochs"] / (b["ms"] * 1e-3),
             "schedulers": out,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "traffic_GBps": round(traffic / (b["ms"] * 1e-3) / 1e9, 1) if traffic else None,
+                         "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE of k_epochs and k_arcs per "
+                                         "graph-form run, work-groups of 512 (profiles/batched_64rmat_bfs.md)",
                          "tv_bytes": tv, "payload_bytes": payload,
                          "sector_amplified": {"achieved": round(amp, 1), "frac": round(amp / HBM_PEAK_GBS, 4)}},
             "setup_s": {"generate": round(gen_s, 1), "oracle_bfs": round(orc_s, 1)}}
