@@ -181,7 +181,7 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      forks preorder(right), preorder(left); nothing joins, so a node is
  *                      visited in the epoch of its depth (the log goes level by level).
  *   FFT:               args = {log2 N}, 0 <= log2 N <= 20; bufs = {x[N], y[N] (out)}, complex
- *                      fp32 interleaved (re, im), distinct.  y receives the DFT of x,
+ *                      fp32 interleaved (re, im), not overlapping.  y receives the DFT of x,
  *                      y[k] = sum_j x[j] exp(-2 pi i jk / N) (no scaling), by recursive radix-2
  *                      decimation in time: FFT(lo, o, ls) transforms x[o + j 2^ls], j < n =
  *                      N / 2^ls, into y[lo, lo + n); n <= 64 is a leaf (a wavefront runs its

@@ -886,9 +886,11 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
     } break;
     case TREES_PROG_FFT: {
       const uint64_t bytes = (uint64_t)8 << args[0];
-      if (nbufs < 2 || !bufs || !bufs[0].ptr || !bufs[1].ptr || bufs[0].bytes < bytes || bufs[1].bytes < bytes ||
-          bufs[0].ptr == bufs[1].ptr)
-        return fail(c, TREES_E_INVALID, "fft: need bufs {x[N], y[N]} of complex fp32, distinct");
+      if (nbufs < 2 || !bufs || !bufs[0].ptr || !bufs[1].ptr || bufs[0].bytes < bytes || bufs[1].bytes < bytes)
+        return fail(c, TREES_E_INVALID, "fft: need bufs {x[N], y[N]} of complex fp32");
+      const uintptr_t x0 = (uintptr_t)bufs[0].ptr, y0 = (uintptr_t)bufs[1].ptr;
+      if (x0 < y0 + bytes && y0 < x0 + bytes)   // the leaves read x while combines write y
+        return fail(c, TREES_E_INVALID, "fft: x and y must not overlap");
       a.a0 = 0; a.a1 = 0; a.a2 = 0;   // FFT(lo = 0, o = 0, ls = 0): the whole input
       a.ts.p0 = (int32_t)args[0];
       a.ts.ptr0 = (uint64_t)bufs[0].ptr;

@@ -91,7 +91,8 @@ def test_fft_bad_arguments():
         p = ctx.register(T.FFT)
         x = torch.zeros(2 << 10, dtype=torch.float32, device="cuda")
         y = torch.zeros_like(x)
-        for args, bufs in [([21], [x, y]), ([-1], [x, y]), ([10], [x, x]), ([11], [x, y]), ([10], [x])]:
+        for args, bufs in [([21], [x, y]), ([-1], [x, y]), ([10], [x, x]), ([11], [x, y]), ([10], [x]),
+                           ([9], [x[:1024], x[512:]])]:   # (the last two overlap by half)
             with pytest.raises(T.TreesError) as e:
                 ctx.submit(p, args, bufs)
             assert e.value.status == T.E_INVALID
