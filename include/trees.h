@@ -189,6 +189,8 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      combine of n/2 butterflies with twiddles exp(-2 pi i k / n), which the
  *                      work-groups expand co-operatively.  x is not modified.  The arena holds
  *                      2 max(1, N/64) - 1 entries.
+ * A program's output buffers must not overlap its input buffers (INVALID
+ * otherwise; msort's keys and tmp must not overlap either).
  * The arena is sized to the exact task-vector bound of the tree, rounded up to
  * a multiple of 64 entries (arenas start on 64-entry boundaries); if it does
  * not fit in the free budget the call returns NOMEM and changes nothing (the

@@ -823,6 +823,13 @@ trees_status trees_register_program(trees_ctx *c, int32_t kind, int32_t *out_pro
   return TREES_OK;
 }
 
+// Whether the first n bytes of buffers a and b share memory (a tree writes
+// its output buffers while it reads its inputs).
+bool overlap(const trees_buf &a, const trees_buf &b, uint64_t na, uint64_t nb) {
+  const uintptr_t x = (uintptr_t)a.ptr, y = (uintptr_t)b.ptr;
+  return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
 trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32_t nargs,
                           const trees_buf *bufs, int32_t nbufs, uint64_t *out_tree) {
   if (!c || !out_tree) return fail(c, TREES_E_INVALID, "null argument");
@@ -852,6 +859,8 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       if (nbufs < 2 || !bufs || (N > 0 && (!bufs[0].ptr || !bufs[1].ptr)) ||
           bufs[0].bytes < (uint64_t)N * 4 || bufs[1].bytes < (uint64_t)N * 4)
         return fail(c, TREES_E_INVALID, "msort: need bufs {keys[N], tmp[N]} of uint32");
+      if (overlap(bufs[0], bufs[1], (uint64_t)N * 4, (uint64_t)N * 4))
+        return fail(c, TREES_E_INVALID, "msort: keys and tmp must not overlap");
       a.a0 = 0; a.a1 = (int32_t)N; a.a2 = 0;
       a.ts.p0 = (int32_t)N;
       a.ts.ptr0 = (uint64_t)bufs[0].ptr;
@@ -862,6 +871,9 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       if (nbufs < 3 || !bufs || !bufs[0].ptr || !bufs[1].ptr || !bufs[2].ptr ||
           bufs[0].bytes < (uint64_t)(V + 1) * 4 || bufs[2].bytes < (uint64_t)V * 4)
         return fail(c, TREES_E_INVALID, "bfs: need bufs {row_ptr[V+1], col_idx[E], depth[V]} of int32");
+      if (overlap(bufs[2], bufs[0], (uint64_t)V * 4, (uint64_t)(V + 1) * 4) ||
+          overlap(bufs[2], bufs[1], (uint64_t)V * 4, bufs[1].bytes))
+        return fail(c, TREES_E_INVALID, "bfs: depth must not overlap the graph");
       a.a0 = (int32_t)src;
       a.ts.p0 = (int32_t)V;
       a.ts.p1 = (int32_t)src;
@@ -876,6 +888,10 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
           bufs[3].bytes < (uint64_t)V * 4)
         return fail(c, TREES_E_INVALID,
                     "sssp: need bufs {row_ptr[V+1], col_idx[E], weights[E], dist[V]} of int32");
+      if (overlap(bufs[3], bufs[0], (uint64_t)V * 4, (uint64_t)(V + 1) * 4) ||
+          overlap(bufs[3], bufs[1], (uint64_t)V * 4, bufs[1].bytes) ||
+          overlap(bufs[3], bufs[2], (uint64_t)V * 4, bufs[2].bytes))
+        return fail(c, TREES_E_INVALID, "sssp: dist must not overlap the graph or the weights");
       a.a0 = (int32_t)src;
       a.ts.p0 = (int32_t)V;
       a.ts.p1 = (int32_t)src;
@@ -903,6 +919,9 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
           bufs[0].bytes < (uint64_t)n * 4 || bufs[1].bytes < (uint64_t)n * 4 ||
           bufs[2].bytes < (uint64_t)(n + 1) * 4)
         return fail(c, TREES_E_INVALID, "postorder: need bufs {left[n], right[n], log[n+1]} of int32");
+      if (overlap(bufs[2], bufs[0], (uint64_t)(n + 1) * 4, (uint64_t)n * 4) ||
+          overlap(bufs[2], bufs[1], (uint64_t)(n + 1) * 4, (uint64_t)n * 4))
+        return fail(c, TREES_E_INVALID, "traversal: log must not overlap the tree");
       a.a0 = (int32_t)args[1];
       a.ts.p0 = (int32_t)n;
       a.ts.p1 = (int32_t)args[1];

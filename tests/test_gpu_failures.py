@@ -109,3 +109,26 @@ def test_bad_arguments_and_late_registration():
         assert c.results(t)[0] == 55
         with pytest.raises(T.TreesError):
             c.results(t)                                # released: the id is stale
+
+
+def test_overlapping_buffers_refused():
+    """Output buffers that overlap a tree's inputs (or msort's keys and tmp)
+    are refused at submit with INVALID; nothing is admitted."""
+    import torch
+
+    import paper_1608_00571_amd as T
+    with ctx("plain") as c:
+        pm, pb = c.register(T.MSORT_U32), c.register(T.BFS_CSR)
+        keys = torch.zeros(4096, dtype=torch.int32, device="cuda")
+        rp = torch.zeros(101, dtype=torch.int32, device="cuda")
+        ci = torch.zeros(16, dtype=torch.int32, device="cuda")
+        for prog, args, bufs in [(pm, [2048], [keys[:2048], keys[1024:3072]]),
+                                 (pb, [100, 0], [rp, ci, rp[:100]]),
+                                 (pb, [10, 0], [rp, ci, ci[:10]])]:
+            with pytest.raises(T.TreesError) as e:
+                c.submit(prog, args, bufs)
+            assert e.value.status == T.E_INVALID
+        assert c.num_trees == 0
+        t = c.submit(pm, [2048], [keys[:2048], keys[2048:]])   # adjacent, not overlapping: admitted
+        c.run()
+        c.results(t)
