@@ -35,23 +35,23 @@ HBM_PEAK_GBS = 8000.0
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "a39e3a83f295935a", "fetch_bytes": 68792867, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "5d34e8d915231878", "fetch_bytes": 2830514, "write_bytes": 3504698},
-    "k_plain<MS>": {"src": "5d34e8d915231878", "fetch_bytes": 2243764, "write_bytes": 2354595},
+    "k_map_merge<1024,8192>": {"src": "6ac319ee73aa2102", "fetch_bytes": 68792867, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "2e2c90353acff024", "fetch_bytes": 2830514, "write_bytes": 3504698},
+    "k_plain<MS>": {"src": "2e2c90353acff024", "fetch_bytes": 2243764, "write_bytes": 2354595},
     # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 10429604027,
+    "k_epochs<FIB|NQ>": {"src": "2e2c90353acff024", "wg": 512, "fetch_bytes": 10429604027,
                          "write_bytes": 12474202208},
     # one graph-form run of the 64-graph BFS batch, k_epochs and k_arcs together
     # (profiles/batched_64rmat_bfs.md)
-    "k_epochs<GRAPH> bfs": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 19532886380 + 79275849928,
+    "k_epochs<GRAPH> bfs": {"src": "2e2c90353acff024", "wg": 512, "fetch_bytes": 19532886380 + 79275849928,
                             "write_bytes": 463671200 + 2487117888},
     # one persistent run of the FFT batch (64 x 2^18), one k_epochs dispatch
     # (profiles/fft_64x2e18_and_2e20.md)
-    "k_epochs<FFT> batch": {"src": "5d34e8d915231878", "wg": 1024, "fetch_bytes": 1963832719,
+    "k_epochs<FFT> batch": {"src": "2e2c90353acff024", "wg": 1024, "fetch_bytes": 1963832719,
                             "write_bytes": 1764480576},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "5d34e8d915231878", "wg": 512, "fetch_bytes": 180044801134 + 141456997183,
+    "k_epochs<GRAPH> sssp": {"src": "2e2c90353acff024", "wg": 512, "fetch_bytes": 180044801134 + 141456997183,
                              "write_bytes": 3365986048 + 4415063936},
 }
 

@@ -64,10 +64,11 @@ struct TreeStatic {
   int32_t cap;       // arena capacity in entries
   int32_t tbase;     // global type id of the program's first type
   int32_t kind;      // trees_builtin
-  int32_t p0, p1;    // fib n | nqueens n | msort N | bfs, sssp V, source | postorder n, root
-  uint32_t tp;       // tbase | (nqueens n or postorder n) << 8, as the work list carries it
+  int32_t p0, p1;    // fib n | nqueens n | msort N | bfs, sssp V, source | traversal n, root | fft log2 N
+  uint32_t tp;       // tbase | parameter << 8 (nqueens n, traversal n, fft log2 N, sssp bucket
+                     // width), as the work list carries it
   // msort: keys, tmp; bfs: row_ptr, col_idx, depth; sssp: row_ptr, col_idx,
-  // dist, weights; postorder: left, right, log
+  // dist, weights; postorder, preorder: left, right, log; fft: x, y
   uint64_t ptr0, ptr1, ptr2, ptr3;
 };
 
