@@ -1013,7 +1013,7 @@ def main():
         args.wg = (1024 if args.config in (1, 2, 8) and (args.sched == "plain" or args.config == 8)
                    else 512 if args.config in (4, 5, 6, 7) else 256)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:
