@@ -52,7 +52,11 @@ enum {
  *             replayed until no tree is live.
  *  PERSISTENT all live trees share each epoch inside one co-resident
  *             (cooperative) launch with a device grid barrier per epoch.
- *  AUTO       PERSISTENT or GRAPH as the tuned configuration says. */
+ *  AUTO       the launch shape (scheduler, work-group size, work-groups per
+ *             CU, graph chunk) that a tuner recorded for this device and the
+ *             context's workload class in the tuned file (trees_tuned_shape);
+ *             without such a record, GRAPH at the context's own shape.  The
+ *             file is read once, at the context's first AUTO run. */
 typedef enum {
   TREES_SCHED_PLAIN = 0,
   TREES_SCHED_GRAPH = 1,
@@ -122,7 +126,17 @@ typedef struct {
   double seconds;          /* host wall time of the run */
   int32_t grid;            /* work-groups of the batched launch (0 for PLAIN) */
   int32_t api_blocks_per_cu; /* the runtime's occupancy figure for that kernel */
+  int32_t sched;           /* the scheduler that ran (AUTO resolved) */
+  int32_t wg_size;         /* its work-group size */
 } trees_run_stats;
+
+/* A launch shape: what the tuner chooses and AUTO applies. */
+typedef struct {
+  int32_t sched;           /* TREES_SCHED_PLAIN, _GRAPH or _PERSISTENT */
+  int32_t wg_size;         /* 256, 512 or 1024 */
+  int32_t blocks_per_cu;   /* 0 = automatic */
+  int32_t graph_chunk;     /* 0 = the context's */
+} trees_shape;
 
 typedef struct {
   int32_t epoch, cen, b, e, launched, valid, forks, joins, nfc;
@@ -173,7 +187,8 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  *                      bufs = {left[n], right[n], log[n+1] (out)} int32; left/right hold each
  *                      node's children, -1 = none.  postorder(node) forks postorder(right),
  *                      postorder(left) and joins a visit of node; a visit appends the node to
- *                      log (log[n] counts the visits; the library zeroes it at submit).  Nodes
+ *                      log (log[n] counts the visits; the library zeroes it at the next
+ *                      trees_run, before the tree's first epoch).  Nodes
  *                      must form a tree under root (each reachable node has one parent).
  *                      The arena holds 2n+1 entries (every postorder task, null children
  *                      included).
@@ -201,15 +216,17 @@ trees_status trees_submit(trees_ctx *ctx, int32_t prog, const int64_t *args, int
                           const trees_buf *bufs, int32_t nbufs, uint64_t *out_tree);
 
 /* Run epochs until no tree is live, trees_abort is called, or max_epochs
- * epochs have run (< 0: no limit).  Blocking.  A tree that is stopped by the
+ * epochs have run (< 0: no limit).  Each epoch is Phase 1, 2 and 3 of
+ * Section 4.3 over every live tree; a tree ends when its stack of pending
+ * ranges is empty (Section 4.3.3).  Blocking.  A tree that is stopped by the
  * budget keeps its state and continues at the next trees_run.  out may be
  * NULL. */
 trees_status trees_run(trees_ctx *ctx, int64_t max_epochs, uint32_t flags, trees_run_stats *out);
 
 /* Result of one tree.  Returns PENDING while it is live, its error if it
- * failed, OK otherwise.  *out_value receives the root's emitted value (fib:
- * F(n); nqueens: the count; msort and BFS: 0, their output is in the
- * caller's buffers).  OK and errors release the tree's slot and arena: the id
+ * failed, OK otherwise.  *out_value receives the value the root task emitted
+ * into its own entry (Section 4.3.2, emit; fib: F(n); nqueens: the count;
+ * msort and BFS: 0, their output is in the caller's buffers).  OK and errors release the tree's slot and arena: the id
  * is invalid afterwards.  Either output pointer may be NULL. */
 trees_status trees_results(trees_ctx *ctx, uint64_t tree, int64_t *out_value,
                            trees_tree_stats *out_stats);
@@ -266,6 +283,63 @@ trees_status trees_set_schedule(trees_ctx *ctx, int32_t sched, int32_t wg_size,
 /* Exact task-vector entries a tree of `kind` with `args` can occupy at once.
  * Admission charges this rounded up to a multiple of 64.  Host-only. */
 trees_status trees_tv_bound(int32_t kind, const int64_t *args, int32_t nargs, int64_t *entries);
+
+/* The tuned shape for a device name (hipDeviceProp_t::name) and a workload
+ * class, read from the tuned file at `path` (NULL: $TREES_TUNE_FILE, else
+ * $HOME/.cache/trees/tuned.txt).  The file holds one shape per line:
+ * device TAB class TAB "sched wg_size blocks_per_cu graph_chunk"; the last
+ * line for a (device, class) pair wins and lines that do not parse are
+ * skipped.  OK and *out filled if a shape was found, INVALID otherwise.
+ * Host-only. */
+trees_status trees_tuned_shape(const char *path, const char *device, const char *wclass, trees_shape *out);
+
+/* The workload class of a context, as the tuned file keys it: the kinds of
+ * its registered programs (trees_builtin numbers), ascending, joined by '+'
+ * ("2+4" for FIB_I64 and NQUEENS).  Copies at most cap bytes, NUL included. */
+trees_status trees_workload_class(const trees_ctx *ctx, char *buf, int32_t cap);
+
+/* ---------------------------------------------------------------------------
+ * Native worklist BFS and SSSP: the hand-managed formulation that Section 6.3
+ * compares TREES with.  Each iteration is one kernel over an input worklist
+ * of vertices; every vertex relaxes its out-arcs (BFS: a head at depth -1 is
+ * claimed by compare-and-swap to level + 1; SSSP: a head's distance is lowered
+ * by an atomic min) and pushes each head it claims or improves to the output
+ * worklist through one atomically advanced tail counter (an SSSP head at most
+ * once per iteration).  After each kernel the host reads back that one count;
+ * the lists swap and the next kernel covers the old output list, until an
+ * iteration pushes nothing.  The kernels run on the context's stream with its
+ * work-group size and the host polls host-mapped memory for the count, as the
+ * PLAIN scheduler does for its epoch counters.
+ *
+ * Workspace: caller-owned device memory of at least trees_wl_workspace_bytes
+ * bytes, 256-byte aligned, not overlapping the output; it holds the two
+ * worklists (V int32 each), the SSSP push stamps (V int32) and 256 bytes of
+ * counters, and may be reused between calls (not concurrently).
+ * Errors: INVALID (bad sizes, null pointers, workspace too small or
+ * misaligned, output overlapping it), STATE (an asynchronous trees_run is
+ * active), DEVICE.  Blocking: returns when the last iteration has finished.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t iterations;      /* relaxation kernels launched (the last pushes nothing) */
+  int32_t pad;
+  uint64_t pushed;         /* vertices pushed to output worklists, all iterations */
+  double seconds;          /* host wall time of the call */
+} trees_wl_stats;
+
+/* Workspace bytes for a graph of V vertices (sssp != 0: with the stamps). */
+trees_status trees_wl_workspace_bytes(int32_t V, int32_t sssp, uint64_t *bytes);
+
+/* BFS from source: depth[V] (out) receives hop counts, -1 = unreachable.
+ * int32 CSR row_ptr[V + 1], col_idx[E] (device pointers). */
+trees_status trees_wl_bfs(trees_ctx *ctx, int32_t V, int32_t source, const int32_t *row_ptr,
+                          const int32_t *col_idx, int32_t *depth, void *ws, uint64_t ws_bytes,
+                          trees_wl_stats *out);
+
+/* SSSP from source with int32 weights[E] >= 0 (every distance below 2^31 - 1):
+ * dist[V] (out) receives shortest distances, 2^31 - 1 = unreachable. */
+trees_status trees_wl_sssp(trees_ctx *ctx, int32_t V, int32_t source, const int32_t *row_ptr,
+                           const int32_t *col_idx, const int32_t *weights, int32_t *dist, void *ws,
+                           uint64_t ws_bytes, trees_wl_stats *out);
 
 /* Free task-vector entries of the budget (for admission decisions). */
 int64_t trees_free_entries(const trees_ctx *ctx);

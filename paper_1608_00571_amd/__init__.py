@@ -67,7 +67,18 @@ class _TreeStats(ctypes.Structure):
 class _RunStats(ctypes.Structure):
     _fields_ = [("global_epochs", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
                 ("stop_reason", ctypes.c_int32), ("live", ctypes.c_int32), ("seconds", ctypes.c_double),
-                ("grid", ctypes.c_int32), ("api_blocks_per_cu", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("api_blocks_per_cu", ctypes.c_int32),
+                ("sched", ctypes.c_int32), ("wg_size", ctypes.c_int32)]
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("sched", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("graph_chunk", ctypes.c_int32)]
+
+
+class _WlStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("pad", ctypes.c_int32), ("pushed", ctypes.c_uint64),
+                ("seconds", ctypes.c_double)]
 
 
 class _KTime(ctypes.Structure):
@@ -122,6 +133,16 @@ def lib():
         L.trees_free_entries.argtypes = [vp]
         L.trees_num_trees.restype = i32
         L.trees_num_trees.argtypes = [vp]
+        L.trees_tuned_shape.restype = i32
+        L.trees_tuned_shape.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_Shape)]
+        L.trees_workload_class.restype = i32
+        L.trees_workload_class.argtypes = [vp, ctypes.c_char_p, i32]
+        L.trees_wl_workspace_bytes.restype = i32
+        L.trees_wl_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(u64)]
+        L.trees_wl_bfs.restype = i32
+        L.trees_wl_bfs.argtypes = [vp, i32, i32, vp, vp, vp, vp, u64, ctypes.POINTER(_WlStats)]
+        L.trees_wl_sssp.restype = i32
+        L.trees_wl_sssp.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, u64, ctypes.POINTER(_WlStats)]
         _lib = L
     return _lib
 
@@ -129,7 +150,9 @@ def lib():
 EXPORTED = ("trees_create", "trees_destroy", "trees_last_error", "trees_register_program",
             "trees_submit", "trees_run", "trees_results", "trees_trace", "trees_abort",
             "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees",
-            "trees_kernel_times", "trees_profile_mask", "trees_epoch_times", "trees_debug_phases")
+            "trees_kernel_times", "trees_profile_mask", "trees_epoch_times", "trees_debug_phases",
+            "trees_tuned_shape", "trees_workload_class", "trees_wl_workspace_bytes", "trees_wl_bfs",
+            "trees_wl_sssp")
 
 
 @dataclass
@@ -152,6 +175,34 @@ class RunStats:
     seconds: float
     grid: int = 0
     api_blocks_per_cu: int = 0
+    sched: int = 0
+    wg_size: int = 0
+
+
+def tuned_shape(device: str, wclass: str, path: str | None = None):
+    """The tuned file's (sched, wg_size, blocks_per_cu, graph_chunk) for a
+    device name and workload class, or None (what AUTO reads)."""
+    out = _Shape()
+    rc = lib().trees_tuned_shape(path.encode() if path else None, device.encode(), wclass.encode(),
+                                 ctypes.byref(out))
+    if rc:
+        return None
+    return (int(out.sched), int(out.wg_size), int(out.blocks_per_cu), int(out.graph_chunk))
+
+
+@dataclass
+class WlStats:
+    iterations: int
+    pushed: int
+    seconds: float
+
+
+def wl_workspace_bytes(V: int, sssp: bool = False) -> int:
+    out = ctypes.c_uint64(0)
+    rc = lib().trees_wl_workspace_bytes(V, 1 if sssp else 0, ctypes.byref(out))
+    if rc:
+        raise TreesError(rc, "trees_wl_workspace_bytes")
+    return int(out.value)
 
 
 def tv_bound(kind: int, args) -> int:
@@ -268,7 +319,8 @@ class Context:
         st = _RunStats()
         self._check(lib().trees_run(self.h, max_epochs, 0, ctypes.byref(st)), "run")
         return RunStats(int(st.global_epochs), int(st.tasks), int(st.stop_reason), int(st.live),
-                        float(st.seconds), int(st.grid), int(st.api_blocks_per_cu))
+                        float(st.seconds), int(st.grid), int(st.api_blocks_per_cu), int(st.sched),
+                        int(st.wg_size))
 
     def results(self, tree: int):
         """(value, TreeStats); raises TreesError(PENDING) if the tree is live,
@@ -335,6 +387,32 @@ class Context:
     def set_schedule(self, sched, wg: int = 0, blocks_per_cu: int = 0, graph_chunk: int = 0):
         s = SCHEDS[sched] if isinstance(sched, str) else int(sched)
         self._check(lib().trees_set_schedule(self.h, s, wg, blocks_per_cu, graph_chunk), "set_schedule")
+
+    def wl_bfs(self, V: int, source: int, row_ptr, col_idx, depth, ws) -> WlStats:
+        """Native worklist BFS (Section 6.3's comparison): depth (int32 [V],
+        out) gets hop counts; ws: a device workspace of wl_workspace_bytes(V)."""
+        self._torch.cuda.current_stream(self.device).synchronize()
+        st = _WlStats()
+        rp, ci, d, w = (_ptr_bytes(t)[0] for t in (row_ptr, col_idx, depth, ws))
+        self._check(lib().trees_wl_bfs(self.h, V, source, rp, ci, d, w, _ptr_bytes(ws)[1], ctypes.byref(st)),
+                    "wl_bfs")
+        return WlStats(int(st.iterations), int(st.pushed), float(st.seconds))
+
+    def wl_sssp(self, V: int, source: int, row_ptr, col_idx, weights, dist, ws) -> WlStats:
+        """Native worklist SSSP: dist (int32 [V], out) gets shortest distances."""
+        self._torch.cuda.current_stream(self.device).synchronize()
+        st = _WlStats()
+        rp, ci, wt, d, w = (_ptr_bytes(t)[0] for t in (row_ptr, col_idx, weights, dist, ws))
+        self._check(lib().trees_wl_sssp(self.h, V, source, rp, ci, wt, d, w, _ptr_bytes(ws)[1],
+                                        ctypes.byref(st)), "wl_sssp")
+        return WlStats(int(st.iterations), int(st.pushed), float(st.seconds))
+
+    @property
+    def workload_class(self) -> str:
+        """The registered program kinds as the tuned file keys them ("2+4")."""
+        buf = ctypes.create_string_buffer(128)
+        self._check(lib().trees_workload_class(self.h, buf, 128), "workload_class")
+        return buf.value.decode()
 
     @property
     def free_entries(self) -> int:

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtrees.so")
 ARCH = os.environ.get("TREES_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["epoch.hip", "map.hip", "trees.cpp"]
+SOURCES = ["epoch.hip", "map.hip", "worklist.hip", "trees.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -698,7 +698,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       } else if (vis) {
         pos = atomicAdd(&log[n], 1);
       }
-      if (vis && pos < n) log[pos] = a0v[k];   // (more visits than nodes: the input was no tree)
+      if (vis && pos >= 0 && pos < n) log[pos] = a0v[k];   // (more visits than nodes: the input was no tree)
     }
   }
 

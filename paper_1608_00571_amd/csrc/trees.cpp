@@ -6,6 +6,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 #include <chrono>
 #include <map>
@@ -28,6 +31,9 @@ hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
 hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, int32_t fill, hipStream_t s);
 const void *kernel_epochs(int wg, uint32_t need);
+hipError_t launch_wl(const WlArgs &a, int wg, bool sssp, hipStream_t s);
+hipError_t launch_wl_init(int32_t *val, int32_t *stamp, int32_t V, int32_t src, int32_t fill, int32_t *in,
+                          void *ctl, hipStream_t s);
 }  // namespace trees
 
 using namespace trees;
@@ -207,6 +213,9 @@ struct trees_ctx {
   Admit *adm_dev = nullptr;
   PlainMirror *mirror = nullptr;   // host-mapped, written after each plain epoch
   uint32_t plain_seq = 0;
+  WlMirror *wl_mirror = nullptr;   // host-mapped, written after each worklist iteration
+  WlMirror *wl_mirror_dev = nullptr;
+  uint32_t wl_seq = 0;
   SchedHdr *hdr_host = nullptr;
   TreeState *st_host = nullptr;
   int32_t *abort_flag = nullptr;
@@ -217,8 +226,12 @@ struct trees_ctx {
   uint32_t gkey_ops = 0;
   int sched = TREES_SCHED_PERSISTENT;
   int wg = 256, bpc = 0, chunk = 8;
+  std::string devname;              // hipDeviceProp_t::name (the tuned file's device key)
+  bool tuned_done = false;          // AUTO: the tuned file has been consulted
+  bool tuned_ok = false;            // ... and held a shape for this device and workload class
+  trees_shape tuned{};
   int ncu = 0;
-  int last_grid = 0, last_api_bpc = 0;
+  int last_grid = 0, last_api_bpc = 0, last_wg = 0;
   bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // plain-scheduler launch timing: event pairs resolved after the tree's
@@ -230,6 +243,7 @@ struct trees_ctx {
   double clock_hz = 1e8;
   double timeout_s = 60.0;   // host and device waits give up after this long
   bool running = false;
+  bool async_on = false;           // an asynchronous run is in flight
   std::string err;
   std::mutex mu;
 };
@@ -362,14 +376,14 @@ trees_status resolve_events(trees_ctx *c) {
 
 // Wait until the plain epoch launch `seq` has published its counters in the
 // mirror.  Polls host memory; checks the stream for errors now and then.
-trees_status wait_mirror(trees_ctx *c, uint32_t seq) {
+trees_status wait_seq(trees_ctx *c, const uint32_t *seqp, uint32_t seq) {
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 1;; ++spin) {
-    if (__atomic_load_n(&c->mirror->seq, __ATOMIC_ACQUIRE) == seq) return TREES_OK;
+    if (__atomic_load_n(seqp, __ATOMIC_ACQUIRE) == seq) return TREES_OK;
     if ((spin & 1023) == 0) {
       const hipError_t q = hipStreamQuery(c->stream);
       if (q == hipSuccess) {
-        if (__atomic_load_n(&c->mirror->seq, __ATOMIC_ACQUIRE) == seq) return TREES_OK;
+        if (__atomic_load_n(seqp, __ATOMIC_ACQUIRE) == seq) return TREES_OK;
         return fail(c, TREES_E_DEVICE, "epoch launch ended without publishing its counters");
       }
       if (q != hipErrorNotReady) return fail(c, TREES_E_DEVICE, std::string("epoch launch: ") + hipGetErrorString(q));
@@ -379,6 +393,7 @@ trees_status wait_mirror(trees_ctx *c, uint32_t seq) {
     __builtin_ia32_pause();
   }
 }
+trees_status wait_mirror(trees_ctx *c, uint32_t seq) { return wait_seq(c, &c->mirror->seq, seq); }
 
 // ---------------------------------------------------------------------------
 // PLAIN: the paper's host-driven loop, one tree at a time.
@@ -611,6 +626,147 @@ trees_status run_persistent(trees_ctx *c, int64_t max_epochs) {
   return TREES_OK;
 }
 
+// The workload class of a context: its registered program kinds, ascending,
+// joined by '+' (the key of a tuned shape beside the device name).
+std::string workload_class(const trees_ctx *c) {
+  std::vector<int> k;
+  for (const auto &p : c->progs) k.push_back(p.kind);
+  std::sort(k.begin(), k.end());
+  std::string out;
+  for (size_t i = 0; i < k.size(); ++i) out += (i ? "+" : "") + std::to_string(k[i]);
+  return out;
+}
+
+std::string tuned_path(const char *path) {
+  if (path && *path) return path;
+  const char *e = getenv("TREES_TUNE_FILE");
+  if (e && *e) return e;
+  const char *h = getenv("HOME");
+  return std::string(h && *h ? h : ".") + "/.cache/trees/tuned.txt";
+}
+
+// Reads the tuned file: one shape per line, "device<TAB>class<TAB>sched wg bpc
+// chunk"; the last line for (device, class) wins.  Lines that do not parse
+// are skipped.
+bool read_tuned(const std::string &path, const std::string &dev, const std::string &wclass, trees_shape *out) {
+  FILE *f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char *t1 = strchr(line, '\t');
+    if (!t1) continue;
+    char *t2 = strchr(t1 + 1, '\t');
+    if (!t2) continue;
+    *t1 = 0; *t2 = 0;
+    if (dev != line || wclass != (t1 + 1)) continue;
+    trees_shape sh{};
+    if (sscanf(t2 + 1, "%d %d %d %d", &sh.sched, &sh.wg_size, &sh.blocks_per_cu, &sh.graph_chunk) != 4) continue;
+    if (sh.sched < TREES_SCHED_PLAIN || sh.sched > TREES_SCHED_PERSISTENT) continue;
+    if (sh.wg_size != 256 && sh.wg_size != 512 && sh.wg_size != 1024) continue;
+    if (sh.blocks_per_cu < 0 || sh.graph_chunk < 0) continue;
+    *out = sh;
+    found = true;
+  }
+  fclose(f);
+  return found;
+}
+
+trees_status run_sched(trees_ctx *c, int sched, int64_t max_epochs, const std::vector<int> &before,
+                       uint64_t *gepochs_out, int32_t *stop_out) {
+  trees_status s = TREES_OK;
+  uint64_t gepochs = 0;
+  int32_t stop_reason = 1;
+  c->last_wg = c->wg;
+  if (sched == TREES_SCHED_PLAIN) {
+    std::vector<int> order = before;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return c->trees[a].order < c->trees[b].order; });
+    int64_t budget = max_epochs;
+    const bool trace = c->dc.trace_on != 0;
+    for (int slot : order) {
+      s = run_plain_tree(c, slot, &budget, &gepochs, trace);
+      if (s) return s;
+      if (budget == 0) { stop_reason = 2; break; }
+      if (*(volatile int32_t *)c->abort_flag) { stop_reason = 3; break; }
+    }
+  } else {
+    s = (sched == TREES_SCHED_GRAPH) ? run_graph(c, max_epochs) : run_persistent(c, max_epochs);
+    if (s) return s;
+    gepochs = (uint64_t)c->hdr_host->run_epochs;
+    stop_reason = c->hdr_host->stop_reason;
+    s = sync_states(c);
+    if (s) return s;
+  }
+  *gepochs_out = gepochs;
+  *stop_out = stop_reason;
+  return TREES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Native worklist BFS / SSSP (Section 6.3's hand-managed comparison)
+// ---------------------------------------------------------------------------
+struct WlLayout {
+  size_t ctl, in0, in1, stamp, total;
+};
+WlLayout wl_layout(int64_t V, bool sssp) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  WlLayout L{};
+  L.ctl = 0;
+  L.in0 = up(sizeof(WlCtl));
+  L.in1 = L.in0 + up((size_t)V * 4);
+  L.stamp = L.in1 + up((size_t)V * 4);
+  L.total = L.stamp + (sssp ? up((size_t)V * 4) : 0);
+  return L;
+}
+
+trees_status wl_run(trees_ctx *c, bool sssp, int32_t V, int32_t source, const int32_t *row_ptr,
+                    const int32_t *col_idx, const int32_t *weights, int32_t *val, void *ws, uint64_t ws_bytes,
+                    trees_wl_stats *out) {
+  if (!c) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  const char *what = sssp ? "wl_sssp" : "wl_bfs";
+  if (V < 1 || source < 0 || source >= V) return fail(c, TREES_E_INVALID, std::string(what) + ": need V >= 1 and 0 <= source < V");
+  if (!row_ptr || !col_idx || !val || !ws || (sssp && !weights))
+    return fail(c, TREES_E_INVALID, std::string(what) + ": null pointer");
+  const WlLayout L = wl_layout(V, sssp);
+  if (ws_bytes < L.total) return fail(c, TREES_E_INVALID, std::string(what) + ": workspace too small");
+  const uintptr_t a = (uintptr_t)ws, b = (uintptr_t)val;
+  if (a < b + (uint64_t)V * 4 && b < a + L.total)
+    return fail(c, TREES_E_INVALID, std::string(what) + ": the output overlaps the workspace");
+  if ((a & 255) != 0) return fail(c, TREES_E_INVALID, std::string(what) + ": workspace not 256-byte aligned");
+  if (c->async_on) return fail(c, TREES_E_STATE, std::string(what) + ": an asynchronous run is active");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, TREES_E_DEVICE, "hipSetDevice failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  char *w = (char *)ws;
+  int32_t *lists[2] = {(int32_t *)(w + L.in0), (int32_t *)(w + L.in1)};
+  int32_t *stamp = sssp ? (int32_t *)(w + L.stamp) : nullptr;
+  HIPCHK(c, launch_wl_init(val, stamp, V, source, sssp ? INT32_MAX : -1, lists[0], w + L.ctl, c->stream));
+  uint32_t n = 1;
+  int32_t it = 0;
+  uint64_t pushed = 0;
+  while (n > 0) {
+    WlArgs A{};
+    A.row = row_ptr; A.col = col_idx; A.w = weights; A.val = val;
+    A.in = lists[it & 1]; A.out = lists[(it & 1) ^ 1]; A.stamp = stamp;
+    A.ctl = (WlCtl *)(w + L.ctl); A.mir = c->wl_mirror_dev;
+    A.n_in = n; A.level = it; A.par = it & 1;
+    A.seq = ++c->wl_seq ? c->wl_seq : ++c->wl_seq;
+    HIPCHK(c, launch_wl(A, c->wg, sssp, c->stream));
+    TRY(wait_seq(c, &c->wl_mirror->seq, A.seq));
+    n = __atomic_load_n(&c->wl_mirror->count, __ATOMIC_ACQUIRE);
+    if (n > (uint32_t)V) return fail(c, TREES_E_DEVICE, std::string(what) + ": output worklist beyond V entries");
+    pushed += n;
+    ++it;
+  }
+  if (out) {
+    out->iterations = it;
+    out->pad = 0;
+    out->pushed = pushed;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return TREES_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -644,6 +800,7 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(TREES_E_DEVICE, "no device properties");
   c->ncu = prop.multiProcessorCount;
+  c->devname = prop.name;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
     c->clock_hz = khz * 1000.0;
@@ -748,8 +905,13 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
       hipHostMalloc((void **)&c->hdr_host, sizeof(SchedHdr), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->st_host, T * sizeof(TreeState), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->r_host, 64, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->abort_flag, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+      hipHostMalloc((void **)&c->abort_flag, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+      hipHostMalloc((void **)&c->wl_mirror, sizeof(WlMirror), hipHostMallocCoherent | hipHostMallocMapped) !=
+          hipSuccess)
     return bail(TREES_E_NOMEM, "hipHostMalloc failed");
+  memset(c->wl_mirror, 0, sizeof(WlMirror));
+  if (hipHostGetDevicePointer((void **)&c->wl_mirror_dev, c->wl_mirror, 0) != hipSuccess)
+    return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   *c->abort_flag = 0;
   int32_t *dev_abort = nullptr;
   if (hipHostGetDevicePointer((void **)&dev_abort, c->abort_flag, 0) != hipSuccess)
@@ -780,6 +942,7 @@ void trees_destroy(trees_ctx *c) {
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->r_host) (void)hipHostFree(c->r_host);
   if (c->abort_flag) (void)hipHostFree(c->abort_flag);
+  if (c->wl_mirror) (void)hipHostFree(c->wl_mirror);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -928,9 +1091,6 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
       a.ts.ptr0 = (uint64_t)bufs[0].ptr;
       a.ts.ptr1 = (uint64_t)bufs[1].ptr;
       a.ts.ptr2 = (uint64_t)bufs[2].ptr;
-      // the visit counter (log[n]) starts at zero, before the tree's first epoch
-      if (hipMemsetAsync((int32_t *)bufs[2].ptr + n, 0, 4, c->stream) != hipSuccess)
-        return fail(c, TREES_E_DEVICE, "postorder: clearing the visit counter failed");
     } break;
   }
   int slot = -1;
@@ -964,6 +1124,11 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
     c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1], -1});
   if (P.kind == TREES_PROG_SSSP_CSR)
     c->depth_inits.push_back({(int32_t *)bufs[3].ptr, (int32_t)args[0], (int32_t)args[1], INT32_MAX});
+  // a traversal's visit counter (log[n]) starts at zero before the tree's
+  // first epoch; it is cleared inside trees_run, on the context's stream,
+  // after the caller's own work on the buffer
+  if (P.kind == TREES_PROG_POSTORDER || P.kind == TREES_PROG_PREORDER)
+    c->depth_inits.push_back({(int32_t *)bufs[2].ptr + args[0], 1, -1, 0});
   c->tslots = std::max(c->tslots, slot + 1);
   c->ntrees++;
   *out_tree = ((uint64_t)t.gen << 32) | (uint32_t)slot;
@@ -984,26 +1149,26 @@ trees_status trees_run(trees_ctx *c, int64_t max_epochs, uint32_t flags, trees_r
     if (c->trees[i].hstatus == H_LIVE) before.push_back(i);
   uint64_t gepochs = 0;
   int32_t stop_reason = 1;
-  int sched = c->sched == TREES_SCHED_AUTO ? TREES_SCHED_PERSISTENT : c->sched;
-  if (sched == TREES_SCHED_PLAIN) {
-    std::vector<int> order = before;
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return c->trees[a].order < c->trees[b].order; });
-    int64_t budget = max_epochs;
-    const bool trace = c->dc.trace_on != 0;
-    for (int slot : order) {
-      s = run_plain_tree(c, slot, &budget, &gepochs, trace);
-      if (s) return s;
-      if (budget == 0) { stop_reason = 2; break; }
-      if (*(volatile int32_t *)c->abort_flag) { stop_reason = 3; break; }
+  // AUTO: the shape the tuner chose for this device and workload class (read
+  // once from the tuned file), else the graph form at the context's shape
+  int sched = c->sched;
+  const int wg0 = c->wg, bpc0 = c->bpc, chunk0 = c->chunk;
+  if (sched == TREES_SCHED_AUTO) {
+    if (!c->tuned_done) {
+      c->tuned_ok = read_tuned(tuned_path(nullptr), c->devname, workload_class(c), &c->tuned);
+      c->tuned_done = true;
     }
-  } else {
-    s = (sched == TREES_SCHED_GRAPH) ? run_graph(c, max_epochs) : run_persistent(c, max_epochs);
-    if (s) return s;
-    gepochs = (uint64_t)c->hdr_host->run_epochs;
-    stop_reason = c->hdr_host->stop_reason;
-    s = sync_states(c);
-    if (s) return s;
+    sched = TREES_SCHED_GRAPH;
+    if (c->tuned_ok) {
+      sched = c->tuned.sched;
+      c->wg = c->tuned.wg_size;
+      c->bpc = c->tuned.blocks_per_cu;
+      if (c->tuned.graph_chunk > 0) c->chunk = c->tuned.graph_chunk;
+    }
   }
+  s = run_sched(c, sched, max_epochs, before, &gepochs, &stop_reason);
+  c->wg = wg0; c->bpc = bpc0; c->chunk = chunk0;   // (AUTO's shape holds for this run only)
+  if (s) return s;
   if (out) {
     out->global_epochs = gepochs;
     uint64_t tasks = 0;
@@ -1019,6 +1184,8 @@ trees_status trees_run(trees_ctx *c, int64_t max_epochs, uint32_t flags, trees_r
     out->grid = (sched == TREES_SCHED_PLAIN) ? 0 : c->last_grid;
     out->api_blocks_per_cu = c->last_api_bpc;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out->sched = sched;
+    out->wg_size = c->last_wg;
   }
   if (stop_reason == 4) return fail(c, TREES_E_DEVICE, "persistent barrier timed out");
   return TREES_OK;
@@ -1138,6 +1305,36 @@ trees_status trees_epoch_times(trees_ctx *c, double *us, int32_t cap, int32_t *n
   }
   *n = ne;
   return TREES_OK;
+}
+
+trees_status trees_tuned_shape(const char *path, const char *device, const char *wclass, trees_shape *out) {
+  if (!device || !wclass || !out) return TREES_E_INVALID;
+  return read_tuned(tuned_path(path), device, wclass, out) ? TREES_OK : TREES_E_INVALID;
+}
+
+trees_status trees_workload_class(const trees_ctx *c, char *buf, int32_t cap) {
+  if (!c || !buf || cap <= 0) return TREES_E_INVALID;
+  const std::string w = workload_class(c);
+  const size_t n = std::min<size_t>(w.size(), (size_t)cap - 1);
+  memcpy(buf, w.data(), n);
+  buf[n] = 0;
+  return TREES_OK;
+}
+
+trees_status trees_wl_workspace_bytes(int32_t V, int32_t sssp, uint64_t *bytes) {
+  if (!bytes || V < 1) return TREES_E_INVALID;
+  *bytes = wl_layout(V, sssp != 0).total;
+  return TREES_OK;
+}
+
+trees_status trees_wl_bfs(trees_ctx *c, int32_t V, int32_t source, const int32_t *row_ptr, const int32_t *col_idx,
+                          int32_t *depth, void *ws, uint64_t ws_bytes, trees_wl_stats *out) {
+  return wl_run(c, false, V, source, row_ptr, col_idx, nullptr, depth, ws, ws_bytes, out);
+}
+
+trees_status trees_wl_sssp(trees_ctx *c, int32_t V, int32_t source, const int32_t *row_ptr, const int32_t *col_idx,
+                           const int32_t *weights, int32_t *dist, void *ws, uint64_t ws_bytes, trees_wl_stats *out) {
+  return wl_run(c, true, V, source, row_ptr, col_idx, weights, dist, ws, ws_bytes, out);
 }
 
 int64_t trees_free_entries(const trees_ctx *c) { return c ? c->free_ent : 0; }

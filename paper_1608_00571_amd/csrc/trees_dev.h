@@ -264,4 +264,42 @@ struct PlainArgs {
   uint32_t nwg;   // work-groups of the launch (the last to finish publishes); set by the launcher
 };
 
+
+// ---------------------------------------------------------------------------
+// Native worklist BFS / SSSP (the hand-managed comparison of Section 6.3)
+// ---------------------------------------------------------------------------
+constexpr int kWlChunk = 1024;   // worklist entries per work-group
+
+// Control words of one worklist run (in the caller's workspace, 256 B).
+struct alignas(128) WlCtl {
+  uint32_t tail[2];      // output-list counters, by iteration parity
+  uint32_t pad0[30];
+  uint32_t ticket;       // work-groups of the iteration that have finished
+  uint32_t pad1[31];
+};
+
+// Host-mapped copy of an iteration's output count; `seq` is written last.
+struct WlMirror {
+  uint32_t count;
+  uint32_t seq;
+};
+
+struct WlArgs {
+  const int32_t *row;      // CSR row pointers [V + 1]
+  const int32_t *col;      // CSR heads [E]
+  const int32_t *w;        // SSSP arc weights [E] (null for BFS)
+  int32_t *val;            // BFS depth / SSSP distance [V]
+  const int32_t *in;       // input worklist
+  int32_t *out;            // output worklist
+  int32_t *stamp;          // SSSP: iteration that last pushed each vertex [V]
+  WlCtl *ctl;
+  WlMirror *mir;           // device address of the host-mapped mirror
+  uint32_t n_in;           // entries of the input list
+  int32_t level;           // iteration number (BFS: the depth of the input vertices)
+  int32_t par;             // iteration parity (which tail counter this iteration advances)
+  uint32_t seq;            // launch number published in the mirror
+  uint32_t nwg;            // work-groups of the launch
+  int32_t pad;
+};
+
 }  // namespace trees

@@ -89,3 +89,17 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(T, "_lib", None)
     with pytest.raises(ImportError):
         T.lib()
+
+
+def test_worklist_workspace_bytes():
+    """The worklist comparator's workspace: 256 B of counters and two lists of
+    V int32 (plus V push stamps for SSSP), each section 256-byte aligned."""
+    import paper_1608_00571_amd as T
+    if not os.path.exists(T.LIB_PATH):
+        pytest.skip("libtrees.so not built")
+    up = lambda x: (x + 255) // 256 * 256
+    for V in (1, 63, 64, 1000, 1 << 22):
+        assert T.wl_workspace_bytes(V) == 256 + 2 * up(4 * V)
+        assert T.wl_workspace_bytes(V, sssp=True) == 256 + 3 * up(4 * V)
+    with pytest.raises(T.TreesError):
+        T.wl_workspace_bytes(0)

@@ -30,3 +30,30 @@ def test_tune_picks_fastest_and_caches(tmp_path):
     # another workload class is tuned separately
     A.tune(measure, list(cost)[:3], "devX", "other", cache_path=path)
     assert len(calls) == n + 3
+
+
+def test_tuned_file_round_trip(tmp_path):
+    """The tuner's tuned file is what the library's AUTO scheduler reads: a
+    shape written for (device, workload class) comes back through the C ABI,
+    the last line for a pair wins, other pairs and malformed lines do not
+    interfere."""
+    import paper_1608_00571_amd as T
+    path = str(tmp_path / "tuned.txt")
+    A.write_tuned("AMD Instinct MI355X", "2+4", A.Shape("graph", 512, 2, 16), path)
+    A.write_tuned("AMD Instinct MI355X", "5", A.Shape("persistent", 1024, 1, 8), path)
+    with open(path, "a") as f:
+        f.write("garbage line\nAMD Instinct MI355X\t2+4\tnot numbers\n")
+    assert T.tuned_shape("AMD Instinct MI355X", "2+4", path) == (T.GRAPH, 512, 2, 16)
+    assert T.tuned_shape("AMD Instinct MI355X", "5", path) == (T.PERSISTENT, 1024, 1, 8)
+    assert T.tuned_shape("AMD Instinct MI355X", "3", path) is None
+    assert T.tuned_shape("other device", "2+4", path) is None
+    # a later choice for the same pair replaces the earlier one
+    A.write_tuned("AMD Instinct MI355X", "2+4", A.Shape("persistent", 256, 0, 8), path)
+    assert T.tuned_shape("AMD Instinct MI355X", "2+4", path) == (T.PERSISTENT, 256, 0, 8)
+    with open(path) as f:
+        assert sum(1 for ln in f if ln.startswith("AMD Instinct MI355X\t2+4\t")) == 1
+    # a line with an invalid work-group size is skipped
+    with open(path, "a") as f:
+        f.write("AMD Instinct MI355X\t5\t1 384 0 8\n")
+    assert T.tuned_shape("AMD Instinct MI355X", "5", path) == (T.PERSISTENT, 1024, 1, 8)
+    assert T.tuned_shape("nobody", "x", str(tmp_path / "missing.txt")) is None

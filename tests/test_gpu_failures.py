@@ -132,3 +132,36 @@ def test_overlapping_buffers_refused():
         t = c.submit(pm, [2048], [keys[:2048], keys[2048:]])   # adjacent, not overlapping: admitted
         c.run()
         c.results(t)
+
+
+@pytest.mark.parametrize("kind", ["postorder", "preorder"])
+def test_traversal_log_cleared_after_pending_fill(kind):
+    """A traversal's visit counter (log[n]) is cleared inside trees_run, after
+    the caller's own pending work on the log: a fill of the log that is still
+    queued on the caller's stream at submit (behind a device-side sleep)
+    lands before the clear, so the tree still logs every node once.  A
+    submit refused for lack of budget leaves the log untouched."""
+    import torch
+
+    import inputs
+    import paper_1608_00571_amd as T
+    left, right = inputs.binary_tree(5000, 11)
+    n = left.shape[0]
+    lt = torch.from_numpy(left).cuda()
+    rt = torch.from_numpy(right).cuda()
+    with ctx("graph", arena=(2 * n + 1 + 64) * T.BYTES_PER_ENTRY) as c:
+        p = c.register(T.POSTORDER if kind == "postorder" else T.PREORDER)
+        log = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+        torch.cuda._sleep(20_000_000)   # keeps the fill below queued past the submit
+        log.fill_(-7)
+        t = c.submit(p, [n, 0], [lt, rt, log])
+        # a second tree does not fit: refused, and its log keeps its contents
+        log2 = torch.full((n + 1,), 5, dtype=torch.int32, device="cuda")
+        assert c.try_submit(p, [n, 0], [lt, rt, log2]) is None
+        c.run()
+        c.results(t)
+        torch.cuda.synchronize()
+        out = log.cpu().numpy()
+        assert int(out[n]) == n
+        assert sorted(out[:n].tolist()) == list(range(n))
+        assert np.all(log2.cpu().numpy() == 5)
