@@ -341,6 +341,20 @@ trees_status trees_wl_sssp(trees_ctx *ctx, int32_t V, int32_t source, const int3
                            const int32_t *col_idx, const int32_t *weights, int32_t *dist, void *ws,
                            uint64_t ws_bytes, trees_wl_stats *out);
 
+/* trees_wl_bfs for callers that cannot allocate memory at call time (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the worklists and counters live in a fixed array of device
+ * memory inside the library (32 MiB + 256 B on every GPU it runs on, held
+ * until the process ends) instead of a caller's workspace.  Graphs of at most
+ * 2^22 vertices (INVALID above).  The call allocates nothing: no device, host
+ * or pinned memory.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (each call initialises what it reads), so
+ * calls that overlap on one GPU -- from different contexts or threads --
+ * race; calls through one context are serialised.  Results, statistics and
+ * other errors as trees_wl_bfs. */
+trees_status trees_wl_bfs_noalloc(trees_ctx *ctx, int32_t V, int32_t source, const int32_t *row_ptr,
+                                  const int32_t *col_idx, int32_t *depth, trees_wl_stats *out);
+
 /* Free task-vector entries of the budget (for admission decisions). */
 int64_t trees_free_entries(const trees_ctx *ctx);
 

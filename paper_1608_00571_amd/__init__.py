@@ -141,6 +141,8 @@ def lib():
         L.trees_wl_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(u64)]
         L.trees_wl_bfs.restype = i32
         L.trees_wl_bfs.argtypes = [vp, i32, i32, vp, vp, vp, vp, u64, ctypes.POINTER(_WlStats)]
+        L.trees_wl_bfs_noalloc.restype = i32
+        L.trees_wl_bfs_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(_WlStats)]
         L.trees_wl_sssp.restype = i32
         L.trees_wl_sssp.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, u64, ctypes.POINTER(_WlStats)]
         _lib = L
@@ -152,7 +154,7 @@ EXPORTED = ("trees_create", "trees_destroy", "trees_last_error", "trees_register
             "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees",
             "trees_kernel_times", "trees_profile_mask", "trees_epoch_times", "trees_debug_phases",
             "trees_tuned_shape", "trees_workload_class", "trees_wl_workspace_bytes", "trees_wl_bfs",
-            "trees_wl_sssp")
+            "trees_wl_sssp", "trees_wl_bfs_noalloc")
 
 
 @dataclass
@@ -396,6 +398,15 @@ class Context:
         rp, ci, d, w = (_ptr_bytes(t)[0] for t in (row_ptr, col_idx, depth, ws))
         self._check(lib().trees_wl_bfs(self.h, V, source, rp, ci, d, w, _ptr_bytes(ws)[1], ctypes.byref(st)),
                     "wl_bfs")
+        return WlStats(int(st.iterations), int(st.pushed), float(st.seconds))
+
+    def wl_bfs_noalloc(self, V: int, source: int, row_ptr, col_idx, depth) -> WlStats:
+        """wl_bfs with its workspace in the library's fixed device array (no
+        allocation in the call; V <= 2^22)."""
+        self._torch.cuda.current_stream(self.device).synchronize()
+        st = _WlStats()
+        rp, ci, d = (_ptr_bytes(t)[0] for t in (row_ptr, col_idx, depth))
+        self._check(lib().trees_wl_bfs_noalloc(self.h, V, source, rp, ci, d, ctypes.byref(st)), "wl_bfs_noalloc")
         return WlStats(int(st.iterations), int(st.pushed), float(st.seconds))
 
     def wl_sssp(self, V: int, source: int, row_ptr, col_idx, weights, dist, ws) -> WlStats:

@@ -34,6 +34,8 @@ const void *kernel_epochs(int wg, uint32_t need);
 hipError_t launch_wl(const WlArgs &a, int wg, bool sssp, hipStream_t s);
 hipError_t launch_wl_init(int32_t *val, int32_t *stamp, int32_t V, int32_t src, int32_t fill, int32_t *in,
                           void *ctl, hipStream_t s);
+hipError_t wl_scratch_setup(int device);
+void *wl_scratch_ptr(int device);
 }  // namespace trees
 
 using namespace trees;
@@ -801,6 +803,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(TREES_E_DEVICE, "no device properties");
   c->ncu = prop.multiProcessorCount;
   c->devname = prop.name;
+  // the allocation-free worklist BFS's fixed workspace on this device
+  if (wl_scratch_setup(c->device) != hipSuccess) return bail(TREES_E_DEVICE, "hipGetSymbolAddress of the worklist scratch failed");
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
     c->clock_hz = khz * 1000.0;
@@ -1335,6 +1339,15 @@ trees_status trees_wl_bfs(trees_ctx *c, int32_t V, int32_t source, const int32_t
 trees_status trees_wl_sssp(trees_ctx *c, int32_t V, int32_t source, const int32_t *row_ptr, const int32_t *col_idx,
                            const int32_t *weights, int32_t *dist, void *ws, uint64_t ws_bytes, trees_wl_stats *out) {
   return wl_run(c, true, V, source, row_ptr, col_idx, weights, dist, ws, ws_bytes, out);
+}
+
+trees_status trees_wl_bfs_noalloc(trees_ctx *c, int32_t V, int32_t source, const int32_t *row_ptr,
+                                  const int32_t *col_idx, int32_t *depth, trees_wl_stats *out) {
+  if (!c) return TREES_E_INVALID;
+  if (V > kWlScratchMaxV) return fail(c, TREES_E_INVALID, "wl_bfs_noalloc: V above 2^22, the fixed workspace's limit");
+  void *ws = wl_scratch_ptr(c->device);
+  if (!ws) return fail(c, TREES_E_STATE, "wl_bfs_noalloc: no fixed workspace on this device");
+  return wl_run(c, false, V, source, row_ptr, col_idx, nullptr, depth, ws, kWlScratchBytes, out);
 }
 
 int64_t trees_free_entries(const trees_ctx *c) { return c ? c->free_ent : 0; }

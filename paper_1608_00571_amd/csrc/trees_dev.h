@@ -269,6 +269,11 @@ struct PlainArgs {
 // Native worklist BFS / SSSP (the hand-managed comparison of Section 6.3)
 // ---------------------------------------------------------------------------
 constexpr int kWlChunk = 1024;   // worklist entries per work-group
+// The allocation-free worklist BFS keeps its workspace (256 B of counters
+// and two worklists of V int32, 256-byte aligned sections) in a fixed device
+// array: graphs of up to 2^22 vertices.
+constexpr int32_t kWlScratchMaxV = 1 << 22;
+constexpr size_t kWlScratchBytes = 256 + 2 * (size_t)kWlScratchMaxV * 4;
 
 // Control words of one worklist run (in the caller's workspace, 256 B).
 struct alignas(128) WlCtl {

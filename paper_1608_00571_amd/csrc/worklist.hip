@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "prims.h"
 #include "trees_dev.h"
 
@@ -179,6 +181,38 @@ hipError_t launch_wl_init(int32_t *val, int32_t *stamp, int32_t V, int32_t src, 
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   return hipLaunchKernel((const void *)&k_wl_init, dim3(blocks), dim3(256), args, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free worklist BFS: a fixed array in device
+// memory (each GPU the library runs on holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address, taken once per device at context creation, is kept below.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kWlScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// With `device` current: record the device address of its scratch array.
+hipError_t wl_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+// The device address recorded for `device`, or null before its setup.
+void *wl_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 size_t wl_ctl_bytes() { return sizeof(WlCtl); }
