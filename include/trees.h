@@ -74,6 +74,11 @@ enum {
                          * the next epoch */
 };
 
+/* trees_run flags */
+enum {
+  TREES_RUN_ASYNC = 1u  /* start a persistent run and return at once (see trees_run) */
+};
+
 typedef struct {
   uint32_t struct_size;   /* sizeof(trees_config) */
   int32_t device;         /* HIP device ordinal */
@@ -87,7 +92,8 @@ typedef struct {
                            * never exceeds 3/4 of the runtime's occupancy figure) */
   int32_t graph_chunk;    /* epochs per captured graph; 0 = 8 */
   uint32_t flags;         /* TREES_F_* */
-  double timeout_s;       /* PERSISTENT barrier spin limit in seconds; 0 = 60 */
+  double timeout_s;       /* PERSISTENT barrier spin limit in seconds; 0 = 60; also how long an
+                           * asynchronous run may stay idle (no live tree) before it ends */
 } trees_config;
 
 /* Built-in task programs (their task bodies are compiled into the library). */
@@ -121,7 +127,8 @@ typedef struct {
 typedef struct {
   uint64_t global_epochs;  /* epochs executed by this run */
   uint64_t tasks;          /* valid tasks of trees that finished in this run */
-  int32_t stop_reason;     /* 1 drained, 2 epoch budget, 3 abort, 4 barrier timeout */
+  int32_t stop_reason;     /* 1 drained, 2 epoch budget, 3 abort, 4 barrier timeout,
+                            * 5 an asynchronous run idle for timeout_s */
   int32_t live;            /* trees still live after the run */
   double seconds;          /* host wall time of the run */
   int32_t grid;            /* work-groups of the batched launch (0 for PLAIN) */
@@ -211,7 +218,15 @@ trees_status trees_register_program(trees_ctx *ctx, int32_t kind, int32_t *out_p
  * not fit in the free budget the call returns NOMEM and changes nothing (the
  * caller may retry once other trees have been collected).  Buffers must stay
  * alive and unmodified until trees_results returns OK for the tree.  The tree
- * becomes live at the next trees_run.  *out_tree receives its id. */
+ * becomes live at the next trees_run.  *out_tree receives its id.
+ * While an asynchronous run is active (trees_run with TREES_RUN_ASYNC) the
+ * call may come from any host thread: the tree is published into a lock-free
+ * admission ring in host-mapped memory, which the running kernel reads at
+ * every epoch boundary; the kernel then places the root (Section 5.2.1),
+ * initialises the BFS depth / SSSP distance / visit counter on the device
+ * and runs the tree from the next epoch on, beside the trees already live.
+ * The caller's writes to the payload must have completed (its stream
+ * synchronised) before the call. */
 trees_status trees_submit(trees_ctx *ctx, int32_t prog, const int64_t *args, int32_t nargs,
                           const trees_buf *bufs, int32_t nbufs, uint64_t *out_tree);
 
@@ -220,7 +235,21 @@ trees_status trees_submit(trees_ctx *ctx, int32_t prog, const int64_t *args, int
  * Section 4.3 over every live tree; a tree ends when its stack of pending
  * ranges is empty (Section 4.3.3).  Blocking.  A tree that is stopped by the
  * budget keeps its state and continues at the next trees_run.  out may be
- * NULL. */
+ * NULL.  flags: 0 or TREES_RUN_ASYNC.
+ *
+ * TREES_RUN_ASYNC (PERSISTENT or AUTO scheduler; INVALID otherwise) launches
+ * the persistent kernel and returns at once: trees_submit may then be called
+ * concurrently (trees join the shared epochs at the next epoch boundary),
+ * and finished trees come back through a completion ring that trees_poll
+ * and trees_results read, without stopping the kernel.  With no tree live,
+ * the kernel waits for submissions in slices of 2 ms (empty epochs, not
+ * counted) and ends by itself after timeout_s idle (stop_reason 5), on
+ * trees_abort, or at max_epochs.  The next blocking trees_run closes the run:
+ * the kernel finishes every live and submitted tree, then returns; that call
+ * reports the whole asynchronous run in *out (max_epochs is not used).
+ * STATE if an asynchronous run is already active.  While one is active,
+ * trees_trace, trees_epoch_times, trees_debug_phases, trees_set_schedule
+ * and the worklist calls return STATE. */
 trees_status trees_run(trees_ctx *ctx, int64_t max_epochs, uint32_t flags, trees_run_stats *out);
 
 /* Result of one tree.  Returns PENDING while it is live, its error if it
@@ -230,6 +259,12 @@ trees_status trees_run(trees_ctx *ctx, int64_t max_epochs, uint32_t flags, trees
  * is invalid afterwards.  Either output pointer may be NULL. */
 trees_status trees_results(trees_ctx *ctx, uint64_t tree, int64_t *out_value,
                            trees_tree_stats *out_stats);
+
+/* Ids of finished trees (their results ready), each reported once, oldest
+ * first: at most cap ids into ids, their number in *n.  During an
+ * asynchronous run it takes in the completion ring first.  Trees already
+ * released by trees_results are skipped. */
+trees_status trees_poll(trees_ctx *ctx, uint64_t *ids, int32_t cap, int32_t *n);
 
 /* Per-epoch records of a tree run with TREES_F_TRACE (at most 256 epochs).
  * Copies up to cap records into out and stores the count in *n.  Call before

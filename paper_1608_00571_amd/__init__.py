@@ -36,6 +36,7 @@ PROGRAMS = {"fib32": FIB_I32, "fib64": FIB_I64, "msort": MSORT_U32, "nqueens": N
 SSSP_UNREACHED = 2**31 - 1   # distance of a vertex the source does not reach
 
 F_TRACE, F_DEBUG, F_PROFILE, F_NOMAP = 1, 2, 4, 8
+RUN_ASYNC = 1
 BYTES_PER_ENTRY = 28
 
 
@@ -113,6 +114,8 @@ def lib():
         L.trees_run.argtypes = [vp, i64, ctypes.c_uint32, ctypes.POINTER(_RunStats)]
         L.trees_results.restype = i32
         L.trees_results.argtypes = [vp, u64, ctypes.POINTER(i64), ctypes.POINTER(_TreeStats)]
+        L.trees_poll.restype = i32
+        L.trees_poll.argtypes = [vp, ctypes.POINTER(u64), i32, ctypes.POINTER(i32)]
         L.trees_trace.restype = i32
         L.trees_trace.argtypes = [vp, u64, vp, i32, ctypes.POINTER(i32)]
         L.trees_abort.restype = i32
@@ -154,7 +157,7 @@ EXPORTED = ("trees_create", "trees_destroy", "trees_last_error", "trees_register
             "trees_set_schedule", "trees_tv_bound", "trees_free_entries", "trees_num_trees",
             "trees_kernel_times", "trees_profile_mask", "trees_epoch_times", "trees_debug_phases",
             "trees_tuned_shape", "trees_workload_class", "trees_wl_workspace_bytes", "trees_wl_bfs",
-            "trees_wl_sssp", "trees_wl_bfs_noalloc")
+            "trees_wl_sssp", "trees_wl_bfs_noalloc", "trees_poll")
 
 
 @dataclass
@@ -259,6 +262,7 @@ class Context:
         if rc:
             raise TreesError(rc, L.trees_last_error(None).decode())
         self.h = h
+        self._async = False
         self._keep = {}   # tree id -> payload tensors kept alive until results
         self._progs = {}
 
@@ -269,6 +273,10 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            # an asynchronous run ends at its next epoch boundary (trees_destroy
+            # also requests it); then the device may be synchronised
+            if self._async:
+                lib().trees_abort(self.h)
             self._torch.cuda.synchronize(self.device)
             lib().trees_destroy(self.h)
             self.h = None
@@ -295,7 +303,12 @@ class Context:
         self._progs[kind] = out.value
         return out.value
 
-    def submit(self, prog: int, args, bufs=()) -> int:
+    def submit(self, prog: int, args, bufs=(), ready: bool = False) -> int:
+        """trees_submit.  During an asynchronous run the payload must be on the
+        device already: unless `ready`, the current stream is synchronised
+        first."""
+        if bufs and self._async and not ready:
+            self._torch.cuda.current_stream(self.device).synchronize()
         a = (ctypes.c_int64 * max(1, len(args)))(*args)
         pb = [_ptr_bytes(t) for t in bufs]
         b = (_Buf * max(1, len(pb)))(*[_Buf(p, n) for p, n in pb])
@@ -307,19 +320,23 @@ class Context:
         self._keep[out.value] = tuple(bufs)
         return out.value
 
-    def try_submit(self, prog: int, args, bufs=()):
+    def try_submit(self, prog: int, args, bufs=(), ready: bool = False):
         """submit(), but returns None instead of raising when the tree does not fit now."""
         try:
-            return self.submit(prog, args, bufs)
+            return self.submit(prog, args, bufs, ready)
         except TreesError as e:
             if e.status == E_NOMEM:
                 return None
             raise
 
-    def run(self, max_epochs: int = -1) -> RunStats:
+    def run(self, max_epochs: int = -1, asynchronous: bool = False) -> RunStats:
+        """trees_run.  asynchronous=True starts a persistent run and returns at
+        once (submit, poll and results work while it runs); the next blocking
+        run() closes it and reports the whole run."""
         self._torch.cuda.current_stream(self.device).synchronize()
         st = _RunStats()
-        self._check(lib().trees_run(self.h, max_epochs, 0, ctypes.byref(st)), "run")
+        self._check(lib().trees_run(self.h, max_epochs, RUN_ASYNC if asynchronous else 0, ctypes.byref(st)), "run")
+        self._async = asynchronous
         return RunStats(int(st.global_epochs), int(st.tasks), int(st.stop_reason), int(st.live),
                         float(st.seconds), int(st.grid), int(st.api_blocks_per_cu), int(st.sched),
                         int(st.wg_size))
@@ -347,6 +364,13 @@ class Context:
             if e.status == E_PENDING:
                 return None
             raise
+
+    def poll_finished(self, cap: int = 4096) -> list:
+        """Ids of trees that have finished since the last call (trees_poll)."""
+        arr = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int32(0)
+        self._check(lib().trees_poll(self.h, arr, cap, ctypes.byref(n)), "poll")
+        return [int(arr[i]) for i in range(n.value)]
 
     def trace(self, tree: int) -> np.ndarray:
         out = np.zeros(256, dtype=REC_DTYPE)

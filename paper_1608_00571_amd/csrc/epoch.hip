@@ -33,6 +33,7 @@
 #include "bodies.h"
 #include "map.h"
 #include "prims.h"
+#include "trees.h"
 #include "trees_dev.h"
 
 namespace trees {
@@ -56,6 +57,7 @@ struct Lds {
   uint32_t gen;
   int32_t sink;            // destination of atomics whose completion must be awaited
   int32_t tflag;
+  int32_t sflag, scnt;     // work-list scan: broadcast and counter (adoption)
   uint32_t jbase;          // first map job reserved by this work-group
   uint64_t ubase;          // first map unit reserved by this work-group
   int64_t tprof;           // debug: clock at the last phase boundary
@@ -1149,6 +1151,86 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
 }
 
 // ---------------------------------------------------------------------------
+// Admission of a tree on the device: its descriptor, state and counters, and
+// its root in entry 0 of its arena, to run in epoch 0 (Section 5.2.1).
+// ---------------------------------------------------------------------------
+__device__ void admit_one(const DevCtx &C, const Admit &a) {
+  const int s = a.slot;
+  ((TreeStatic *)C.ts)[s] = a.ts;
+  TreeState T = {};
+  T.cen = 0; T.b = 0; T.e = 1; T.old = 1; T.sp = 0; T.status = TS_LIVE; T.err = 0;
+  T.epochs = 0; T.tasks = 1; T.launched = 0; T.result = 0; T.done_gepoch = -1;
+  T.start_gepoch = -1; T.peak = 1; T.ntrace = 0;
+  C.st[s] = T;
+  TreeHot Hh = {};
+  Hh.nfc = 1;
+  C.hot[s] = Hh;
+  C.t_len[s] = 1; C.t_cen[s] = 0; C.t_b[s] = 0;
+  const int64_t r0 = a.ts.base;
+  C.code[r0] = a.root_code;
+  C.a0[r0] = a.a0; C.a1[r0] = a.a1; C.a2[r0] = a.a2; C.a3[r0] = a.a3;
+  C.r[r0] = 0;
+}
+
+// Whether a program's per-vertex or log buffer is initialised before its
+// first epoch (BFS depth, SSSP distance, a traversal's visit counter).
+__device__ __forceinline__ bool needs_init(int kind) {
+  return kind == TREES_PROG_BFS_CSR || kind == TREES_PROG_SSSP_CSR || kind == TREES_PROG_POSTORDER ||
+         kind == TREES_PROG_PREORDER;
+}
+
+// Asynchronous run: adopt the trees published in the admission ring since the
+// last scan.  Their slots are appended to the candidate list at `nlive`; the
+// ones whose buffers need initialising are listed for the init phase that
+// precedes the next epoch's chunks.  Returns the number adopted.  Every
+// thread of the scanning work-group calls it.
+template <int WG>
+__device__ int adopt(const DevCtx &C, Lds<WG> &L, int32_t *cand, int nlive) {
+  SchedHdr *H = C.hdr;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const uint32_t tail = __hip_atomic_load(&C.ring->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    L.sflag = (int)(tail - H->adm_head);
+    L.scnt = H->initN;
+  }
+  __syncthreads();
+  const int nn = min(L.sflag, C.tmax - nlive);   // (never clamped: a record needs a free slot)
+  const uint32_t head = H->adm_head;
+  __syncthreads();
+  if (nn <= 0) return 0;
+  for (int j = tid; j < nn; j += WG) {
+    const Admit a = C.ring_adm[(head + (uint32_t)j) % (uint32_t)C.tmax];
+    admit_one(C, a);
+    cand[nlive + j] = a.slot;
+    if (needs_init(a.ts.kind)) C.init_slot[atomicAdd(&L.scnt, 1)] = a.slot;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    H->adm_head = head + (uint32_t)nn;
+    H->initN = L.scnt;
+    __hip_atomic_store(&C.ring->head, head + (uint32_t)nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  __syncthreads();
+  return nn;
+}
+
+// The init phase of an asynchronous run: every work-group sweeps the buffers
+// of the trees adopted by the last scan (grid-stride), before their roots run.
+__device__ void run_inits(const DevCtx &C, int n) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    const TreeStatic &T = C.ts[C.init_slot[j]];
+    int32_t *p = (int32_t *)T.ptr2;
+    int64_t cnt = T.p0, src = T.p1;
+    int32_t fill = -1;   // BFS depth
+    if (T.kind == TREES_PROG_SSSP_CSR) fill = INT32_MAX;
+    if (T.kind == TREES_PROG_POSTORDER || T.kind == TREES_PROG_PREORDER) { p += T.p0; cnt = 1; src = -1; fill = 0; }
+    for (int64_t x = gid; x < cnt; x += step) p[x] = (x == src) ? 0 : fill;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Work-list construction (the serial part of Phase 1 over all trees): an
 // exclusive scan of the per-tree range lengths.  One work-group.
 // ---------------------------------------------------------------------------
@@ -1156,9 +1238,13 @@ template <int WG>
 __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
+  // an epoch that had no work list (an asynchronous run waiting for
+  // submissions) is not counted
+  const bool real = after_epoch && H->L > 0;
   if (after_epoch) {   // trees finished this epoch: result and end epoch
     const int nd = H->done_count;
     const int64_t ge = H->gepoch;
+    const uint32_t ct = H->ctail;
     constexpr int RD = WG >= 1024 ? 1 : 1024 / WG;
     for (int j0 = 0; j0 < nd; j0 += WG * RD) {
       int slot[RD], err[RD];
@@ -1181,63 +1267,117 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
         TreeState *T = &C.st[slot[r]];
         if (err[r] == 0) T->result = res[r];
         T->done_gepoch = ge;
+        if (C.async_mode) {   // its completion record, for the host
+          Completion *q = &C.ring_done[(ct + (uint32_t)(j0 + r * WG + tid)) % (uint32_t)C.tmax];
+          const auto sys = [](auto *p, auto v) {
+            __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          };
+          sys(&q->slot, (int32_t)slot[r]);
+          sys(&q->err, (int32_t)err[r]);
+          sys(&q->epochs, T->epochs);
+          sys(&q->peak, T->peak);
+          sys(&q->tasks, T->tasks);
+          sys(&q->launched, T->launched);
+          sys(&q->result, err[r] == 0 ? res[r] : (int64_t)0);
+          sys(&q->start_gepoch, T->start_gepoch);
+          sys(&q->done_gepoch, ge);
+        }
+      }
+    }
+    if (C.async_mode && nd > 0) {   // the records have landed: publish their count
+      wait_vmem();
+      __syncthreads();
+      if (tid == 0) {
+        H->ctail = ct + (uint32_t)nd;
+        __hip_atomic_store(&C.ring->ctail, ct + (uint32_t)nd, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
   }
   // Candidates: after an epoch, the trees of the last work list (a live
-  // tree always has a non-empty range); at the start of a run, every slot.
-  // Rounds of WG x R candidates: every load of a round is issued before any
-  // of its values is used, then one work-group scan places the round.
+  // tree always has a non-empty range), plus the trees an asynchronous run
+  // adopts now; at the start of a run, every slot.  Rounds of WG x R
+  // candidates: every load of a round is issued before any of its values is
+  // used, then one work-group scan places the round.
   const int sel = H->live_sel;
-  const int32_t *src = C.live + (size_t)sel * C.tmax;
+  int32_t *src = C.live + (size_t)sel * C.tmax;
   int32_t *dst = C.live + (size_t)(after_epoch ? (sel ^ 1) : 0) * C.tmax;
-  const int n = after_epoch ? H->live : H->tslots;
-  const int64_t g = H->gepoch + (after_epoch ? 1 : 0);
+  int n = after_epoch ? H->live : H->tslots;
+  const int64_t g = H->gepoch + (real ? 1 : 0);
   constexpr int R = WG >= 1024 ? 1 : 1024 / WG;   // (bounded: registers of the epoch kernel)
   int ctot = 0;
   uint32_t itot = 0;
-  for (int base = 0; base < n; base += WG * R) {
-    int slot[R], len[R], b[R], cen[R];
-    int64_t tbase[R], sg[R];
-    uint32_t tp[R];
+  const bool asy = C.async_mode != 0 && after_epoch;
+  if (asy && tid == 0) H->initN = 0;   // (the last scan's list was swept before this epoch)
+  __syncthreads();
+  for (;;) {
+    if (asy) n += adopt<WG>(C, L, src, n);
+    ctot = 0;
+    itot = 0;
+    for (int base = 0; base < n; base += WG * R) {
+      int slot[R], len[R], b[R], cen[R];
+      int64_t tbase[R], sg[R];
+      uint32_t tp[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int t = base + r * WG + tid;
-      slot[r] = t < n ? (after_epoch ? src[t] : t) : -1;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
-      if (slot[r] >= 0) {
-        const int s = slot[r];
-        len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
-        tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
+      for (int r = 0; r < R; ++r) {
+        const int t = base + r * WG + tid;
+        slot[r] = t < n ? (after_epoch ? src[t] : t) : -1;
       }
-    }
-    int cnt = 0, items = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (len[r] > 0) { ++cnt; items += len[r]; }
-    int rc, ri;
-    int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
-    uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
+      for (int r = 0; r < R; ++r) {
+        len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
+        if (slot[r] >= 0) {
+          const int s = slot[r];
+          len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
+          tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
+        }
+      }
+      int cnt = 0, items = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (len[r] <= 0) continue;
-      const int s = slot[r];
-      dst[k] = s;
-      C.wl_tree[k] = s;
-      C.wl_off[k] = off;
-      C.wl_b[k] = b[r];
-      C.wl_tb[k] = (uint32_t)(tbase[r] >> 6);
-      C.wl_tp[k] = tp[r];
-      C.wl_cen[k] = cen[r];
-      if (sg[r] < 0) C.st[s].start_gepoch = g;
-      ++k;
-      off += (uint32_t)len[r];
+      for (int r = 0; r < R; ++r)
+        if (len[r] > 0) { ++cnt; items += len[r]; }
+      int rc, ri;
+      int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
+      uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (len[r] <= 0) continue;
+        const int s = slot[r];
+        dst[k] = s;
+        C.wl_tree[k] = s;
+        C.wl_off[k] = off;
+        C.wl_b[k] = b[r];
+        C.wl_tb[k] = (uint32_t)(tbase[r] >> 6);
+        C.wl_tp[k] = tp[r];
+        C.wl_cen[k] = cen[r];
+        if (sg[r] < 0) C.st[s].start_gepoch = g;
+        ++k;
+        off += (uint32_t)len[r];
+      }
+      ctot += rc;
+      itot += (uint32_t)ri;
     }
-    ctot += rc;
-    itot += (uint32_t)ri;
+    if (!asy || ctot > 0) break;
+    // Asynchronous run with nothing live: wait for a submission, the close
+    // request or an abort, for at most one slice; then run an empty epoch
+    // (every work-group returns to the barrier, whose waits stay short).
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t t0 = realtime();
+      int more = 0;
+      while (true) {
+        if ((int)(__hip_atomic_load(&C.ring->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - H->adm_head) > 0) {
+          more = 1;
+          break;
+        }
+        if (__hip_atomic_load(&C.ring->close, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (C.abort_flag && *C.abort_flag) break;
+        if (realtime() - t0 > C.slice_ticks) break;
+        __builtin_amdgcn_s_sleep(8);
+      }
+      L.sflag = more;
+    }
+    __syncthreads();
+    if (!L.sflag) break;
   }
   __syncthreads();
   if (tid == 0) {
@@ -1246,6 +1386,7 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
       H->mapJ = (uint32_t)(mc >> kMapShift);
       st_agent(&H->map_ctr, (uint64_t)0);
     }
+    if (!asy) H->initN = 0;
     st_agent(&H->chunk_ctr, 0u);   // every work-group has stopped claiming this epoch's chunks
     st_agent(&H->arc_jobs, 0u);    // and has left this epoch's arc phase
     st_agent(&H->arc_tiles, 0u);
@@ -1258,15 +1399,29 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
     H->L = ctot;
     H->live = ctot;
     H->done_count = 0;
-    if (after_epoch) {
+    if (real) {
       if (H->run_epochs < kEpochStamps) H->stamp[H->run_epochs] = realtime();
       H->gepoch += 1;
       H->run_epochs += 1;
     }
     int stop = 0;
-    if (ctot == 0) stop = 1;
-    else if (H->max_epochs >= 0 && H->run_epochs >= H->max_epochs) stop = 2;
-    else if (C.abort_flag && *C.abort_flag) stop = 3;
+    if (ctot == 0) {
+      stop = 1;
+      if (C.async_mode) {   // an asynchronous run drains only once the host closes it
+        const int64_t now = realtime();
+        if (H->idle_t0 == 0) H->idle_t0 = now;
+        const bool closed = __hip_atomic_load(&C.ring->close, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+        stop = closed ? 1 : (now - H->idle_t0 > C.idle_ticks ? 5 : 0);
+        // a submission published before the close request is adopted first
+        // (the host writes the tail before close, so it is visible here)
+        if ((int)(__hip_atomic_load(&C.ring->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - H->adm_head) > 0)
+          stop = 0;
+      }
+    } else {
+      H->idle_t0 = 0;
+      if (H->max_epochs >= 0 && H->run_epochs >= H->max_epochs) stop = 2;
+    }
+    if (C.abort_flag && *C.abort_flag) stop = 3;
     if (H->stop_reason == 4) stop = 4;   // a barrier timed out: stay stopped
     H->stop = stop;
     if (stop) H->stop_reason = stop;
@@ -1580,7 +1735,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   __shared__ Lds<WG> L;
   __shared__ MapL M;
   __shared__ VL V;
-  __shared__ uint32_t s_hdr[5];
+  __shared__ uint32_t s_hdr[6];
   lds_init<WG>(C, L);
   if (threadIdx.x == 0) L.tflag = 0;
   if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
@@ -1588,12 +1743,20 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   SchedHdr *H = C.hdr;
   const PlainArgs P{};
   while (true) {
-    if (threadIdx.x == 0) { s_hdr[0] = H->S; s_hdr[1] = (uint32_t)H->L; s_hdr[2] = (uint32_t)H->stop; s_hdr[3] = H->mapJ; }
+    if (threadIdx.x == 0) {
+      s_hdr[0] = H->S; s_hdr[1] = (uint32_t)H->L; s_hdr[2] = (uint32_t)H->stop; s_hdr[3] = H->mapJ;
+      s_hdr[5] = (uint32_t)H->initN;
+    }
     __syncthreads();
     const uint32_t S = s_hdr[0];
     const int32_t nL = (int32_t)s_hdr[1];
     const bool stop = s_hdr[2] != 0;
     const uint32_t mapJ = persistent ? s_hdr[3] : 0u;
+    // trees adopted by an asynchronous run's last scan: their buffers are
+    // initialised by every work-group before their roots run (also when the
+    // run stops here: they stay live for the next run)
+    const int32_t initN = persistent ? (int32_t)s_hdr[5] : 0;
+    if (initN > 0) run_inits(C, initN);
     if constexpr (kMap) {
       if (mapJ) {   // merges registered by the previous epoch: partition, barrier, merge
         uint32_t J;
@@ -1606,7 +1769,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
       }
     }
     if (stop) break;
-    if (mapJ && !grid_barrier<WG>(C, L, false, true)) break;
+    if ((mapJ || initN > 0) && !grid_barrier<WG>(C, L, false, true)) break;
     // Chunks go to work-groups in runs of consecutive chunks; within a run
     // each chunk continues where the previous one ended.  Kernels with BFS
     // (whose chunks differ in cost by orders of magnitude) claim runs from a
@@ -1699,22 +1862,7 @@ __global__ __launch_bounds__(WG) void k_scan(DevCtx C) {
 __global__ void k_admit(DevCtx C, const Admit *adm, int32_t n) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const Admit a = adm[j];
-  const int s = a.slot;
-  ((TreeStatic *)C.ts)[s] = a.ts;
-  TreeState T = {};
-  T.cen = 0; T.b = 0; T.e = 1; T.old = 1; T.sp = 0; T.status = TS_LIVE; T.err = 0;
-  T.epochs = 0; T.tasks = 1; T.launched = 0; T.result = 0; T.done_gepoch = -1;
-  T.start_gepoch = -1; T.peak = 1; T.ntrace = 0;
-  C.st[s] = T;
-  TreeHot Hh = {};
-  Hh.nfc = 1;
-  C.hot[s] = Hh;
-  C.t_len[s] = 1; C.t_cen[s] = 0; C.t_b[s] = 0;
-  const int64_t r0 = a.ts.base;
-  C.code[r0] = a.root_code;
-  C.a0[r0] = a.a0; C.a1[r0] = a.a1; C.a2[r0] = a.a2; C.a3[r0] = a.a3;
-  C.r[r0] = 0;
+  admit_one(C, adm[j]);
 }
 
 // A graph program's per-vertex array before its first epoch: 0 at the

@@ -11,10 +11,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "trees_dev.h"
@@ -245,7 +247,16 @@ struct trees_ctx {
   double clock_hz = 1e8;
   double timeout_s = 60.0;   // host and device waits give up after this long
   bool running = false;
+  // asynchronous runs (TREES_RUN_ASYNC)
   bool async_on = false;           // an asynchronous run is in flight
+  AsyncRing *ring = nullptr;       // host-mapped: ring header
+  Admit *ring_adm = nullptr;       // host-mapped: admission records [tmax]
+  Completion *ring_done = nullptr; // host-mapped: completion records [tmax]
+  uint32_t ring_tail = 0;          // admission records published in this run
+  uint32_t chead = 0;              // completion records consumed in this run
+  uint64_t async_tasks = 0;        // tasks of the trees finished in this run
+  std::chrono::steady_clock::time_point async_t0;
+  std::deque<uint64_t> finished;   // finished trees not yet reported by trees_poll
   std::string err;
   std::mutex mu;
 };
@@ -310,6 +321,61 @@ uint32_t ops_needed(trees_ctx *c) {
   return o;
 }
 
+uint64_t tree_id(const trees_ctx *c, int slot) { return ((uint64_t)c->trees[slot].gen << 32) | (uint32_t)slot; }
+
+// Stage a submission for the next trees_run, with the initialisation of the
+// program's per-vertex or log buffer that precedes the tree's first epoch.
+void stage(trees_ctx *c, const Admit &a) {
+  c->staged.push_back(a);
+  const TreeStatic &ts = a.ts;
+  switch (ts.kind) {
+    case TREES_PROG_BFS_CSR: c->depth_inits.push_back({(int32_t *)ts.ptr2, ts.p0, ts.p1, -1}); break;
+    case TREES_PROG_SSSP_CSR: c->depth_inits.push_back({(int32_t *)ts.ptr2, ts.p0, ts.p1, INT32_MAX}); break;
+    // a traversal's visit counter (log[n]) starts at zero: cleared inside
+    // trees_run, on the context's stream, after the caller's own work on it
+    case TREES_PROG_POSTORDER:
+    case TREES_PROG_PREORDER: c->depth_inits.push_back({(int32_t *)ts.ptr2 + ts.p0, 1, -1, 0}); break;
+  }
+}
+
+// Mark a tree finished (its state mirror filled) and queue it for trees_poll.
+void mark_done(trees_ctx *c, int slot) {
+  c->trees[slot].hstatus = H_DONE;
+  c->finished.push_back(tree_id(c, slot));
+  if (c->finished.size() > 2 * (size_t)c->tmax) {   // a caller that never polls: drop released ids
+    std::deque<uint64_t> keep;
+    for (uint64_t id : c->finished) {
+      const int s = (int)(uint32_t)id;
+      const HostTree &t = c->trees[s];
+      if (t.hstatus == H_DONE && t.gen == (uint32_t)(id >> 32)) keep.push_back(id);
+    }
+    c->finished.swap(keep);
+  }
+}
+
+// Consume the completion records an asynchronous run has published.
+void drain_completions(trees_ctx *c) {
+  const uint32_t ct = __atomic_load_n(&c->ring->ctail, __ATOMIC_ACQUIRE);
+  while (c->chead != ct) {
+    const Completion q = c->ring_done[c->chead % (uint32_t)c->tmax];
+    ++c->chead;
+    if (q.slot < 0 || q.slot >= c->tmax) continue;
+    HostTree &t = c->trees[q.slot];
+    if (t.hstatus != H_LIVE) continue;
+    t.st.status = TS_DONE;
+    t.st.err = q.err;
+    t.st.epochs = q.epochs;
+    t.st.peak = q.peak;
+    t.st.tasks = q.tasks;
+    t.st.launched = q.launched;
+    t.st.result = q.result;
+    t.st.start_gepoch = q.start_gepoch;
+    t.st.done_gepoch = q.done_gepoch;
+    if (q.err == 0) c->async_tasks += (uint64_t)q.tasks;
+    mark_done(c, q.slot);
+  }
+}
+
 trees_status flush_admissions(trees_ctx *c) {
   const int n = (int)c->staged.size();
   if (n) {
@@ -342,7 +408,7 @@ trees_status sync_states(trees_ctx *c) {
     HostTree &t = c->trees[s];
     if (t.hstatus != H_LIVE) continue;
     t.st = c->st_host[s];
-    if (t.st.status == TS_DONE) t.hstatus = H_DONE;
+    if (t.st.status == TS_DONE) mark_done(c, s);
   }
   return TREES_OK;
 }
@@ -506,14 +572,14 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
   HIPCHK(c, hipStreamSynchronize(c->stream));
   TRY(resolve_events(c));
   t.st = st;
-  if (done) t.hstatus = H_DONE;
+  if (done) mark_done(c, slot);
   return TREES_OK;
 }
 
 // ---------------------------------------------------------------------------
 // GRAPH / PERSISTENT: device Phases 1 and 3.
 // ---------------------------------------------------------------------------
-trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
+trees_status hdr_begin(trees_ctx *c, int64_t max_epochs, bool async = false) {
   // read-modify-write of the header's scalar part
   HIPCHK(c, hipMemcpyAsync(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -535,8 +601,16 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs) {
   c->hdr_host->arc_next = 0;
   c->hdr_host->arc_arrive = 0;
   c->hdr_host->arc_phase = 0;
+  c->hdr_host->initN = 0;
+  c->hdr_host->adm_head = 0;
+  c->hdr_host->ctail = 0;
+  c->hdr_host->idle_t0 = 0;
   HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, launch_scan(c->dc, c->stream));
+  // (the first scan of an asynchronous run does not stop on an empty work
+  // list: the run waits for submissions)
+  DevCtx d = c->dc;
+  d.async_mode = async ? 1 : 0;
+  HIPCHK(c, launch_scan(d, c->stream));
   return TREES_OK;
 }
 
@@ -606,6 +680,66 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     }
   }
   return TREES_OK;
+}
+
+// Starts an asynchronous persistent run and returns while it runs: trees
+// submitted meanwhile go through the admission ring, finished ones come back
+// through the completion ring (Section 5.2.1's root placement happens on the
+// device, at the epoch boundary after the submission).
+trees_status start_async(trees_ctx *c, int64_t max_epochs) {
+  c->ring->tail = 0;
+  c->ring->head = 0;
+  c->ring->ctail = 0;
+  c->ring->close = 0;
+  trees_status s = hdr_begin(c, max_epochs, true);
+  if (s) return s;
+  c->ring_tail = 0;
+  c->chead = 0;
+  c->async_tasks = 0;
+  // every program's kernel code, since any may be submitted during the run
+  uint32_t need = 0;
+  for (auto &p : c->progs) need |= p.ops;
+  if (!need) return fail(c, TREES_E_STATE, "asynchronous run: no program registered");
+  const int grid = grid_size(c, need, true);
+  c->last_grid = grid;
+  DevCtx d = c->dc;
+  d.async_mode = 1;
+  HIPCHK(c, launch_epochs(d, c->wg, need, grid, 1, c->stream));
+  c->async_on = true;
+  c->async_t0 = std::chrono::steady_clock::now();
+  return TREES_OK;
+}
+
+// After an asynchronous run's kernel has returned (or to make it return:
+// close = it drains first): collect its completions and the state of the
+// trees it left live; submissions it never adopted are staged for the next
+// run.
+trees_status finish_async(trees_ctx *c, bool close) {
+  if (close) __atomic_store_n(&c->ring->close, 1, __ATOMIC_RELEASE);
+  const auto t0 = std::chrono::steady_clock::now();
+  while (true) {
+    const hipError_t q = hipStreamQuery(c->stream);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady) {
+      c->async_on = false;
+      return fail(c, TREES_E_DEVICE, std::string("asynchronous run: ") + hipGetErrorString(q));
+    }
+    drain_completions(c);
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (el > 2 * c->timeout_s + 10) {
+      c->async_on = false;
+      return fail(c, TREES_E_DEVICE, "asynchronous run did not end within the time limit");
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+  c->async_on = false;
+  drain_completions(c);
+  HIPCHK(c, hipMemcpyAsync(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // records published after the kernel's last look at the ring
+  for (uint32_t k = c->hdr_host->adm_head; k != c->ring_tail; ++k) stage(c, c->ring_adm[k % (uint32_t)c->tmax]);
+  for (const Admit &a : c->staged) c->trees[a.slot].hstatus = H_STAGED;
+  return sync_states(c);
 }
 
 trees_status run_persistent(trees_ctx *c, int64_t max_epochs) {
@@ -851,7 +985,7 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
                o_wtb = take((T + 1) * 4), o_wtp = take((T + 1) * 4),
                o_dl = take(T * 4), o_lv = take(2 * T * 4), o_hdr = take(sizeof(SchedHdr)),
                o_pl = take(sizeof(PlainCounters)),
-               o_adm = take(T * sizeof(Admit));
+               o_adm = take(T * sizeof(Admit)), o_init = take(T * 4);
   const bool nomap = (cfg->flags & TREES_F_NOMAP) != 0;
   const size_t MJ = nomap ? 0 : (size_t)kMapJobs;
   const size_t PC = nomap ? 0 : (size_t)kPartCap;
@@ -884,6 +1018,7 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.hdr = (SchedHdr *)(b + o_hdr);
   c->dc.plain = (PlainCounters *)(b + o_pl);
   c->adm_dev = (Admit *)(b + o_adm);
+  c->dc.init_slot = (int32_t *)(b + o_init);
   c->dc.mj_lo = (int32_t *)(b + o_mjl);
   c->dc.mj_hi = (int32_t *)(b + o_mjh);
   c->dc.mj_src = (const uint32_t **)(b + o_mjs);
@@ -901,6 +1036,7 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.debug = (cfg->flags & TREES_F_DEBUG) ? 1 : 0;
   const double to = cfg->timeout_s > 0 ? cfg->timeout_s : 60.0;
   c->dc.timeout_ticks = (int64_t)(to * c->clock_hz);
+  c->dc.idle_ticks = (int64_t)(to * c->clock_hz);   // an idle asynchronous run ends by itself after this
   c->timeout_s = to;
   // pinned host memory
   if (hipHostMalloc((void **)&c->adm_host, T * sizeof(Admit), hipHostMallocDefault) != hipSuccess ||
@@ -914,6 +1050,24 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
           hipSuccess)
     return bail(TREES_E_NOMEM, "hipHostMalloc failed");
   memset(c->wl_mirror, 0, sizeof(WlMirror));
+  {   // asynchronous runs: ring header, admission and completion records
+    const size_t rb = sizeof(AsyncRing) + T * sizeof(Admit) + T * sizeof(Completion);
+    char *rp = nullptr;
+    if (hipHostMalloc((void **)&rp, rb, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+      return bail(TREES_E_NOMEM, "hipHostMalloc of the asynchronous rings failed");
+    memset(rp, 0, rb);
+    c->ring = (AsyncRing *)rp;
+    c->ring_adm = (Admit *)(rp + sizeof(AsyncRing));
+    c->ring_done = (Completion *)(rp + sizeof(AsyncRing) + T * sizeof(Admit));
+    char *rd = nullptr;
+    if (hipHostGetDevicePointer((void **)&rd, rp, 0) != hipSuccess)
+      return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
+    c->dc.ring = (AsyncRing *)rd;
+    c->dc.ring_adm = (const Admit *)(rd + sizeof(AsyncRing));
+    c->dc.ring_done = (Completion *)(rd + sizeof(AsyncRing) + T * sizeof(Admit));
+    c->dc.async_mode = 0;
+    c->dc.slice_ticks = (int64_t)(2e-3 * c->clock_hz);   // 2 ms of idle waiting per empty epoch
+  }
   if (hipHostGetDevicePointer((void **)&c->wl_mirror_dev, c->wl_mirror, 0) != hipSuccess)
     return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   *c->abort_flag = 0;
@@ -934,6 +1088,10 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
 
 void trees_destroy(trees_ctx *c) {
   if (!c) return;
+  if (c->async_on) {   // end the asynchronous run at its next epoch boundary
+    __atomic_store_n(&c->ring->close, 1, __ATOMIC_RELEASE);
+    __atomic_store_n(c->abort_flag, 1, __ATOMIC_SEQ_CST);
+  }
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -947,6 +1105,7 @@ void trees_destroy(trees_ctx *c) {
   if (c->r_host) (void)hipHostFree(c->r_host);
   if (c->abort_flag) (void)hipHostFree(c->abort_flag);
   if (c->wl_mirror) (void)hipHostFree(c->wl_mirror);
+  if (c->ring) (void)hipHostFree(c->ring);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1001,6 +1160,9 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
                           const trees_buf *bufs, int32_t nbufs, uint64_t *out_tree) {
   if (!c || !out_tree) return fail(c, TREES_E_INVALID, "null argument");
   std::lock_guard<std::mutex> g(c->mu);
+  // an asynchronous run that has ended by itself (idle limit, budget, abort)
+  // no longer adopts submissions: collect it, and stage this tree instead
+  if (c->async_on && hipStreamQuery(c->stream) != hipErrorNotReady) TRY(finish_async(c, false));
   if (prog < 0 || prog >= (int)c->progs.size()) return fail(c, TREES_E_INVALID, "unknown program id");
   const Prog &P = c->progs[prog];
   int64_t bound = 0;
@@ -1123,16 +1285,19 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
                          : (P.kind == TREES_PROG_SSSP_CSR && nargs >= 4) ? (uint32_t)args[3] : 0u;
   t.tp = (uint32_t)P.tbase | (param << 8);
   a.ts.tp = t.tp;
-  c->staged.push_back(a);
-  if (P.kind == TREES_PROG_BFS_CSR)
-    c->depth_inits.push_back({(int32_t *)bufs[2].ptr, (int32_t)args[0], (int32_t)args[1], -1});
-  if (P.kind == TREES_PROG_SSSP_CSR)
-    c->depth_inits.push_back({(int32_t *)bufs[3].ptr, (int32_t)args[0], (int32_t)args[1], INT32_MAX});
-  // a traversal's visit counter (log[n]) starts at zero before the tree's
-  // first epoch; it is cleared inside trees_run, on the context's stream,
-  // after the caller's own work on the buffer
-  if (P.kind == TREES_PROG_POSTORDER || P.kind == TREES_PROG_PREORDER)
-    c->depth_inits.push_back({(int32_t *)bufs[2].ptr + args[0], 1, -1, 0});
+  if (c->async_on) {
+    // publish into the admission ring: the running kernel adopts the tree at
+    // its next epoch boundary (and initialises its buffers there)
+    c->ring_adm[c->ring_tail % (uint32_t)c->tmax] = a;
+    __atomic_store_n(&c->ring->tail, c->ring_tail + 1, __ATOMIC_RELEASE);
+    c->ring_tail++;
+    t.hstatus = H_LIVE;
+    memset(&t.st, 0, sizeof(t.st));
+    t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 1; t.st.peak = 1;
+    t.st.done_gepoch = -1; t.st.start_gepoch = -1;
+  } else {
+    stage(c, a);
+  }
   c->tslots = std::max(c->tslots, slot + 1);
   c->ntrees++;
   *out_tree = ((uint64_t)t.gen << 32) | (uint32_t)slot;
@@ -1140,17 +1305,53 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
 }
 
 trees_status trees_run(trees_ctx *c, int64_t max_epochs, uint32_t flags, trees_run_stats *out) {
-  (void)flags;
   if (!c) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (flags & ~(uint32_t)TREES_RUN_ASYNC) return fail(c, TREES_E_INVALID, "unknown trees_run flags");
   auto t0 = std::chrono::steady_clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, TREES_E_DEVICE, "hipSetDevice failed");
+  if (out) memset(out, 0, sizeof(*out));
+  if (c->async_on) {
+    // a blocking call closes the asynchronous run: its kernel finishes every
+    // live and submitted tree, then returns
+    if (flags & TREES_RUN_ASYNC) return fail(c, TREES_E_STATE, "an asynchronous run is already active");
+    TRY(finish_async(c, true));
+    if (out) {
+      out->global_epochs = (uint64_t)c->hdr_host->run_epochs;
+      out->tasks = c->async_tasks;
+      out->stop_reason = c->hdr_host->stop_reason;
+      int live = 0;
+      for (int i = 0; i < c->tslots; ++i) live += c->trees[i].hstatus == H_LIVE || c->trees[i].hstatus == H_STAGED;
+      out->live = live;
+      out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - c->async_t0).count();
+      out->grid = c->last_grid;
+      out->api_blocks_per_cu = c->last_api_bpc;
+      out->sched = TREES_SCHED_PERSISTENT;
+      out->wg_size = c->wg;
+    }
+    if (c->hdr_host->stop_reason == 4) return fail(c, TREES_E_DEVICE, "persistent barrier timed out");
+    return TREES_OK;
+  }
   *(volatile int32_t *)c->abort_flag = 0;
   trees_status s = flush_admissions(c);
   if (s) return s;
   std::vector<int> before;
   for (int i = 0; i < c->tslots; ++i)
     if (c->trees[i].hstatus == H_LIVE) before.push_back(i);
+  if (flags & TREES_RUN_ASYNC) {
+    if (c->sched != TREES_SCHED_PERSISTENT && c->sched != TREES_SCHED_AUTO)
+      return fail(c, TREES_E_INVALID, "an asynchronous run needs the PERSISTENT (or AUTO) scheduler");
+    TRY(start_async(c, max_epochs));
+    if (out) {
+      out->live = (int32_t)before.size();
+      out->grid = c->last_grid;
+      out->api_blocks_per_cu = c->last_api_bpc;
+      out->sched = TREES_SCHED_PERSISTENT;
+      out->wg_size = c->wg;
+      out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return TREES_OK;
+  }
   uint64_t gepochs = 0;
   int32_t stop_reason = 1;
   // AUTO: the shape the tuner chose for this device and workload class (read
@@ -1205,12 +1406,22 @@ static HostTree *find_tree(trees_ctx *c, uint64_t id, int *slot) {
   return &t;
 }
 
+// While an asynchronous run is active: take in its completions, and collect
+// the run if its kernel has ended by itself.
+static trees_status async_progress(trees_ctx *c) {
+  if (!c->async_on) return TREES_OK;
+  drain_completions(c);
+  if (hipStreamQuery(c->stream) != hipErrorNotReady) return finish_async(c, false);
+  return TREES_OK;
+}
+
 trees_status trees_results(trees_ctx *c, uint64_t tree, int64_t *out_value, trees_tree_stats *out) {
   if (!c) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
   int slot;
   HostTree *t = find_tree(c, tree, &slot);
   if (!t) return fail(c, TREES_E_INVALID, "unknown tree id");
+  if (t->hstatus == H_LIVE) TRY(async_progress(c));
   if (t->hstatus != H_DONE) {
     if (out) { memset(out, 0, sizeof(*out)); out->status = TREES_E_PENDING; }
     return TREES_E_PENDING;
@@ -1234,9 +1445,28 @@ trees_status trees_results(trees_ctx *c, uint64_t tree, int64_t *out_value, tree
   return rc;
 }
 
+trees_status trees_poll(trees_ctx *c, uint64_t *ids, int32_t cap, int32_t *n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !ids)) return TREES_E_INVALID;
+  std::lock_guard<std::mutex> g(c->mu);
+  *n = 0;
+  TRY(async_progress(c));
+  int k = 0;
+  while (k < cap && !c->finished.empty()) {
+    const uint64_t id = c->finished.front();
+    c->finished.pop_front();
+    int slot;
+    HostTree *t = find_tree(c, id, &slot);
+    if (!t || t->hstatus != H_DONE) continue;   // already released by trees_results
+    ids[k++] = id;
+  }
+  *n = k;
+  return TREES_OK;
+}
+
 trees_status trees_trace(trees_ctx *c, uint64_t tree, trees_epoch_rec *out, int32_t cap, int32_t *n) {
   if (!c || !n) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (c->async_on) return fail(c, TREES_E_STATE, "trees_trace: an asynchronous run is active");
   int slot;
   HostTree *t = find_tree(c, tree, &slot);
   if (!t) return fail(c, TREES_E_INVALID, "unknown tree id");
@@ -1259,6 +1489,7 @@ trees_status trees_abort(trees_ctx *c) {
 trees_status trees_set_schedule(trees_ctx *c, int32_t sched, int32_t wg, int32_t bpc, int32_t chunk) {
   if (!c) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (c->async_on) return fail(c, TREES_E_STATE, "trees_set_schedule: an asynchronous run is active");
   if (sched < 0 || sched > TREES_SCHED_AUTO) return fail(c, TREES_E_INVALID, "bad scheduler");
   if (wg && wg != 256 && wg != 512 && wg != 1024) return fail(c, TREES_E_INVALID, "bad wg_size");
   c->sched = sched;
@@ -1292,6 +1523,7 @@ trees_status trees_kernel_times(trees_ctx *c, trees_ktime *out, int32_t n) {
 trees_status trees_debug_phases(trees_ctx *c, double *us, int32_t n) {
   if (!c || !us) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (c->async_on) return fail(c, TREES_E_STATE, "trees_debug_phases: an asynchronous run is active");
   HIPCHK(c, hipMemcpy(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost));
   for (int k = 0; k < n && k < 8; ++k) us[k] = (double)c->hdr_host->phase[k] * 1e6 / c->clock_hz;
   return TREES_OK;
@@ -1300,6 +1532,7 @@ trees_status trees_debug_phases(trees_ctx *c, double *us, int32_t n) {
 trees_status trees_epoch_times(trees_ctx *c, double *us, int32_t cap, int32_t *n) {
   if (!c || !n) return TREES_E_INVALID;
   std::lock_guard<std::mutex> g(c->mu);
+  if (c->async_on) return fail(c, TREES_E_STATE, "trees_epoch_times: an asynchronous run is active");
   HIPCHK(c, hipMemcpy(c->hdr_host, c->dc.hdr, sizeof(SchedHdr), hipMemcpyDeviceToHost));
   const int ne = (int)std::min<int64_t>(c->hdr_host->run_epochs, kEpochStamps);
   int64_t prev = c->hdr_host->stamp0;

@@ -117,7 +117,12 @@ struct SchedHdr {
   int32_t stop_reason;  // 1 = drained, 2 = epoch budget, 3 = abort, 4 = timeout
   int32_t tslots;       // slots [0, tslots) may hold trees
   uint32_t mapJ;        // map jobs registered by the last epoch (raw count)
-  int32_t pad0[14];
+  int32_t initN;        // asynchronous run: adopted trees whose buffers the next epoch initialises
+  uint32_t adm_head;    // asynchronous run: admission records adopted so far
+  uint32_t ctail;       // asynchronous run: completion records published so far
+  int32_t pad9;
+  int64_t idle_t0;      // asynchronous run: device clock when no tree was left live (0: busy)
+  int32_t pad0[8];
   alignas(128) uint32_t arrive;   // barrier arrivals of the last work-group of each group
   int32_t pad1[31];
   struct alignas(128) Grp { uint32_t n; int32_t pad[31]; } grp[8];   // per-group arrivals (blockIdx % 8)
@@ -204,6 +209,35 @@ struct PlainMirror {
   uint32_t pad;
 };
 
+// ---------------------------------------------------------------------------
+// Asynchronous runs (TREES_RUN_ASYNC): trees submitted while a persistent
+// run is in flight arrive through an admission ring in host-mapped memory,
+// and finished trees leave through a completion ring beside it.  Each ring
+// has one slot per tree slot, so neither can overflow: a record is written
+// only for a tree slot that is in use, and a slot is reused only after the
+// host has consumed its completion.
+// ---------------------------------------------------------------------------
+struct Completion {
+  int32_t slot, err, epochs, peak;
+  int64_t tasks, launched, result, start_gepoch, done_gepoch;
+  int64_t pad;
+};
+
+struct alignas(64) AsyncRing {
+  uint32_t tail;        // host: admission records published
+  uint32_t head;        // device: admission records adopted (for the host's information)
+  uint32_t ctail;       // device: completion records published
+  int32_t close;        // host: end the run once no tree is live and nothing waits
+  int32_t pad[12];
+};
+
+// One staged submission, applied on the device by the admission kernel
+// (or, in an asynchronous run, adopted from the admission ring).
+struct Admit {
+  int32_t slot, root_code, a0, a1, a2, a3;
+  TreeStatic ts;
+};
+
 // Everything a kernel needs, passed by value.
 struct DevCtx {
   int32_t *code, *a0, *a1, *a2, *a3;
@@ -246,14 +280,18 @@ struct DevCtx {
   int32_t *arc_item;              // [kArcJobs * kArcItemWords]
   int32_t *arc_seg;               // [7 * kArcSegPool]: the segment record planes
   int4 *arc_tile;                 // [kArcTilesAll]: {job, first item, last item, -}
+  // asynchronous runs (async_mode != 0 only in the persistent launch of one)
+  AsyncRing *ring;                // device address of the host-mapped ring header
+  const Admit *ring_adm;          // [tmax] admission records (host-mapped)
+  Completion *ring_done;          // [tmax] completion records (host-mapped)
+  int32_t *init_slot;             // [tmax] adopted trees whose buffers need initialising
+  int32_t async_mode;
+  int32_t pad4;
+  int64_t slice_ticks;            // idle wait for a submission before an empty epoch
+  int64_t idle_ticks;             // idle time after which the run ends by itself
   uint8_t op_of_type[kMaxTypes + 1];
 };
 
-// One staged submission, applied on the device by the admission kernel.
-struct Admit {
-  int32_t slot, root_code, a0, a1, a2, a3;
-  TreeStatic ts;
-};
 
 // Arguments of one plain-scheduler epoch (one tree, host-driven).
 struct PlainArgs {
