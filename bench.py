@@ -11,11 +11,18 @@ under the plain scheduler (one launch per epoch, Phases 1 and 3 on the host).
 Inputs are resident in HBM before the timed region; every step sorts its own
 fresh copy of the keys.
 
-Prints one JSON line: tasks/s over the whole step (the metric), epochs/s,
-the roofline of the dominant epoch kernel (algorithmic bytes / HIP-event
-kernel time, against 8 TB/s HBM), and the CPU oracle timed on this host.
+Prints one JSON line: tasks/s over the whole step (the metric, timed without
+per-launch events), epochs/s, the roofline of the dominant kernel and of the
+epoch kernel (algorithmic bytes / HIP-event kernel time, against 8 TB/s HBM),
+the CPU oracle timed on this host, and the rest of the metric measured in
+the same run, each checked against the oracle: the 4096-tree batch (graph
+and persistent forms vs one tree at a time under the plain scheduler, with
+the batched epoch kernel's task-vector roofline), the 64-graph R-MAT BFS
+batch beside the native worklist BFS, and serving latency (p50/p99 at 50%
+and 80% of saturation).
 
     python bench.py [--steps K] [--warmup W] [--config 2|1|3|4|5|6|7|8] [--sched plain|graph|persistent]
+                    [--no-blocks] [--no-cpu] [--no-compare]
 """
 from __future__ import annotations
 
@@ -29,6 +36,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    """A progress line on stderr (the JSON line is stdout's only output)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 # HBM bytes per launch of a kernel as rocprofv3 counted them (FETCH_SIZE and
 # WRITE_SIZE, each in its own run, scaled by what the same counters read for
@@ -287,29 +299,44 @@ def bench_cfg2(args):
     }
     per = {k: dict(ms=kt[kinds[k]][0], launches=kt[kinds[k]][1], bytes=per_step_bytes[k][0],
                    tv=per_step_bytes[k][1]) for k in kinds}
-    # The merge pass holds the largest share of device time (rocprofv3 kernel
-    # trace of this step); its launches are the ones the roofline covers.
-    dom = "k_map_merge<1024,8192>"
+    # the dominant kernel: the largest share of device time in the breakdown
+    # step (every launch timed)
+    dom = max(per, key=lambda k: per[k]["ms"])
+    epk = "k_plain<FIB>"   # the epoch kernel of the step's largest tree
 
-    # The measurement: only the dominant kernel's launches carry events.
+    # The throughput: steps with no per-launch events (an event pair costs
+    # host time per launch, and the plain scheduler's loop is host-driven).
     r = run_cfg2(args, args.sched, args.steps, args.warmup, key_bufs=key_bufs, keys_np=keys_np,
-                 timed_kinds=[kinds[dom]])
-    dt, outs, ktl = r["dt"], r["outs"], r["kt"]
+                 timed_kinds=[])
+    dt, outs = r["dt"], r["outs"]
     vf, sf, sm, rs = outs[-1]
     tasks = sf.tasks + sm.tasks
     epochs = sf.epochs + sm.epochs
     ms_step = dt * 1e3 / args.steps
-    d = dict(ms=ktl[kinds[dom]][0], launches=ktl[kinds[dom]][1], bytes=per[dom]["bytes"] * args.steps)
-    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic_for(dom, d["launches"] and
-                                                                              d["bytes"] // d["launches"]),
-            "kernel": dom, "launches": d["launches"],
-            "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 3),
-            "algorithmic_bytes_per_launch": int(d["bytes"] / max(1, d["launches"])),
-            "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (profiles/plain_fib32_msort2e24.md)"}
+    # The roofline: the same steps again, events on the dominant kernel's and
+    # the epoch kernel's launches only (HIP events on the launching stream)
+    rr = run_cfg2(args, args.sched, args.steps, 0, key_bufs=key_bufs, keys_np=keys_np,
+                  timed_kinds=sorted({kinds[dom], kinds[epk]}))
+    ktl = rr["kt"]
+
+    def roof_of(k, what):
+        d = dict(ms=ktl[kinds[k]][0], launches=ktl[kinds[k]][1], bytes=per[k]["bytes" if what == "all" else "tv"]
+                 * args.steps)
+        a = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+        return {"bound": "hbm", "achieved": round(a, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(a / HBM_PEAK_GBS, 6),
+                "traffic": traffic_for(k, d["launches"] and d["bytes"] // d["launches"]),
+                "kernel": k, "launches": d["launches"],
+                "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 3),
+                "algorithmic_bytes_per_launch": int(d["bytes"] / max(1, d["launches"])),
+                "timed_steps": args.steps}
+    roof = roof_of(dom, "all")
+    roof["dominant_from"] = "largest summed HIP-event kernel time per step over all launches of the step"
+    roof["traffic_from"] = "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (profiles/plain_fib32_msort2e24.md)"
     sp = stream_peak(4 * N)
-    roof["achievable"] = {**sp, "frac": round(achieved / sp["GBps"], 4)}
+    roof["achievable"] = {**sp, "frac": round(roof["achieved"] / sp["GBps"], 4)}
+    roof_ep = roof_of(epk, "tv")
+    roof_ep["what"] = "task-vector bytes of fib(32)'s tasks (D3) over its epoch launches' kernel time"
     kernels = {k: {"ms_per_step": round(v["ms"], 3),
                    "launches_per_step": v["launches"],
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2) if v["ms"] else None,
@@ -325,6 +352,7 @@ def bench_cfg2(args):
         "epochs_per_s": epochs / (dt / args.steps),
         "kernels": kernels,
         "roofline": roof,
+        "roofline_epoch_kernel": roof_ep,
     }
     if args.compare:
         alt = {}
@@ -340,46 +368,43 @@ def bench_cfg2(args):
     return line
 
 
-def bench_cfg3(args):
-    """4096 independent trees (half fib(10..28), half N-queens(6..11)) in
-    shared epochs: persistent and graph forms, and the same trees one at a
-    time under the plain scheduler."""
-    import oracle
+def batch_block(ntrees: int = 4096, wg: int = 512, reps: int = 3, plain_subset: int = 512, tune: bool = False):
+    """The batched configuration: `ntrees` independent trees (half fib(10..28),
+    half N-queens(6..11), seeded random order) in shared epochs, under the
+    graph and persistent forms; the first `plain_subset` of them also one at
+    a time under the plain scheduler and batched, for the batched-vs-plain
+    factor on the same trees.  Every tree checked against its oracle run.
+    The roofline is the batched epoch kernel's: algorithmic task-vector
+    bytes of the whole batch over its summed kernel time (HIP events around
+    each graph replay or the persistent launch)."""
+    import numpy as np
     import torch
 
     import inputs
+    import oracle
     import paper_1608_00571_amd as T
 
-    mix = inputs.batch_mix(args.trees)
+    mix = inputs.batch_mix(ntrees)
     kinds = [(T.FIB_I64 if k == "fib" else T.NQUEENS, n) for k, n in mix]
-    # expected per-tree results and statistics (oracle emulation per distinct tree)
     expect = {}
     for kind, n in set(kinds):
         r = oracle.fib(n) if kind == T.FIB_I64 else oracle.nqueens(n)
         expect[(kind, n)] = (r.result, r.tasks, r.epochs, r.peak, r.launched)
     nq = {n: nqueens_shape(n) for kind, n in set(kinds) if kind == T.NQUEENS}
-    tv_bytes = 0
-    for kind, n in kinds:
-        res, tasks, epochs, peak, launched = expect[(kind, n)]
-        if kind == T.FIB_I64:
-            tv_bytes += fib_bytes(n, launched, tasks)["tv"]
-        else:
-            tv_bytes += nq[n][2] + 4 * (launched - tasks)
+
+    def tv_of(ks):
+        tv = 0
+        for kind, n in ks:
+            res, tasks, epochs, peak, launched = expect[(kind, n)]
+            tv += fib_bytes(n, launched, tasks)["tv"] if kind == T.FIB_I64 else nq[n][2] + 4 * (launched - tasks)
+        return tv
+    tv_bytes = tv_of(kinds)
     total_tasks = sum(expect[k][1] for k in kinds)
     arena = (sum(T.tv_bound(k, [n]) + 64 for k, n in kinds) + 4096) * T.BYTES_PER_ENTRY
 
-    def run(sched, wg, bpc=0, chunk=8, steps=1, warmup=1, subset=None):
-        ks = kinds if subset is None else kinds[:subset]
-        ctx = T.Context(arena, sched=sched, wg=wg, blocks_per_cu=bpc, graph_chunk=chunk, profile=True,
-                        max_trees=len(ks))
-        try:
-            return run_in(ctx, sched, ks, steps, warmup)
-        finally:
-            ctx.close()
-
     def run_in(ctx, sched, ks, steps, warmup):
         pf, pq = ctx.register(T.FIB_I64), ctx.register(T.NQUEENS)
-        times, gep = [], 0
+        times = []
         for it in range(warmup + steps):
             ids = [ctx.submit(pf if k == T.FIB_I64 else pq, [n]) for k, n in ks]
             torch.cuda.synchronize()
@@ -396,71 +421,91 @@ def bench_cfg3(args):
                 kms = sum(kt1[x][0] - kt0[x][0] for x in kt1)
                 et = ctx.epoch_times() if sched != "plain" else None
                 times.append((dt, kms, rs, et))
-        dt = min(t[0] for t in times)
-        kms = min(t[1] for t in times)
-        return dict(dt=dt, kernel_ms=kms, rs=times[0][2], et=times[0][3])
+        b = min(times, key=lambda t: t[0])
+        return dict(dt=b[0], kernel_ms=min(t[1] for t in times), rs=b[2], et=b[3])
 
-    out = {}
-    # autotune scheduler x work-group size x work-groups per CU x graph chunk
-    from paper_1608_00571_amd import autotune
+    def run(sched, wg_, bpc=0, chunk=8, steps=1, warmup=1, subset=None, timed=True):
+        ks = kinds if subset is None else kinds[:subset]
+        ctx = T.Context(arena, sched=sched, wg=wg_, blocks_per_cu=bpc, graph_chunk=chunk, profile=True,
+                        max_trees=len(ks))
+        if not timed:
+            ctx.profile_mask([])
+        try:
+            return run_in(ctx, sched, ks, steps, warmup)
+        finally:
+            ctx.close()
+
+    out = {"workload": f"{len(kinds)} trees: fib(10..28) int64 + nqueens(6..11), shared epochs",
+           "tasks": total_tasks, "tv_bytes": tv_bytes, "wg": wg}
     tuned = None
-    if args.tune:
+    if tune:
+        from paper_1608_00571_amd import autotune
         tctx = T.Context(arena, sched="graph", profile=True, max_trees=len(kinds))
+        tctx.register(T.FIB_I64)
+        tctx.register(T.NQUEENS)
 
         def measure(shape):
             shape.apply(tctx)
             return run_in(tctx, shape.sched, kinds, 1, 0)["dt"]
         tuned, table = autotune.tune(measure, autotune.candidates(bpcs=(0, 2, 3, 4, 6, 8), chunks=(8, 16)),
-                                     torch.cuda.get_device_name(0), f"batch{len(kinds)}", use_cache=False)
+                                     torch.cuda.get_device_name(0), f"batch{len(kinds)}", use_cache=False,
+                                     wclass=tctx.workload_class)
         tctx.close()
         out["autotune_top5"] = [{**s.__dict__, "ms": round(t * 1e3, 3)} for s, t in table[:5]]
-    shapes = [("persistent", args.wg, 0, 8), ("graph", args.wg, 0, 8)]
+    shapes = [("graph", wg, 0, 8), ("persistent", wg, 0, 8)]
     if tuned is not None:
         shapes.insert(0, (tuned.sched, tuned.wg, tuned.blocks_per_cu, tuned.graph_chunk))
-    for i, (sched, wg, bpc, ch) in enumerate(shapes):
-        r = run(sched, wg, bpc, ch, steps=args.steps, warmup=args.warmup)
-        if i == 0 and tuned is not None:
-            sched = f"tuned:{sched}/wg{wg}/bpc{bpc}/chunk{ch}"
-        out[sched] = {"tasks_per_s": total_tasks / r["dt"], "ms": round(r["dt"] * 1e3, 3),
-                      "kernel_ms": round(r["kernel_ms"], 3), "global_epochs": r["rs"].global_epochs,
-                      "grid": r["rs"].grid,
-                      "tv_GBps_kernel": round(tv_bytes / (r["kernel_ms"] * 1e-3) / 1e9, 1)}
-        et = r["et"]
+    forms = {}
+    for i, (sched, wg_, bpc, ch) in enumerate(shapes):
+        # wall time without per-launch events, kernel time from an identical timed run with them
+        rw = run(sched, wg_, bpc, ch, steps=reps, warmup=1, timed=False)
+        rk = run(sched, wg_, bpc, ch, steps=reps, warmup=0, timed=True)
+        name = f"tuned:{sched}/wg{wg_}/bpc{bpc}/chunk{ch}" if (i == 0 and tuned is not None) else sched
+        f = {"tasks_per_s": total_tasks / rw["dt"], "ms": round(rw["dt"] * 1e3, 3),
+             "kernel_ms": round(rk["kernel_ms"], 3), "global_epochs": rw["rs"].global_epochs,
+             "epochs_per_s": rw["rs"].global_epochs / rw["dt"], "grid": rw["rs"].grid,
+             "tv_GBps_kernel": round(tv_bytes / (rk["kernel_ms"] * 1e-3) / 1e9, 1)}
+        et = rk["et"]
         if et is not None and len(et):
-            import numpy as np
-            out[sched]["epoch_us"] = {"min": round(float(np.min(et)), 2), "median": round(float(np.median(et)), 2),
-                                      "max": round(float(np.max(et)), 2),
-                                      "narrow_epochs_median": round(float(np.median(np.sort(et)[:10])), 2)}
-    best = max((k for k in out if "tasks_per_s" in out[k]), key=lambda k: out[k]["tasks_per_s"])
-    # plain: the same trees one after another, one launch per epoch
-    sub = args.plain_subset
-    rp = run("plain", args.wg, steps=1, warmup=0, subset=sub)
+            f["epoch_us"] = {"min": round(float(np.min(et)), 2), "median": round(float(np.median(et)), 2),
+                             "max": round(float(np.max(et)), 2),
+                             "narrow_epochs_median": round(float(np.median(np.sort(et)[:10])), 2)}
+        forms[name] = f
+    out["forms"] = forms
+    best = max(forms, key=lambda k: forms[k]["tasks_per_s"])
+    out["best"] = best
+    # the same first `plain_subset` trees: one at a time (plain) and batched
+    sub = min(plain_subset, len(kinds))
     sub_tasks = sum(expect[k][1] for k in kinds[:sub])
-    out["plain_one_at_a_time"] = {"tasks_per_s": sub_tasks / rp["dt"], "trees": sub, "ms": round(rp["dt"] * 1e3, 1)}
-    factor = out[best]["tasks_per_s"] / out["plain_one_at_a_time"]["tasks_per_s"]
-    ach = tv_bytes / (out[best]["kernel_ms"] * 1e-3) / 1e9
-    m = MEASURED_TRAFFIC["k_epochs<FIB|NQ>"]
-    traffic3 = traffic_for("k_epochs<FIB|NQ>", tv_bytes) if f"wg{m['wg']}/" in best else None
-    line = {
-        "metric": "tasks/s", "value": out[best]["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[best]["ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+int32",
-        "data": "synthetic",
-        "config": {"workload": f"{len(kinds)} trees: fib(10..28) int64 + nqueens(6..11), shared epochs",
-                   "sched": best, "wg": args.wg, "tasks": total_tasks, "tv_bytes": tv_bytes},
-        "epochs_per_s": out[best]["global_epochs"] / (out[best]["ms"] * 1e-3),
-        "schedulers": out,
-        "batched_vs_plain_factor": round(factor, 2),
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic3,
-                     "kernel": f"k_epochs<FIB|NQ> ({best})",
-                     "algorithmic_bytes_per_run": tv_bytes,
-                     "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE per run, work-groups of 512 "
-                                     "(profiles/batched_4096trees_fib_nqueens.md)"},
-    }
-    sp = stream_peak(1 << 30)
-    line["roofline"]["achievable"] = {**sp, "frac": round(ach / sp["GBps"], 4)}
-    return line
+    rp = run("plain", 1024, steps=1, warmup=0, subset=sub, timed=False)
+    bsched = forms[best]
+    rb = run(best.split(":")[-1].split("/")[0], wg, steps=reps, warmup=1, subset=sub, timed=False)
+    out["same_trees"] = {"trees": sub, "tasks": sub_tasks,
+                         "plain_one_at_a_time": {"tasks_per_s": sub_tasks / rp["dt"], "ms": round(rp["dt"] * 1e3, 2),
+                                                 "wg": 1024},
+                         "batched": {"tasks_per_s": sub_tasks / rb["dt"], "ms": round(rb["dt"] * 1e3, 3)}}
+    out["batched_vs_plain_factor"] = round(rp["dt"] / rb["dt"], 2)
+    ach = tv_bytes / (bsched["kernel_ms"] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": f"k_epochs<FIB|NQ> ({best}, wg {wg})",
+                       "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_run": tv_bytes,
+                       "traffic": traffic_for("k_epochs<FIB|NQ>", tv_bytes),
+                       "what": "task-vector bytes each task must move (D3) over the summed kernel time"}
+    out["checked"] = "every tree's result, tasks, epochs, peak and lanes against its oracle run"
+    return out
+
+
+def bench_cfg3(args):
+    """The batched configuration as its own line (see batch_block)."""
+    blk = batch_block(args.trees, args.wg if args.wg != 256 else 512, max(1, args.steps), args.plain_subset,
+                      args.tune)
+    b = blk["forms"][blk["best"]]
+    return {"metric": "tasks/s", "value": b["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
+            "steps": max(1, args.steps), "warmup": 1, "ms_per_step": b["ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+int32",
+            "data": "synthetic",
+            "config": {"workload": blk["workload"], "sched": blk["best"], "wg": blk["wg"]},
+            "epochs_per_s": b["epochs_per_s"], "batch": blk, "roofline": blk["roofline"]}
 
 
 def bench_cfg1(args):
@@ -500,84 +545,156 @@ def bench_cfg1(args):
             "launch_readback_us_per_epoch": round(dt * 1e6 / 39 - kms * 1e3 / 39, 2)}
 
 
-def bench_cfg4(args):
-    """64 R-MAT graphs (scale uniform in [16, 22], E = 16 V), one BFS tree
-    each, in shared epochs; depths checked against the oracle's queue BFS."""
-    import numpy as np
+def bfs_graphs(ngraphs: int = 64, workers: int = 16):
+    """The BFS batch's R-MAT graphs (scale 16..22, E = 16 V) on the host and
+    the device, and the oracle's queue-BFS depths of each (both generated in
+    parallel threads: the C routines release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
 
     import inputs
     import oracle
+    scales = inputs.bfs_batch_scales(ngraphs)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        gs = list(ex.map(lambda a: inputs.bfs_batch_graph(*a), list(enumerate(scales))))
+    gen_s = time.perf_counter() - t0
+    dev = [(torch.from_numpy(G.row_ptr).to("cuda"), torch.from_numpy(G.col_idx).to("cuda"),
+            torch.empty(G.V, dtype=torch.int32, device="cuda")) for G in gs]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        want = list(ex.map(lambda G: oracle.bfs_queue(G.V, G.row_ptr, G.col_idx, G.source), gs))
+    orc_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    return gs, dev, want, {"generate": round(gen_s, 1), "oracle_bfs": round(orc_s, 1)}
+
+
+def bfs_block(ngraphs: int = 64, wg: int = 512, reps: int = 3, scheds=("graph", "persistent", "plain"),
+              worklist: bool = True, graphs=None):
+    """The batched graph configuration: 64 BFS trees (one per R-MAT graph,
+    scale 16..22) in shared epochs, and, as the paper's comparison (Section
+    6.3), the native worklist BFS on each graph one after another, beside
+    TREES' plain scheduler on each graph one after another.  Depths checked
+    against the oracle's queue BFS in every run."""
+    import numpy as np
+    import torch
+
     import paper_1608_00571_amd as T
 
-    scales = inputs.bfs_batch_scales(args.graphs)
-    t0 = time.perf_counter()
-    gs, dev = [], []
-    for g, sc in enumerate(scales):
-        G = inputs.bfs_batch_graph(g, sc)
-        rp = torch.from_numpy(G.row_ptr).to("cuda")
-        ci = torch.from_numpy(G.col_idx).to("cuda")
-        d = torch.empty(G.V, dtype=torch.int32, device="cuda")
-        gs.append(G)
-        dev.append((rp, ci, d))
-    gen_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    want = [oracle.bfs_queue(G.V, G.row_ptr, G.col_idx, G.source) for G in gs]
-    orc_s = time.perf_counter() - t0
+    gs, dev, want, setup = graphs if graphs is not None else bfs_graphs(ngraphs)
     V = sum(G.V for G in gs)
     E = sum(G.E for G in gs)
-    # arcs scanned = out-degree summed over reached vertices; algorithmic bytes per VISIT
     scanned = sum(int(np.diff(G.row_ptr)[w >= 0].sum()) for G, w in zip(gs, want))
     reached = sum(int((w >= 0).sum()) for w in want)
-    max_depth = max(int(w.max()) for w in want)
-    tv = 12 * reached + 8 * reached            # VISIT entry + the child entry that created it
-    payload = 8 * reached + 8 * scanned + 4 * reached   # row_ptr pair, col + depth probe per arc, claim
+    # algorithmic bytes of the batch: per reached vertex its VISIT entry (code,
+    # a0 read; code written) and the child entry that created it; its row_ptr
+    # pair; per arc of a reached vertex the head and its depth probe; per claim
+    # the depth written
+    tv = 12 * reached + 8 * reached
+    payload = 8 * reached + 8 * scanned + 4 * reached
     arena = (V + 64 * len(gs) + 4096) * T.BYTES_PER_ENTRY
-    out = {}
-    for sched in args.scheds.split(","):
-        ctx = T.Context(arena, sched=sched, wg=args.wg, profile=True, max_trees=len(gs))
+
+    def check(stats):
+        for (G, b, w, st) in zip(gs, dev, want, stats):
+            assert np.array_equal(b[2].cpu().numpy(), w), "BFS depths differ from the queue BFS"
+            assert st.tasks == int((w >= 0).sum()) and st.epochs == int(w.max()) + 1
+
+    out = {"workload": f"{len(gs)} R-MAT BFS trees, scale 16..22, E=16V (0.57,0.19,0.19,0.05)",
+           "V": V, "E": E, "reached": reached, "arcs_scanned": scanned, "wg": wg, "setup_s": setup}
+    forms = {}
+    for sched in scheds:
+        ctx = T.Context(arena, sched=sched, wg=wg if sched != "plain" else wg, profile=True, max_trees=len(gs))
+        ctx.profile_mask([])
         p = ctx.register(T.BFS_CSR)
         best = None
-        for it in range(args.warmup + args.steps):
-            ids = [ctx.submit(p, [G.V, G.source], list(b)) for G, b in zip(gs, dev)]
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            rs = ctx.run()
-            dt = time.perf_counter() - t1
-            stats = [ctx.results(t)[1] for t in ids]
-            for (G, b, w, st) in zip(gs, dev, want, stats):
-                assert np.array_equal(b[2].cpu().numpy(), w), "BFS depths differ from the queue BFS"
-                assert st.tasks == int((w >= 0).sum()) and st.epochs == int(w.max()) + 1
-            if it >= args.warmup and (best is None or dt < best[0]):
-                best = (dt, rs, ctx.epoch_times() if sched != "plain" else None)
+        per_graph = None
+        n_it = 1 + (reps if sched != "plain" else 1)
+        for it in range(n_it):
+            if sched == "plain":   # one graph at a time: a run per graph
+                times = []
+                stats = []
+                for G, b in zip(gs, dev):
+                    t = ctx.submit(p, [G.V, G.source], list(b))
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    ctx.run()
+                    times.append(time.perf_counter() - t1)
+                    stats.append(ctx.results(t)[1])
+                dt = sum(times)
+                rs = None
+            else:
+                ids = [ctx.submit(p, [G.V, G.source], list(b)) for G, b in zip(gs, dev)]
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rs = ctx.run()
+                dt = time.perf_counter() - t1
+                stats = [ctx.results(t)[1] for t in ids]
+                times = None
+            check(stats)
+            if it >= 1 or sched == "plain":
+                if best is None or dt < best[0]:
+                    best = (dt, rs, ctx.epoch_times() if sched != "plain" else None)
+                    per_graph = times
         ctx.close()
         dt, rs, et = best
-        out[sched] = {"vertices_per_s": reached / dt, "edges_per_s": scanned / dt, "ms": round(dt * 1e3, 3),
-                      "global_epochs": rs.global_epochs, "GBps_tv_payload": round((tv + payload) / dt / 1e9, 1)}
+        forms[sched] = {"vertices_per_s": reached / dt, "edges_per_s": scanned / dt, "ms": round(dt * 1e3, 3)}
+        if rs is not None:
+            forms[sched]["global_epochs"] = rs.global_epochs
+            forms[sched]["epochs_per_s"] = rs.global_epochs / dt
         if et is not None and len(et):
-            out[sched]["epoch_us"] = [round(float(x), 1) for x in et]
-    best = max(out, key=lambda k: out[k]["vertices_per_s"])
-    b = out[best]
+            forms[sched]["epoch_us"] = [round(float(x), 1) for x in et]
+        if per_graph is not None:
+            forms[sched]["per_graph_ms"] = [round(x * 1e3, 3) for x in per_graph]
+    out["forms"] = forms
+    best = max((k for k in forms if k != "plain"), key=lambda k: forms[k]["vertices_per_s"])
+    out["best"] = best
+    if worklist:   # the native worklist BFS, one graph after another
+        ctx = T.Context(1 << 20, sched="plain", wg=wg)
+        ws = torch.empty(T.wl_workspace_bytes(max(G.V for G in gs)), dtype=torch.uint8, device="cuda")
+        wl_best = None
+        for it in range(2):
+            times, iters = [], 0
+            for G, b, w in zip(gs, dev, want):
+                st = ctx.wl_bfs(G.V, G.source, b[0], b[1], b[2], ws)
+                assert np.array_equal(b[2].cpu().numpy(), w), "worklist BFS depths differ from the queue BFS"
+                assert st.iterations == int(w.max()) + 1
+                times.append(st.seconds)
+                iters += st.iterations
+            if wl_best is None or sum(times) < sum(wl_best[0]):
+                wl_best = (times, iters)
+        ctx.close()
+        wt = sum(wl_best[0])
+        out["worklist"] = {"ms": round(wt * 1e3, 3), "vertices_per_s": reached / wt, "iterations": wl_best[1],
+                           "per_graph_ms": [round(x * 1e3, 3) for x in wl_best[0]],
+                           "trees_plain_over_worklist": round(forms["plain"]["ms"] / (wt * 1e3), 4)
+                           if "plain" in forms else None,
+                           "trees_batched_over_worklist": round(forms[best]["ms"] / (wt * 1e3), 4),
+                           "note": "times are host wall per graph (launches, per-iteration count readback); "
+                                   "the paper reports TREES within 6% of LonestarGPU's bfs on its APU"}
+    b = forms[best]
     ach = (tv + payload) / (b["ms"] * 1e-3) / 1e9
-    amp = (tv + payload + 60 * scanned) / (b["ms"] * 1e-3) / 1e9   # a depth probe moves a 64-B sector
-    m = MEASURED_TRAFFIC["k_epochs<GRAPH> bfs"]
-    traffic = traffic_for("k_epochs<GRAPH> bfs", 0) if (best == "graph" and args.wg == m["wg"]) else None
+    lines = (tv + payload + 60 * scanned) / (b["ms"] * 1e-3) / 1e9   # a depth probe moves a 64-B sector
+    out["roofline"] = {"bound": "hbm", "kernel": f"k_epochs<GRAPH> + k_arcs ({best}, wg {wg})",
+                       "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 4), "tv_bytes": tv, "payload_bytes": payload,
+                       "what": "algorithmic bytes (task-vector + graph payload) over the run's wall time",
+                       "waste": {"note": "random 4-B depth probes move whole 64-B sectors",
+                                 "line_traffic_GBps": round(lines, 1)}}
+    out["checked"] = "every depth against the oracle's queue BFS; tasks = reached, epochs = max depth + 1"
+    return out
+
+
+def bench_cfg4(args):
+    """The batched graph configuration as its own line (see bfs_block)."""
+    blk = bfs_block(args.graphs, args.wg, max(1, args.steps), tuple(args.scheds.split(",")))
+    b = blk["forms"][blk["best"]]
     return {"metric": "tasks/s", "value": b["vertices_per_s"], "unit": "tasks/s (vertices visited)",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms"],
+            "n_gpus": 1, "steps": max(1, args.steps), "warmup": 1, "ms_per_step": b["ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-            "data": "synthetic",
-            "config": {"workload": f"{len(gs)} R-MAT BFS trees, scale 16..22, E=16V", "sched": best,
-                       "V": V, "E": E, "reached": reached, "arcs_scanned": scanned, "max_depth": max_depth},
-            "edges_per_s": b["edges_per_s"], "epochs_per_s": b["global_epochs"] / (b["ms"] * 1e-3),
-            "schedulers": out,
-            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                         "traffic_GBps": round(traffic / (b["ms"] * 1e-3) / 1e9, 1) if traffic else None,
-                         "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE of k_epochs and k_arcs per "
-                                         "graph-form run, work-groups of 512 (profiles/batched_64rmat_bfs.md)",
-                         "tv_bytes": tv, "payload_bytes": payload,
-                         "sector_amplified": {"achieved": round(amp, 1), "frac": round(amp / HBM_PEAK_GBS, 4)}},
-            "setup_s": {"generate": round(gen_s, 1), "oracle_bfs": round(orc_s, 1)}}
+            "data": "synthetic", "config": {"workload": blk["workload"], "sched": blk["best"], "wg": blk["wg"]},
+            "edges_per_s": b["edges_per_s"], "epochs_per_s": b.get("epochs_per_s"), "bfs": blk,
+            "roofline": blk["roofline"]}
 
 
 def bench_cfg7(args):
@@ -778,88 +895,147 @@ def bench_cfg8(args):
     }
 
 
-def serving_workload(nreq, rate, seed=0, pool_scales=range(12, 21)):
-    """Requests of the serving mix plus their host payloads (one R-MAT graph
-    per scale, shared by the requests that draw that scale)."""
-    import inputs
-    from paper_1608_00571_amd.serving import make_jobs
-    reqs = inputs.serving_trace(nreq, rate, seed)
-    pool = {sc: inputs.rmat(sc, inputs.item_seed(5, 1000 + sc)) for sc in pool_scales}
-    keys = {}
+def serving_setup(n_warm: int, n: int, seed: int = 0, workers: int = 16):
+    """The serving configuration's requests (one Poisson trace of n_warm + n
+    requests, arrival times at rate 1, rescaled per run) with their payloads
+    on the device: msort keys (a pristine copy, re-copied into the working
+    buffer before every run, since the sort is in place) and, for every BFS
+    request, its own seeded R-MAT graph.  Host payloads are generated in
+    parallel (the C generators release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
 
-    def keys_for(r):
-        if r.rid not in keys:
-            keys[r.rid] = inputs.keys_u32(r.size, inputs.sub_seed(r.seed, 7))
-        return keys[r.rid]
-    return reqs, pool, make_jobs(reqs, pool, keys_for)
-
-
-def check_serving(jobs, pool):
-    """Every served result equals the oracle's run of that request alone."""
     import numpy as np
-    import oracle
-    fibs, bfs = {}, {}
-    tasks = 0
-    for j in jobs:
-        if j.kind == "fib":
-            n = j.args[0]
-            if n not in fibs:
-                fibs[n] = oracle.fib(n)
-            r = fibs[n]
-            assert (j.value, j.stats.tasks, j.stats.epochs, j.stats.peak_entries) == (r.result, r.tasks, r.epochs, r.peak)
-        elif j.kind == "msort":
-            assert np.array_equal(j.out, np.sort(j.host_payload)), f"msort request {j.rid}"
+    import torch
+
+    import inputs
+    reqs = inputs.serving_trace(n_warm + n, 1.0, seed)
+    with ThreadPoolExecutor(workers) as ex:
+        host = list(ex.map(inputs.request_payload, reqs))
+    dev = []
+    for r, p in zip(reqs, host):
+        if r.kind == "msort":
+            k = torch.from_numpy(np.ascontiguousarray(p).view(np.int32)).to("cuda")
+            dev.append((k, torch.empty_like(k), torch.empty_like(k)))   # pristine, working, merge buffer
+        elif r.kind == "bfs":
+            ci = torch.from_numpy(p.col_idx).to("cuda")
+            if ci.numel() == 0:
+                ci = torch.zeros(1, dtype=torch.int32, device="cuda")
+            dev.append((torch.from_numpy(p.row_ptr).to("cuda"), ci,
+                        torch.empty(p.V, dtype=torch.int32, device="cuda")))
         else:
-            V = j.args[0]
-            sc = V.bit_length() - 1
-            if sc not in bfs:
-                g = pool[sc]
-                bfs[sc] = oracle.bfs_queue(g.V, g.row_ptr, g.col_idx, g.source)
-            assert np.array_equal(j.out, bfs[sc]), f"bfs request {j.rid}"
-        tasks += j.stats.tasks
-    return tasks
+            dev.append(())
+    torch.cuda.synchronize()
+    return reqs, host, dev
+
+
+def serving_jobs(reqs, host, dev, lo: int, hi: int, rate: float | None):
+    """Jobs for requests [lo, hi) of the trace; arrivals at `rate` per second
+    (None: all at once), measured from the first of them."""
+    from paper_1608_00571_amd.serving import Job
+    t0 = reqs[lo].t_arrive
+    jobs = []
+    for r, p, d in zip(reqs[lo:hi], host[lo:hi], dev[lo:hi]):
+        t = 0.0 if rate is None else (r.t_arrive - t0) / rate
+        if r.kind == "fib":
+            jobs.append(Job(r.rid, t, "fib", [r.size]))
+        elif r.kind == "msort":
+            d[1].copy_(d[0])
+            jobs.append(Job(r.rid, t, "msort", [r.size], p, dev=(d[1], d[2]), bytes_payload=8 * r.size))
+        else:
+            jobs.append(Job(r.rid, t, "bfs", [p.V, p.source], p, dev=d,
+                            bytes_payload=4 * (p.V + 1) + 4 * p.E + 4 * p.V))
+    return jobs
+
+
+class ServingCheck:
+    """Every served result against the oracle's run of that request alone:
+    fib value and statistics, msort output, BFS depths (each request's own
+    graph; the queue BFS of a graph is computed once)."""
+
+    def __init__(self):
+        self.fib, self.bfs = {}, {}
+
+    def __call__(self, jobs):
+        import numpy as np
+
+        import oracle
+        tasks = 0
+        for j in jobs:
+            if j.kind == "fib":
+                n = j.args[0]
+                if n not in self.fib:
+                    self.fib[n] = oracle.fib(n)
+                r = self.fib[n]
+                assert (j.value, j.stats.tasks, j.stats.epochs, j.stats.peak_entries) == \
+                    (r.result, r.tasks, r.epochs, r.peak), f"fib request {j.rid}"
+            elif j.kind == "msort":
+                assert np.array_equal(j.out, np.sort(j.host_payload)), f"msort request {j.rid}"
+            else:
+                g = j.host_payload
+                if j.rid not in self.bfs:
+                    self.bfs[j.rid] = oracle.bfs_queue(g.V, g.row_ptr, g.col_idx, g.source)
+                assert np.array_equal(j.out, self.bfs[j.rid]), f"bfs request {j.rid}"
+            tasks += j.stats.tasks
+        return tasks
+
+
+def serving_block(n: int = 600, n_warm: int = 60, arena_gib: int = 16, wg: int = 512, loads=(0.5, 0.8),
+                  modes=("async", "bursts"), burst: int = 4):
+    """The serving configuration: Poisson arrivals of the 40/40/20 fib /
+    msort / BFS mix (fib(12..30), msort of 2^10..2^22 keys, R-MAT BFS of
+    scale 12..20, each BFS request on its own graph).  Saturation from a
+    closed batch, then p50/p99 latency at 50% and 80% of it, in the
+    asynchronous mode (submissions into the running persistent kernel) and,
+    for comparison, the burst mode; every result checked against the
+    oracle."""
+    from paper_1608_00571_amd.serving import Server
+    t0 = time.perf_counter()
+    reqs, host, dev = serving_setup(n_warm, n)
+    setup_s = time.perf_counter() - t0
+    check = ServingCheck()
+    out = {"requests": n, "warmup_requests": n_warm,
+           "mix": "40% fib(12..30) int64, 40% msort 2^10..2^22 uint32 (log-uniform), 20% R-MAT BFS "
+                  "scale 12..20 (one graph per request)",
+           "budget_gib": {"arena": arena_gib, "payload": arena_gib}}
+    for mode in modes:
+        srv = Server(arena_gib << 30, mode=mode, sched="graph", burst=burst, wg=wg,
+                     payload_budget=arena_gib << 30)
+        try:
+            srv.serve(serving_jobs(reqs, host, dev, 0, n_warm, None), realtime=False)
+            sat = srv.serve(serving_jobs(reqs, host, dev, n_warm, n_warm + n, None), realtime=False)
+            sat_tasks = check(sat.jobs)
+            sat_rate = n / sat.seconds
+            m = {"saturation": {"requests_per_s": round(sat_rate, 1), "tasks_per_s": sat_tasks / sat.seconds,
+                                "seconds": round(sat.seconds, 4), "max_inflight": sat.max_inflight,
+                                "epochs": sat.epochs}}
+            for load in loads:
+                r = srv.serve(serving_jobs(reqs, host, dev, n_warm, n_warm + n, load * sat_rate), realtime=True)
+                tasks = check(r.jobs)
+                m[f"load_{int(load * 100)}"] = {
+                    "offered_rps": round(load * sat_rate, 1), "requests_per_s": round(n / r.seconds, 1),
+                    "tasks_per_s": tasks / r.seconds, "p50_ms": round(r.pct(50) * 1e3, 3),
+                    "p99_ms": round(r.pct(99) * 1e3, 3), "max_inflight": r.max_inflight, "epochs": r.epochs}
+        finally:
+            srv.close()
+        out[mode] = m
+    out["checked"] = "every result against the oracle's run of the request alone"
+    out["setup_s"] = round(setup_s, 1)
+    return out
 
 
 def bench_cfg5(args):
-    """Serving: Poisson arrivals of the fib / msort / BFS mix; continuous
-    batching over one context; p50/p99 latency at 50% and 80% of the
-    measured saturation rate."""
-    from paper_1608_00571_amd.serving import Server
-
-    n = args.requests
-    reqs, pool, jobs = serving_workload(n + args.serve_warmup, 1.0)
-    arena = args.serve_arena_gib << 30
-    srv = Server(arena, sched=args.sched if args.sched != "plain" else "graph", burst=args.burst, wg=args.wg)
-    # warm-up, then the closed batch: saturation throughput
-    srv.serve(jobs[: args.serve_warmup], realtime=False)
-    sat = srv.serve(jobs[args.serve_warmup:], realtime=False)
-    sat_tasks = check_serving(sat.jobs, pool)
-    sat_rate = n / sat.seconds
-    out = {"saturation": {"requests_per_s": round(sat_rate, 1), "tasks_per_s": sat_tasks / sat.seconds,
-                          "seconds": round(sat.seconds, 3), "max_inflight": sat.max_inflight,
-                          "bursts": sat.bursts}}
-    for load in (0.5, 0.8):
-        _, _, jl = serving_workload(n + args.serve_warmup, load * sat_rate)
-        jl = jl[args.serve_warmup:]
-        t0 = jl[0].t_arrive
-        for j in jl:
-            j.t_arrive -= t0
-        r = srv.serve(jl, realtime=True)
-        tasks = check_serving(r.jobs, pool)
-        out[f"load_{int(load * 100)}"] = {
-            "offered_rps": round(load * sat_rate, 1), "requests_per_s": round(n / r.seconds, 1),
-            "tasks_per_s": tasks / r.seconds, "p50_ms": round(r.pct(50) * 1e3, 3),
-            "p99_ms": round(r.pct(99) * 1e3, 3), "max_inflight": r.max_inflight, "bursts": r.bursts}
-    srv.close()
-    l80 = out["load_80"]
+    """Serving, as its own line: the serving block, value = tasks/s at 80%
+    of saturation in the asynchronous mode."""
+    blk = serving_block(args.requests, args.serve_warmup, args.serve_arena_gib, args.wg, burst=args.burst)
+    l80 = blk["async"]["load_80"]
     return {"metric": "tasks/s", "value": l80["tasks_per_s"], "unit": "tasks/s", "n_gpus": 1,
-            "steps": 1, "warmup": args.serve_warmup, "ms_per_step": round(n / l80["requests_per_s"] * 1e3, 3),
+            "steps": 1, "warmup": args.serve_warmup, "ms_per_step": round(args.requests / l80["requests_per_s"] * 1e3, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64+u32+int32",
             "data": "synthetic",
-            "config": {"workload": f"serving {n} requests: 40% fib(12..30), 40% msort 2^10..2^22, 20% R-MAT BFS 12..20",
-                       "sched": args.sched if args.sched != "plain" else "graph", "burst_epochs": args.burst,
+            "config": {"workload": f"serving {args.requests} requests: 40% fib(12..30), 40% msort 2^10..2^22, "
+                                   "20% R-MAT BFS 12..20 (own graph each), asynchronous persistent run",
                        "arena_gib": args.serve_arena_gib},
-            "p50_ms": l80["p50_ms"], "p99_ms": l80["p99_ms"], "serving": out}
+            "p50_ms": l80["p50_ms"], "p99_ms": l80["p99_ms"], "serving": blk}
 
 
 def run_traversal(args, prog_kind, n, left, right, lt, rt, log):
@@ -1002,7 +1178,9 @@ def main():
     ap.add_argument("--burst", type=int, default=4)
     ap.add_argument("--no-tune", dest="tune", action="store_false")
     ap.add_argument("--scheds", default="persistent,graph,plain")
-    ap.add_argument("--plain-subset", type=int, default=4096)
+    ap.add_argument("--plain-subset", type=int, default=512)
+    ap.add_argument("--no-blocks", dest="blocks", action="store_false",
+                    help="default line only: skip the batch, BFS and serving blocks")
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the graph / persistent / naive-merge runs of the same workload")
     ap.add_argument("--calib-copy", action="store_true",
@@ -1034,8 +1212,20 @@ def main():
         line = bench_cfg8(args)
     elif args.config == 2:
         line = bench_cfg2(args)
+        log(f"default step: {line['value']:.4g} tasks/s")
         if not args.no_cpu:
             line["cpu_baseline"] = cpu_baseline_cfg2()
+            log("cpu baseline done")
+        if args.blocks:
+            # the rest of the metric, measured in the same run and checked
+            # against the oracle: batched vs per-epoch launch (the tree batch),
+            # BFS (with the worklist comparison) and serving latency
+            line["batch"] = batch_block(wg=512)
+            log("batch block done")
+            line["bfs"] = bfs_block(wg=512)
+            log("bfs block done")
+            line["serving"] = serving_block(wg=512)
+            log("serving block done")
     else:
         print(f"bench.py: --config {args.config} is not wired", file=sys.stderr)
         sys.exit(2)

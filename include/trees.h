@@ -88,8 +88,10 @@ typedef struct {
   int32_t max_trees;      /* tree slots; 0 = 4096 */
   int32_t sched;          /* trees_sched */
   int32_t wg_size;        /* 256, 512 or 1024; 0 = 256 (the paper's work-group size, Section 5.1.1) */
-  int32_t blocks_per_cu;  /* work-groups per CU for GRAPH/PERSISTENT grids; 0 = automatic (PERSISTENT
-                           * never exceeds 3/4 of the runtime's occupancy figure) */
+  int32_t blocks_per_cu;  /* work-groups per CU for GRAPH/PERSISTENT grids; 0 = automatic: the
+                           * co-resident count (the runtime's occupancy figure bounded by the
+                           * kernel's own register and LDS use; 3/4 of it for a kernel that
+                           * uses scratch) */
   int32_t graph_chunk;    /* epochs per captured graph; 0 = 8 */
   uint32_t flags;         /* TREES_F_* */
   double timeout_s;       /* PERSISTENT barrier spin limit in seconds; 0 = 60; also how long an
@@ -132,7 +134,7 @@ typedef struct {
   int32_t live;            /* trees still live after the run */
   double seconds;          /* host wall time of the run */
   int32_t grid;            /* work-groups of the batched launch (0 for PLAIN) */
-  int32_t api_blocks_per_cu; /* the runtime's occupancy figure for that kernel */
+  int32_t api_blocks_per_cu; /* co-resident work-groups per CU of that kernel */
   int32_t sched;           /* the scheduler that ran (AUTO resolved) */
   int32_t wg_size;         /* its work-group size */
 } trees_run_stats;

@@ -28,6 +28,7 @@
 #include <hip/hip_ext.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "bodies.h"
@@ -1180,12 +1181,13 @@ __device__ __forceinline__ bool needs_init(int kind) {
 }
 
 // Asynchronous run: adopt the trees published in the admission ring since the
-// last scan.  Their slots are appended to the candidate list at `nlive`; the
-// ones whose buffers need initialising are listed for the init phase that
-// precedes the next epoch's chunks.  Returns the number adopted.  Every
-// thread of the scanning work-group calls it.
+// last look.  Each becomes a work-list entry of one item (its root, epoch 0)
+// appended after the `*ctot` entries already built (whose items end at
+// `*itot`); the ones whose buffers need initialising are listed for the init
+// phase that precedes the next epoch's chunks.  Every thread of the scanning
+// work-group calls it.
 template <int WG>
-__device__ int adopt(const DevCtx &C, Lds<WG> &L, int32_t *cand, int nlive) {
+__device__ void adopt(const DevCtx &C, Lds<WG> &L, int32_t *live, int *ctot, uint32_t *itot, int64_t g) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -1194,15 +1196,43 @@ __device__ int adopt(const DevCtx &C, Lds<WG> &L, int32_t *cand, int nlive) {
     L.scnt = H->initN;
   }
   __syncthreads();
-  const int nn = min(L.sflag, C.tmax - nlive);   // (never clamped: a record needs a free slot)
+  const int k0 = *ctot;
+  const int nn = min(L.sflag, C.tmax - k0);   // (never clamped: a record needs a free slot)
   const uint32_t head = H->adm_head;
   __syncthreads();
-  if (nn <= 0) return 0;
+  if (nn <= 0) return;
   for (int j = tid; j < nn; j += WG) {
-    const Admit a = C.ring_adm[(head + (uint32_t)j) % (uint32_t)C.tmax];
-    admit_one(C, a);
-    cand[nlive + j] = a.slot;
-    if (needs_init(a.ts.kind)) C.init_slot[atomicAdd(&L.scnt, 1)] = a.slot;
+    // the record, read word by word from host memory (no struct temporary:
+    // this code is inlined into the epoch kernel and must stay lean)
+    const Admit *a = &C.ring_adm[(head + (uint32_t)j) % (uint32_t)C.tmax];
+    const int s = a->slot;
+    const int64_t base = a->ts.base;
+    const uint32_t tp = a->ts.tp;
+    const int32_t kind = a->ts.kind;
+    {
+      const uint32_t *src = (const uint32_t *)&a->ts;
+      uint32_t *dts = (uint32_t *)&C.ts[s];
+      for (int w = 0; w < (int)(sizeof(TreeStatic) / 4); ++w) dts[w] = src[w];
+    }
+    TreeState *T = &C.st[s];
+    T->cen = 0; T->b = 0; T->e = 1; T->old = 1; T->sp = 0; T->status = TS_LIVE; T->err = 0;
+    T->epochs = 0; T->tasks = 1; T->launched = 0; T->result = 0; T->done_gepoch = -1;
+    T->start_gepoch = g; T->peak = 1; T->ntrace = 0;
+    TreeHot *Hh = &C.hot[s];
+    Hh->nfc = 1; Hh->flags = 0; Hh->done = 0; Hh->valid = 0;
+    C.t_len[s] = 1; C.t_cen[s] = 0; C.t_b[s] = 0;
+    C.code[base] = a->root_code;
+    C.a0[base] = a->a0; C.a1[base] = a->a1; C.a2[base] = a->a2; C.a3[base] = a->a3;
+    C.r[base] = 0;
+    const int k = k0 + j;
+    live[k] = s;
+    C.wl_tree[k] = s;
+    C.wl_off[k] = *itot + (uint32_t)j;
+    C.wl_b[k] = 0;
+    C.wl_tb[k] = (uint32_t)(base >> 6);
+    C.wl_tp[k] = tp;
+    C.wl_cen[k] = 0;
+    if (needs_init(kind)) C.init_slot[atomicAdd(&L.scnt, 1)] = s;
   }
   __syncthreads();
   if (tid == 0) {
@@ -1211,7 +1241,19 @@ __device__ int adopt(const DevCtx &C, Lds<WG> &L, int32_t *cand, int nlive) {
     __hip_atomic_store(&C.ring->head, head + (uint32_t)nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   __syncthreads();
-  return nn;
+  *ctot = k0 + nn;
+  *itot += (uint32_t)nn;
+}
+
+// Asynchronous run: make the completion records written so far visible to
+// the host (after the records themselves, and after any merge of the epoch
+// the trees finished in).
+__device__ __forceinline__ void publish_completions(const DevCtx &C) {
+  SchedHdr *H = C.hdr;
+  if (H->ctail_pub != H->ctail) {
+    H->ctail_pub = H->ctail;
+    __hip_atomic_store(&C.ring->ctail, H->ctail, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // The init phase of an asynchronous run: every work-group sweeps the buffers
@@ -1267,117 +1309,128 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
         TreeState *T = &C.st[slot[r]];
         if (err[r] == 0) T->result = res[r];
         T->done_gepoch = ge;
-        if (C.async_mode) {   // its completion record, for the host
-          Completion *q = &C.ring_done[(ct + (uint32_t)(j0 + r * WG + tid)) % (uint32_t)C.tmax];
-          const auto sys = [](auto *p, auto v) {
-            __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-          };
-          sys(&q->slot, (int32_t)slot[r]);
-          sys(&q->err, (int32_t)err[r]);
-          sys(&q->epochs, T->epochs);
-          sys(&q->peak, T->peak);
-          sys(&q->tasks, T->tasks);
-          sys(&q->launched, T->launched);
-          sys(&q->result, err[r] == 0 ? res[r] : (int64_t)0);
-          sys(&q->start_gepoch, T->start_gepoch);
-          sys(&q->done_gepoch, ge);
-        }
       }
     }
-    if (C.async_mode && nd > 0) {   // the records have landed: publish their count
+    if (C.async_mode) {   // a completion record per finished tree, for the host
+      __syncthreads();      // (the results above, written by other threads)
+      for (int j = tid; j < nd; j += WG) {
+        const int sl = C.done_list[j];
+        const TreeState *T = &C.st[sl];
+        Completion *q = &C.ring_done[(ct + (uint32_t)j) % (uint32_t)C.tmax];
+        // (the state's fields, then the record's, one word at a time: the
+        // record lives in host memory)
+        const int32_t err = T->err;
+        __hip_atomic_store(&q->slot, sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->err, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->epochs, T->epochs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->peak, T->peak, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->tasks, T->tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->launched, T->launched, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->result, err == 0 ? T->result : (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->start_gepoch, T->start_gepoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&q->done_gepoch, ge, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    if (C.async_mode && nd > 0) {   // the records are written; published below
       wait_vmem();
       __syncthreads();
-      if (tid == 0) {
-        H->ctail = ct + (uint32_t)nd;
-        __hip_atomic_store(&C.ring->ctail, ct + (uint32_t)nd, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+      if (tid == 0) H->ctail = ct + (uint32_t)nd;
     }
   }
   // Candidates: after an epoch, the trees of the last work list (a live
-  // tree always has a non-empty range), plus the trees an asynchronous run
-  // adopts now; at the start of a run, every slot.  Rounds of WG x R
-  // candidates: every load of a round is issued before any of its values is
-  // used, then one work-group scan places the round.
+  // tree always has a non-empty range); at the start of a run, every slot.
+  // Rounds of WG x R candidates: every load of a round is issued before any
+  // of its values is used, then one work-group scan places the round.
   const int sel = H->live_sel;
-  int32_t *src = C.live + (size_t)sel * C.tmax;
+  const int32_t *src = C.live + (size_t)sel * C.tmax;
   int32_t *dst = C.live + (size_t)(after_epoch ? (sel ^ 1) : 0) * C.tmax;
-  int n = after_epoch ? H->live : H->tslots;
+  const int n = after_epoch ? H->live : H->tslots;
   const int64_t g = H->gepoch + (real ? 1 : 0);
   constexpr int R = WG >= 1024 ? 1 : 1024 / WG;   // (bounded: registers of the epoch kernel)
   int ctot = 0;
   uint32_t itot = 0;
-  const bool asy = C.async_mode != 0 && after_epoch;
-  if (asy && tid == 0) H->initN = 0;   // (the last scan's list was swept before this epoch)
-  __syncthreads();
-  for (;;) {
-    if (asy) n += adopt<WG>(C, L, src, n);
-    ctot = 0;
-    itot = 0;
-    for (int base = 0; base < n; base += WG * R) {
-      int slot[R], len[R], b[R], cen[R];
-      int64_t tbase[R], sg[R];
-      uint32_t tp[R];
+  for (int base = 0; base < n; base += WG * R) {
+    int slot[R], len[R], b[R], cen[R];
+    int64_t tbase[R], sg[R];
+    uint32_t tp[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int t = base + r * WG + tid;
-        slot[r] = t < n ? (after_epoch ? src[t] : t) : -1;
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
-        if (slot[r] >= 0) {
-          const int s = slot[r];
-          len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
-          tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
-        }
-      }
-      int cnt = 0, items = 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (len[r] > 0) { ++cnt; items += len[r]; }
-      int rc, ri;
-      int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
-      uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (len[r] <= 0) continue;
-        const int s = slot[r];
-        dst[k] = s;
-        C.wl_tree[k] = s;
-        C.wl_off[k] = off;
-        C.wl_b[k] = b[r];
-        C.wl_tb[k] = (uint32_t)(tbase[r] >> 6);
-        C.wl_tp[k] = tp[r];
-        C.wl_cen[k] = cen[r];
-        if (sg[r] < 0) C.st[s].start_gepoch = g;
-        ++k;
-        off += (uint32_t)len[r];
-      }
-      ctot += rc;
-      itot += (uint32_t)ri;
+    for (int r = 0; r < R; ++r) {
+      const int t = base + r * WG + tid;
+      slot[r] = t < n ? (after_epoch ? src[t] : t) : -1;
     }
-    if (!asy || ctot > 0) break;
-    // Asynchronous run with nothing live: wait for a submission, the close
-    // request or an abort, for at most one slice; then run an empty epoch
-    // (every work-group returns to the barrier, whose waits stay short).
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
+      if (slot[r] >= 0) {
+        const int s = slot[r];
+        len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
+        tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
+      }
+    }
+    int cnt = 0, items = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (len[r] > 0) { ++cnt; items += len[r]; }
+    int rc, ri;
+    int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
+    uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (len[r] <= 0) continue;
+      const int s = slot[r];
+      dst[k] = s;
+      C.wl_tree[k] = s;
+      C.wl_off[k] = off;
+      C.wl_b[k] = b[r];
+      C.wl_tb[k] = (uint32_t)(tbase[r] >> 6);
+      C.wl_tp[k] = tp[r];
+      C.wl_cen[k] = cen[r];
+      if (sg[r] < 0) C.st[s].start_gepoch = g;
+      ++k;
+      off += (uint32_t)len[r];
+    }
+    ctot += rc;
+    itot += (uint32_t)ri;
+  }
+  // Asynchronous run.  The work list now holds only live trees, so the slots
+  // of the trees that finished this epoch may be handed back: their
+  // completions are published now, or, if the epoch registered merges, after
+  // the map phase that completes them.  Then the trees submitted since the
+  // last look are adopted, after the live ones (a slot the host has reused
+  // already is no longer among them).
+  const bool asy = C.async_mode != 0 && after_epoch;
+  if (asy) {
+    const bool merges = (ld_agent(&H->map_ctr) >> kMapShift) != 0;
     __syncthreads();
     if (tid == 0) {
-      const int64_t t0 = realtime();
-      int more = 0;
-      while (true) {
-        if ((int)(__hip_atomic_load(&C.ring->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - H->adm_head) > 0) {
-          more = 1;
-          break;
-        }
-        if (__hip_atomic_load(&C.ring->close, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-        if (C.abort_flag && *C.abort_flag) break;
-        if (realtime() - t0 > C.slice_ticks) break;
-        __builtin_amdgcn_s_sleep(8);
-      }
-      L.sflag = more;
+      H->initN = 0;   // (the last scan's list was swept before this epoch)
+      if (!merges) publish_completions(C);
     }
     __syncthreads();
-    if (!L.sflag) break;
+    for (;;) {
+      adopt<WG>(C, L, dst, &ctot, &itot, g);
+      if (ctot > 0 || merges) break;
+      // Nothing live: wait for a submission, the close request or an abort,
+      // for at most one slice; then run an empty epoch (every work-group
+      // returns to the barrier, whose waits stay short).
+      if (tid == 0) {
+        const int64_t t0 = realtime();
+        int more = 0;
+        while (true) {
+          if ((int)(__hip_atomic_load(&C.ring->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - H->adm_head) > 0) {
+            more = 1;
+            break;
+          }
+          if (__hip_atomic_load(&C.ring->close, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+          if (C.abort_flag && *C.abort_flag) break;
+          if (realtime() - t0 > C.slice_ticks) break;
+          __builtin_amdgcn_s_sleep(8);
+        }
+        L.sflag = more;
+      }
+      __syncthreads();
+      if (!L.sflag) break;
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -1427,6 +1480,14 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
     if (stop) H->stop_reason = stop;
   }
   __syncthreads();
+}
+
+// The work-list scan out of line, reading the context from its copy in
+// device memory: the epoch kernels' register budget (two work-groups per CU)
+// is then set by their chunk code alone, not by the scan's.
+template <int WG>
+__device__ __noinline__ void schedule_scan_ext(const DevCtx *C, Lds<WG> *L, int after_epoch) {
+  schedule_scan<WG>(*C, *L, after_epoch != 0);
 }
 
 template <int WG, int NS>
@@ -1674,7 +1735,7 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
       if (L.flag2) {
         if (threadIdx.x == 0) H->arc_phase = 1;
       } else {
-        schedule_scan<WG>(C, L, true);
+        schedule_scan_ext<WG>(C.self, &L, 1);
       }
     }
     wait_vmem();
@@ -1770,6 +1831,9 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     }
     if (stop) break;
     if ((mapJ || initN > 0) && !grid_barrier<WG>(C, L, false, true)) break;
+    // asynchronous run: trees that finished in the epoch whose merges just
+    // ran are complete now
+    if (C.async_mode && mapJ && blockIdx.x == 0 && threadIdx.x == 0) publish_completions(C);
     // Chunks go to work-groups in runs of consecutive chunks; within a run
     // each chunk continues where the previous one ended.  Kernels with BFS
     // (whose chunks differ in cost by orders of magnitude) claim runs from a
@@ -1844,7 +1908,7 @@ __global__ __launch_bounds__(WG) void k_arcs(DevCtx C) {
   if (L.flag) {
     if (threadIdx.x == 0) { fence_acquire(); st_agent(&H->arc_arrive, 0u); }
     __syncthreads();
-    schedule_scan<WG>(C, L, true);
+    schedule_scan_ext<WG>(C.self, &L, 1);
   }
 }
 
@@ -1974,12 +2038,37 @@ hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStre
   return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, 0, s);
 }
 
-int coresident_blocks_per_cu(int wg, uint32_t need) {
+// Co-resident work-groups per CU of a batched epoch kernel: the runtime's
+// occupancy figure, bounded by the kernel's own resource use (VGPRs in
+// granules of 8 out of 512 per SIMD lane, at most 8 waves per SIMD; static
+// LDS out of the CU's; SGPRs counted at a conservative 128 of the SIMD's
+// 800, so that a kernel limited by SGPRs is never over-subscribed).  *scratch
+// receives the kernel's private bytes per lane: a persistent grid of a
+// kernel that uses scratch is sized more cautiously by the caller.
+int coresident_blocks_per_cu(int wg, uint32_t need, int *scratch, int *own) {
   const void *fn = kernel_epochs(wg, need);
   if (!fn) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, wg, 0) != hipSuccess) return 0;
-  return nb;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, fn) != hipSuccess) return 0;
+  int dev = 0, lds_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+    return 0;
+  const int waves = (wg + 63) / 64;
+  const int per_simd = (waves + 3) / 4;                 // a work-group's waves spread over the 4 SIMDs
+  const int vg = ((fa.numRegs > 0 ? fa.numRegs : 1) + 7) / 8 * 8;
+  const int w_v = std::min(8, 512 / vg);
+  const int w_s = 800 / 128;
+  const int by_regs = std::min(w_v, w_s) / per_simd;
+  const int lds = (int)((fa.sharedSizeBytes + 511) / 512 * 512);
+  const int by_lds = lds > 0 ? lds_cu / lds : 1 << 20;
+  const int by_waves = 32 / waves;
+  const int mine = std::min(by_regs, std::min(by_lds, by_waves));
+  if (scratch) *scratch = (int)fa.localSizeBytes;
+  if (own) *own = mine;
+  return std::min(nb, mine);
 }
 
 hipError_t launch_scan(const DevCtx &C, hipStream_t s) {

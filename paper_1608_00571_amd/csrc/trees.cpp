@@ -28,7 +28,7 @@ hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int p
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
                       hipStream_t s, const hipEvent_t *ev);
 hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s);
-int coresident_blocks_per_cu(int wg, uint32_t need);
+int coresident_blocks_per_cu(int wg, uint32_t need, int *scratch, int *own);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
 hipError_t launch_depth_init(int32_t *depth, int32_t V, int32_t src, int32_t fill, hipStream_t s);
@@ -217,6 +217,8 @@ struct trees_ctx {
   Admit *adm_dev = nullptr;
   PlainMirror *mirror = nullptr;   // host-mapped, written after each plain epoch
   uint32_t plain_seq = 0;
+  DevCtx *self_dev = nullptr;      // device copies of dc (out-of-line device code reads them)
+  DevCtx *self_host = nullptr;     // pinned staging for them
   WlMirror *wl_mirror = nullptr;   // host-mapped, written after each worklist iteration
   WlMirror *wl_mirror_dev = nullptr;
   uint32_t wl_seq = 0;
@@ -235,7 +237,7 @@ struct trees_ctx {
   bool tuned_ok = false;            // ... and held a shape for this device and workload class
   trees_shape tuned{};
   int ncu = 0;
-  int last_grid = 0, last_api_bpc = 0, last_wg = 0;
+  int last_grid = 0, last_api_bpc = 0, last_wg = 0, last_scratch = 0;
   bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // plain-scheduler launch timing: event pairs resolved after the tree's
@@ -408,7 +410,10 @@ trees_status sync_states(trees_ctx *c) {
     HostTree &t = c->trees[s];
     if (t.hstatus != H_LIVE) continue;
     t.st = c->st_host[s];
-    if (t.st.status == TS_DONE) mark_done(c, s);
+    if (t.st.status == TS_DONE) {
+      mark_done(c, s);
+      if (t.st.err == 0) c->async_tasks += (uint64_t)t.st.tasks;   // (counted only for asynchronous runs)
+    }
   }
   return TREES_OK;
 }
@@ -604,12 +609,23 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs, bool async = false) {
   c->hdr_host->initN = 0;
   c->hdr_host->adm_head = 0;
   c->hdr_host->ctail = 0;
+  c->hdr_host->ctail_pub = 0;
   c->hdr_host->idle_t0 = 0;
   HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
+  // the context's device copies (out-of-line device code reads them): as it
+  // stands now (programs registered since the last run included), and its
+  // asynchronous-run form
+  c->self_host[0] = c->dc;
+  c->self_host[0].self = c->self_dev;
+  c->self_host[1] = c->dc;
+  c->self_host[1].async_mode = 1;
+  c->self_host[1].self = c->self_dev + 1;
+  HIPCHK(c, hipMemcpyAsync(c->self_dev, c->self_host, 2 * sizeof(DevCtx), hipMemcpyHostToDevice, c->stream));
   // (the first scan of an asynchronous run does not stop on an empty work
   // list: the run waits for submissions)
   DevCtx d = c->dc;
   d.async_mode = async ? 1 : 0;
+  d.self = c->self_dev + (async ? 1 : 0);
   HIPCHK(c, launch_scan(d, c->stream));
   return TREES_OK;
 }
@@ -621,15 +637,19 @@ trees_status read_hdr(trees_ctx *c) {
 }
 
 // Work-groups per CU for the batched grids.  The persistent form needs every
-// work-group resident at once, and a cooperative launch sized at the
-// runtime's occupancy figure was not refused yet did not get past its first
-// grid barrier (the spin limit had to end it), so the persistent grid never
-// exceeds 3/4 of that figure.  The graph form has no residency requirement.
+// work-group resident at once: its grid is the co-resident count (the
+// runtime's occupancy figure, bounded by the kernel's own VGPR, SGPR and LDS
+// use).  A kernel that uses scratch (private memory) is held to 3/4 of it:
+// scratch space is handed out per wave by the runtime and may admit fewer
+// waves than the registers and LDS would.  The graph form has no residency
+// requirement.
 int blocks_per_cu(trees_ctx *c, uint32_t need, bool persistent) {
-  int api = coresident_blocks_per_cu(c->wg, need);
+  int scratch = 0, own = 0;
+  int api = coresident_blocks_per_cu(c->wg, need, &scratch, &own);
   if (api <= 0) api = 1;
   c->last_api_bpc = api;
-  const int cap = persistent ? std::max(1, (api * 3) / 4) : api;
+  c->last_scratch = scratch;
+  const int cap = (persistent && scratch > 0) ? std::max(1, (api * 3) / 4) : api;
   return (c->bpc > 0) ? std::min(c->bpc, cap) : cap;
 }
 
@@ -704,6 +724,7 @@ trees_status start_async(trees_ctx *c, int64_t max_epochs) {
   c->last_grid = grid;
   DevCtx d = c->dc;
   d.async_mode = 1;
+  d.self = c->self_dev + 1;
   HIPCHK(c, launch_epochs(d, c->wg, need, grid, 1, c->stream));
   c->async_on = true;
   c->async_t0 = std::chrono::steady_clock::now();
@@ -985,7 +1006,7 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
                o_wtb = take((T + 1) * 4), o_wtp = take((T + 1) * 4),
                o_dl = take(T * 4), o_lv = take(2 * T * 4), o_hdr = take(sizeof(SchedHdr)),
                o_pl = take(sizeof(PlainCounters)),
-               o_adm = take(T * sizeof(Admit)), o_init = take(T * 4);
+               o_adm = take(T * sizeof(Admit)), o_init = take(T * 4), o_self = take(2 * sizeof(DevCtx));
   const bool nomap = (cfg->flags & TREES_F_NOMAP) != 0;
   const size_t MJ = nomap ? 0 : (size_t)kMapJobs;
   const size_t PC = nomap ? 0 : (size_t)kPartCap;
@@ -1019,6 +1040,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.plain = (PlainCounters *)(b + o_pl);
   c->adm_dev = (Admit *)(b + o_adm);
   c->dc.init_slot = (int32_t *)(b + o_init);
+  c->self_dev = (DevCtx *)(b + o_self);   // [0]: the context, [1]: its asynchronous-run form
+  c->dc.self = c->self_dev;
   c->dc.mj_lo = (int32_t *)(b + o_mjl);
   c->dc.mj_hi = (int32_t *)(b + o_mjh);
   c->dc.mj_src = (const uint32_t **)(b + o_mjs);
@@ -1047,7 +1070,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
       hipHostMalloc((void **)&c->r_host, 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->abort_flag, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
       hipHostMalloc((void **)&c->wl_mirror, sizeof(WlMirror), hipHostMallocCoherent | hipHostMallocMapped) !=
-          hipSuccess)
+          hipSuccess ||
+      hipHostMalloc((void **)&c->self_host, 2 * sizeof(DevCtx), hipHostMallocDefault) != hipSuccess)
     return bail(TREES_E_NOMEM, "hipHostMalloc failed");
   memset(c->wl_mirror, 0, sizeof(WlMirror));
   {   // asynchronous runs: ring header, admission and completion records
@@ -1106,6 +1130,7 @@ void trees_destroy(trees_ctx *c) {
   if (c->abort_flag) (void)hipHostFree(c->abort_flag);
   if (c->wl_mirror) (void)hipHostFree(c->wl_mirror);
   if (c->ring) (void)hipHostFree(c->ring);
+  if (c->self_host) (void)hipHostFree(c->self_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

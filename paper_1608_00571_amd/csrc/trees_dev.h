@@ -119,8 +119,8 @@ struct SchedHdr {
   uint32_t mapJ;        // map jobs registered by the last epoch (raw count)
   int32_t initN;        // asynchronous run: adopted trees whose buffers the next epoch initialises
   uint32_t adm_head;    // asynchronous run: admission records adopted so far
-  uint32_t ctail;       // asynchronous run: completion records published so far
-  int32_t pad9;
+  uint32_t ctail;       // asynchronous run: completion records written so far
+  uint32_t ctail_pub;   // asynchronous run: completion records published to the host
   int64_t idle_t0;      // asynchronous run: device clock when no tree was left live (0: busy)
   int32_t pad0[8];
   alignas(128) uint32_t arrive;   // barrier arrivals of the last work-group of each group
@@ -289,6 +289,7 @@ struct DevCtx {
   int32_t pad4;
   int64_t slice_ticks;            // idle wait for a submission before an empty epoch
   int64_t idle_ticks;             // idle time after which the run ends by itself
+  const DevCtx *self;             // a copy of this struct in device memory (for out-of-line code)
   uint8_t op_of_type[kMaxTypes + 1];
 };
 
