@@ -218,15 +218,16 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
   const int32_t cen = T->cen, b = T->b, e = T->e, old = T->old;
   int32_t sp = T->sp;
   const int32_t forks = nfc - old;
+  const int32_t valid = ld_agent(&H->valid);   // tasks executed this epoch (its share of the work)
   const int32_t ep = T->epochs;
   T->epochs = ep + 1;
   T->launched += e - b;
-  T->tasks += (int64_t)forks + joins;
+  T->tasks += valid;
   if (nfc > T->peak) T->peak = nfc;
   if (C.trace_on && ep < kTraceMax) {
     TraceRec q;
     q.epoch = ep; q.cen = cen; q.b = b; q.e = e; q.launched = e - b;
-    q.valid = ld_agent(&H->valid); q.forks = forks; q.joins = (int32_t)joins; q.nfc = nfc;
+    q.valid = valid; q.forks = forks; q.joins = (int32_t)joins; q.nfc = nfc;
     C.trace[(size_t)slot * kTraceMax + ep] = q;
     T->ntrace = ep + 1;
   }
@@ -265,6 +266,139 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
   C.t_len[slot] = top.z - top.y;
   C.t_cen[slot] = top.x;
   C.t_b[slot] = top.y;
+}
+
+// ---------------------------------------------------------------------------
+// The body of one task by its operation (Section 4.3.2): what it forks (nk
+// children, whose arguments follow from x0..x3), whether it joins or emits
+// (val), and the co-operative work it hands on (a merge for the map phase, a
+// leaf sort, an FFT leaf).  errf: the tree's error flags (an invalid node
+// raises TF_ENCODING there); sink receives atomics' results.
+// ---------------------------------------------------------------------------
+template <uint32_t OPS>
+__device__ __forceinline__ void task_body(const DevCtx &C, int op, int32_t a0v, int32_t a1v, int32_t a2v, int32_t a3v,
+                                          int64_t tb, uint32_t tp, int slot, int32_t *errf, int32_t &sink, int &nk,
+                                          int &act, int64_t &val, int32_t &x0, int32_t &x1, int32_t &x2, int32_t &x3,
+                                          bool &want_map, bool &leaf, bool &fleaf) {
+  nk = 0; act = ACT_NONE; val = 0;
+  x0 = x1 = x2 = x3 = 0;
+  want_map = false; leaf = false; fleaf = false;
+  if (op == OP_NONE) return;
+  switch (op) {
+    case OP_FIB32:
+    case OP_FIB64: {
+      const int32_t n = a0v;
+      if (n < 2) { act = ACT_EMIT; val = n; }
+      else { act = ACT_JOIN; nk = 2; x0 = n; }
+    } break;
+    case OP_SUM32: {
+    if constexpr ((OPS & opbit(OP_SUM32)) == 0) break;
+      const int32_t c = a0v;
+      const uint32_t sm = (uint32_t)C.r[tb + c] + (uint32_t)C.r[tb + c + 1];
+      act = ACT_EMIT; val = (int64_t)(int32_t)sm;
+    } break;
+    case OP_SUM64: {
+    if constexpr ((OPS & opbit(OP_SUM64)) == 0) break;
+      const int32_t c = a0v;
+      act = ACT_EMIT; val = C.r[tb + c] + C.r[tb + c + 1];
+    } break;
+    case OP_Q: {
+    if constexpr ((OPS & opbit(OP_Q)) == 0) break;
+      const int32_t n = (int32_t)(tp >> 8);
+      const int32_t row = a0v;
+      if (row == n) { act = ACT_EMIT; val = 1; break; }
+      const uint32_t full = (1u << n) - 1u;
+      const uint32_t cols = (uint32_t)a1v, ld = (uint32_t)a2v, rd = (uint32_t)a3v;
+      const uint32_t avail = ~(cols | ld | rd) & full;
+      if (!avail) { act = ACT_EMIT; val = 0; break; }
+      act = ACT_JOIN; nk = __popc(avail);
+      x0 = row; x1 = (int32_t)cols; x2 = (int32_t)ld; x3 = (int32_t)rd;
+    } break;
+    case OP_QSUM: {
+    if constexpr ((OPS & opbit(OP_QSUM)) == 0) break;
+      // the children's counts (kk <= 14), all loads issued before the sum
+      const int32_t c = a0v, kk = a1v;
+      const int64_t *rr = C.r + tb + c;
+      int64_t part[14];
+#pragma unroll
+      for (int j = 0; j < 14; ++j) part[j] = j < kk ? rr[j] : 0;
+      int64_t sm = 0;
+#pragma unroll
+      for (int j = 0; j < 14; ++j) sm += part[j];
+      act = ACT_EMIT; val = sm;
+    } break;
+    case OP_MS: {
+    if constexpr ((OPS & opbit(OP_MS)) == 0) break;
+      const int32_t lo = a0v, hi = a1v, d = a2v;
+      x0 = lo; x1 = hi; x2 = d;
+      if (hi - lo <= kLeaf) { act = ACT_FINISH; leaf = true; }   // sorted co-operatively below
+      else { act = ACT_JOIN; nk = 2; }
+    } break;
+    case OP_MERGE: {
+    if constexpr ((OPS & opbit(OP_MERGE)) == 0) break;
+      act = ACT_FINISH;
+      x0 = a0v; x1 = a1v; x2 = a2v;
+      if (C.mj_cap > 0) {
+        want_map = true;   // the merge runs in the map phase
+      } else {
+        const TreeStatic *T = &C.ts[slot];
+        ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0, x1, x2);
+      }
+    } break;
+    case OP_VISIT:
+    case OP_SVISIT:
+      act = ACT_FINISH;   // its arcs are expanded co-operatively below
+      break;
+    case OP_POST: {
+    if constexpr ((OPS & opbit(OP_POST)) == 0) break;
+      // Figure 2: postorder(node) forks postorder(right), postorder(left)
+      // and joins a visit of node; postorder(-1) ends.
+      const int32_t node = a0v, n = (int32_t)(tp >> 8);
+      act = ACT_FINISH;
+      if (node < 0) break;
+      if (node >= n) {   // not a node of this tree: an error of the tree
+        sink = or_agent(errf, (int32_t)TF_ENCODING);
+        break;
+      }
+      const TreeStatic *T = &C.ts[slot];
+      act = ACT_JOIN; nk = 2;
+      x0 = node;
+      x1 = ((const int32_t *)T->ptr1)[node];   // right child, forked first
+      x2 = ((const int32_t *)T->ptr0)[node];   // left child
+    } break;
+    case OP_PVISIT:
+      act = ACT_FINISH;   // the visit: appended to the tree's log below
+      break;
+    case OP_FFT: {
+    if constexpr ((OPS & opbit(OP_FFT)) == 0) break;
+      // FFT(lo, o, ls): n = 2^(log2 N - ls) points; a leaf is transformed
+      // by a wavefront below; otherwise fork the even and odd halves and
+      // join the combine (which keeps lo, o, ls)
+      const int lg = (int)(tp >> 8) - a2v;
+      if (lg <= kFftLeafLog) { act = ACT_FINISH; fleaf = true; }
+      else { act = ACT_JOIN; nk = 2; x0 = a0v; x1 = a1v; x2 = a2v; }
+    } break;
+    case OP_COMB:
+      act = ACT_FINISH;   // its butterflies are expanded co-operatively below
+      break;
+    case OP_PRE: {
+    if constexpr ((OPS & opbit(OP_PRE)) == 0) break;
+      // Figure 2: preorder(node) visits node (appended to the log below),
+      // then forks preorder(right), preorder(left); preorder(-1) ends.
+      const int32_t node = a0v, n = (int32_t)(tp >> 8);
+      act = ACT_FINISH;
+      if (node < 0) break;
+      if (node >= n) {
+        sink = or_agent(errf, (int32_t)TF_ENCODING);
+        break;
+      }
+      const TreeStatic *T = &C.ts[slot];
+      nk = 2;
+      x1 = ((const int32_t *)T->ptr1)[node];
+      x2 = ((const int32_t *)T->ptr0)[node];
+    } break;
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -567,116 +701,9 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
   bool want_map[IT], leaf[IT], fleaf[IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    nk[k] = 0; act[k] = ACT_NONE; val[k] = 0;
-    x0[k] = x1[k] = x2[k] = x3[k] = 0;
-    want_map[k] = false; leaf[k] = false; fleaf[k] = false;
-    if (op[k] == OP_NONE) continue;
-    switch (op[k]) {
-      case OP_FIB32:
-      case OP_FIB64: {
-        const int32_t n = a0v[k];
-        if (n < 2) { act[k] = ACT_EMIT; val[k] = n; }
-        else { act[k] = ACT_JOIN; nk[k] = 2; x0[k] = n; }
-      } break;
-      case OP_SUM32: {
-        const int32_t c = a0v[k];
-        const uint32_t sm = (uint32_t)C.r[tb[k] + c] + (uint32_t)C.r[tb[k] + c + 1];
-        act[k] = ACT_EMIT; val[k] = (int64_t)(int32_t)sm;
-      } break;
-      case OP_SUM64: {
-        const int32_t c = a0v[k];
-        act[k] = ACT_EMIT; val[k] = C.r[tb[k] + c] + C.r[tb[k] + c + 1];
-      } break;
-      case OP_Q: {
-        const int32_t n = (int32_t)(tp[k] >> 8);
-        const int32_t row = a0v[k];
-        if (row == n) { act[k] = ACT_EMIT; val[k] = 1; break; }
-        const uint32_t full = (1u << n) - 1u;
-        const uint32_t cols = (uint32_t)a1v[k], ld = (uint32_t)a2v[k], rd = (uint32_t)a3v[k];
-        const uint32_t avail = ~(cols | ld | rd) & full;
-        if (!avail) { act[k] = ACT_EMIT; val[k] = 0; break; }
-        act[k] = ACT_JOIN; nk[k] = __popc(avail);
-        x0[k] = row; x1[k] = (int32_t)cols; x2[k] = (int32_t)ld; x3[k] = (int32_t)rd;
-      } break;
-      case OP_QSUM: {
-        // the children's counts (kk <= 14), all loads issued before the sum
-        const int32_t c = a0v[k], kk = a1v[k];
-        const int64_t *rr = C.r + tb[k] + c;
-        int64_t part[14];
-#pragma unroll
-        for (int j = 0; j < 14; ++j) part[j] = j < kk ? rr[j] : 0;
-        int64_t sm = 0;
-#pragma unroll
-        for (int j = 0; j < 14; ++j) sm += part[j];
-        act[k] = ACT_EMIT; val[k] = sm;
-      } break;
-      case OP_MS: {
-        const int32_t lo = a0v[k], hi = a1v[k], d = a2v[k];
-        x0[k] = lo; x1[k] = hi; x2[k] = d;
-        if (hi - lo <= kLeaf) { act[k] = ACT_FINISH; leaf[k] = true; }   // sorted co-operatively below
-        else { act[k] = ACT_JOIN; nk[k] = 2; }
-      } break;
-      case OP_MERGE: {
-        act[k] = ACT_FINISH;
-        x0[k] = a0v[k]; x1[k] = a1v[k]; x2[k] = a2v[k];
-        if (C.mj_cap > 0) {
-          want_map[k] = true;   // the merge runs in the map phase
-        } else {
-          const TreeStatic *T = &C.ts[slot[k]];
-          ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0[k], x1[k], x2[k]);
-        }
-      } break;
-      case OP_VISIT:
-      case OP_SVISIT:
-        act[k] = ACT_FINISH;   // its arcs are expanded co-operatively below
-        break;
-      case OP_POST: {
-        // Figure 2: postorder(node) forks postorder(right), postorder(left)
-        // and joins a visit of node; postorder(-1) ends.
-        const int32_t node = a0v[k], n = (int32_t)(tp[k] >> 8);
-        act[k] = ACT_FINISH;
-        if (node < 0) break;
-        if (node >= n) {   // not a node of this tree: an error of the tree
-          L.sink = or_agent(MULTI ? &C.hot[slot[k]].flags : &C.plain->flags[P.par], (int32_t)TF_ENCODING);
-          break;
-        }
-        const TreeStatic *T = &C.ts[slot[k]];
-        act[k] = ACT_JOIN; nk[k] = 2;
-        x0[k] = node;
-        x1[k] = ((const int32_t *)T->ptr1)[node];   // right child, forked first
-        x2[k] = ((const int32_t *)T->ptr0)[node];   // left child
-      } break;
-      case OP_PVISIT:
-        act[k] = ACT_FINISH;   // the visit: appended to the tree's log below
-        break;
-      case OP_FFT: {
-        // FFT(lo, o, ls): n = 2^(log2 N - ls) points; a leaf is transformed
-        // by a wavefront below; otherwise fork the even and odd halves and
-        // join the combine (which keeps lo, o, ls)
-        const int lg = (int)(tp[k] >> 8) - a2v[k];
-        if (lg <= kFftLeafLog) { act[k] = ACT_FINISH; fleaf[k] = true; }
-        else { act[k] = ACT_JOIN; nk[k] = 2; x0[k] = a0v[k]; x1[k] = a1v[k]; x2[k] = a2v[k]; }
-      } break;
-      case OP_COMB:
-        act[k] = ACT_FINISH;   // its butterflies are expanded co-operatively below
-        break;
-      case OP_PRE: {
-        // Figure 2: preorder(node) visits node (appended to the log below),
-        // then forks preorder(right), preorder(left); preorder(-1) ends.
-        const int32_t node = a0v[k], n = (int32_t)(tp[k] >> 8);
-        act[k] = ACT_FINISH;
-        if (node < 0) break;
-        if (node >= n) {
-          L.sink = or_agent(MULTI ? &C.hot[slot[k]].flags : &C.plain->flags[P.par], (int32_t)TF_ENCODING);
-          break;
-        }
-        const TreeStatic *T = &C.ts[slot[k]];
-        nk[k] = 2;
-        x1[k] = ((const int32_t *)T->ptr1)[node];
-        x2[k] = ((const int32_t *)T->ptr0)[node];
-      } break;
-      default: break;
-    }
+    int32_t *errf = MULTI ? &C.hot[slot[k]].flags : &C.plain->flags[P.par];
+    task_body<OPS>(C, op[k], a0v[k], a1v[k], a2v[k], a3v[k], tb[k], tp[k], slot[k], errf, L.sink, nk[k], act[k],
+                   val[k], x0[k], x1[k], x2[k], x3[k], want_map[k], leaf[k], fleaf[k]);
   }
 
   // ---- traversal visits (postorder's visit continuation, a preorder task
@@ -850,7 +877,7 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     // joins (and, when tracing, valid tasks) per tree segment
-    seg_add_pair(L.seg_jv, seg[k], act[k] == ACT_JOIN, C.trace_on && op[k] != OP_NONE);
+    seg_add_pair(L.seg_jv, seg[k], act[k] == ACT_JOIN, op[k] != OP_NONE);
     off[k] = lds_reserve(L.seg_cnt, seg[k], nk[k]);
   }
   seg_commit<WG, MULTI>(C, L, P, true);
@@ -1136,7 +1163,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         sg[6 * kArcSegPool + s] = j | (v << 16);
         continue;
       }
-      if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
+      // (the valid count shares the done counter's line: performed before it)
+      if (v) L.sink = add_agent(&C.hot[sl].valid, v);
       const uint64_t add = ((uint64_t)(uint32_t)j << 32) | items;
       PendingFinish f;
       f.slot = sl; f.items = items; f.range = end - beg; f.joins = (uint32_t)j;
@@ -1152,6 +1180,493 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
 }
 
 // ---------------------------------------------------------------------------
+// Batched epochs, one chunk per wavefront (the programs without co-operative
+// expansion: fib, N-queens, merge sort, the traversals).  A wavefront sweeps
+// its own run of work items, 64 * IT at a time, with no work-group barrier:
+// its fork allocation takes one device atomic per tree it touches (the
+// paper's one atomic per wavefront, Section 5.2.3), and so does its
+// retirement count.  The CU overlaps the round trips of many wavefronts
+// instead of stalling a whole work-group on each.
+// ---------------------------------------------------------------------------
+constexpr int kWSeg = 64;   // work-list entries a wavefront caches at once
+
+struct NoWaveLds {};
+
+struct WaveLds {
+  uint32_t end[kWSeg];   // wl_off[kfirst + 1 + e]: where cached entry e ends (~0 past the list)
+  int32_t slot[kWSeg];   // tree slot of entry e
+  int32_t cen[kWSeg];    // its epoch number
+  int32_t b[kWSeg];      // arena-relative start of its range
+  uint32_t tb[kWSeg];    // its arena base / 64
+  uint32_t tp[kWSeg];    // first type id | parameter << 8
+  int32_t cnt[kWSeg];    // children requested per entry in this step (LDS atomics)
+  int32_t base[kWSeg];   // arena-relative first child per entry (-1: overflow)
+  int32_t jv[kWSeg];     // joins | valid tasks << 16 per entry in the current step
+  uint32_t ritems[kWSeg];  // items retired per entry, not yet counted in the tree
+  uint32_t rjoins[kWSeg];  // joins of those items
+  uint32_t rvalid[kWSeg];  // valid tasks among them
+  uint32_t beg0;         // wl_off[kfirst]
+  int32_t kfirst;        // first cached entry (-1: nothing cached)
+  int32_t sink;
+  int32_t pad;
+};
+
+// Orders this wavefront's LDS writes before its later LDS reads of other
+// lanes' words (one wavefront: no work-group barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Counts the items the wavefront retired in its cached entries into their
+// trees (one atomic per tree: retired items | joins << 32); the count that
+// completes a tree's range runs its Phase 3.  Called when the cache is
+// replaced and when the wavefront's run ends.
+__device__ void wave_retire(const DevCtx &C, WaveLds &W) {
+  const int lane = lane_id();
+  const uint32_t it = W.ritems[lane];
+  if (W.kfirst >= 0 && it > 0) {
+    const uint32_t j = W.rjoins[lane];
+    const int32_t v = (int32_t)W.rvalid[lane];
+    const int sl = W.slot[lane];
+    const uint32_t beg = (lane == 0) ? W.beg0 : W.end[lane - 1];
+    if (v) W.sink = add_agent(&C.hot[sl].valid, v);
+    const uint64_t prev = add_agent(&C.hot[sl].done, ((uint64_t)j << 32) | it);
+    if ((uint32_t)prev + it == W.end[lane] - beg) tree_finish(C, sl, (uint32_t)(prev >> 32) + j);
+  }
+  W.ritems[lane] = 0;
+  W.rjoins[lane] = 0;
+  W.rvalid[lane] = 0;
+  W.jv[lane] = 0;
+  wave_sync();
+}
+
+// Caches the 64 work-list entries from the one holding item w (a 64-ary
+// search of the entries' start offsets, then one round trip for the rest).
+__device__ void wave_locate(const DevCtx &C, WaveLds &W, uint32_t w, int32_t nL) {
+  const int lane = lane_id();
+  int lo = 0, hi = nL;
+  while (hi - lo > 1) {   // last entry whose start is <= w
+    const int step = (hi - lo + 63) >> 6;
+    const int p = lo + lane * step;
+    const bool ok = p < hi && C.wl_off[p] <= w;
+    lo = lo + (__popcll(ballot64(ok)) - 1) * step;
+    hi = min(lo + step, hi);
+  }
+  const int e = lo + lane;
+  W.end[lane] = (e + 1 <= nL) ? C.wl_off[e + 1] : 0xFFFFFFFFu;
+  if (e < nL) {
+    W.slot[lane] = C.wl_tree[e];
+    W.cen[lane] = C.wl_cen[e];
+    W.b[lane] = C.wl_b[e];
+    W.tb[lane] = C.wl_tb[e];
+    W.tp[lane] = C.wl_tp[e];
+  }
+  W.cnt[lane] = 0;
+  W.jv[lane] = 0;
+  W.ritems[lane] = 0;
+  W.rjoins[lane] = 0;
+  W.rvalid[lane] = 0;
+  if (lane == 0) {
+    W.kfirst = lo;
+    W.beg0 = C.wl_off[lo];
+  }
+  wave_sync();
+}
+
+// Cached entry holding item w (its end lies above w; w is inside the cache).
+__device__ __forceinline__ int wave_seg(const WaveLds &W, uint32_t w) {
+  int lo = 0, hi = kWSeg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (W.end[mid] <= w) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Traversal visits, merge-sort leaves and map registrations of a step's
+// items (the parts of a task's body that act co-operatively): visits append
+// to the tree's log with one atomic per wavefront and tree; the wavefront
+// sorts its leaves, 8 at a time; merge continuations reserve map job slots
+// and output units with one atomic per wavefront (Section 4.2).
+template <uint32_t OPS, int IT>
+__device__ __forceinline__ void wave_cooperative(const DevCtx &C, const int *seg, const int *slot, const int *op,
+                                                 const uint32_t *tp, const int32_t *a0v, const int *nk,
+                                                 const bool *leaf, const bool *want_map, const int32_t *x0,
+                                                 const int32_t *x1, const int32_t *x2) {
+  const int lane = lane_id();
+  if constexpr ((OPS & OPS_PO) != 0) {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const bool vis = op[k] == OP_PVISIT || (op[k] == OP_PRE && nk[k] == 2);
+      const uint64_t m = ballot64(vis);
+      if (!m) continue;
+      int32_t *log = vis ? (int32_t *)C.ts[slot[k]].ptr2 : nullptr;
+      const int32_t n = (int32_t)(tp[k] >> 8);
+      int32_t pos = 0;
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      const int s0 = __shfl(seg[k], leader, 64);
+      if (__all(!vis || seg[k] == s0)) {
+        int32_t bs = 0;
+        if (lane == leader) bs = atomicAdd(&log[n], __popcll(m));
+        pos = __shfl(bs, leader, 64) + mbcnt64(m);
+      } else if (vis) {
+        pos = atomicAdd(&log[n], 1);
+      }
+      if (vis && pos >= 0 && pos < n) log[pos] = a0v[k];
+    }
+  }
+  if constexpr ((OPS & opbit(OP_MS)) != 0) {
+    constexpr int B = 8;
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      uint64_t lm = ballot64(leaf[k]);
+      while (lm) {
+        uint32_t v[B];
+        int32_t lo[B], n[B];
+        uint32_t *dst[B];
+#pragma unroll
+        for (int bb = 0; bb < B; ++bb) {
+          n[bb] = 0; lo[bb] = 0; dst[bb] = nullptr; v[bb] = 0xFFFFFFFFu;
+          if (lm) {
+            const int l = __ffsll((unsigned long long)lm) - 1;
+            lm &= lm - 1;
+            const int32_t d = __shfl(x2[k], l, 64);
+            lo[bb] = __shfl(x0[k], l, 64);
+            n[bb] = __shfl(x1[k], l, 64) - lo[bb];
+            const TreeStatic *T = &C.ts[__shfl(slot[k], l, 64)];
+            const uint32_t *keys = (const uint32_t *)T->ptr0;
+            dst[bb] = (d & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
+            if (lane < n[bb]) v[bb] = keys[lo[bb] + lane];
+          }
+        }
+        wave_bitonic64<B>(v);
+#pragma unroll
+        for (int bb = 0; bb < B; ++bb)
+          if (lane < n[bb]) dst[bb][lo[bb] + lane] = v[bb];
+      }
+    }
+  }
+  if constexpr ((OPS & opbit(OP_MERGE)) != 0) {
+    int jl = 0;
+    int64_t ul = 0;
+#pragma unroll
+    for (int k = 0; k < IT; ++k)
+      if (want_map[k]) { ++jl; ul += (int64_t)(x1[k] - x0[k]); }
+    if (__any(jl > 0)) {
+      const int jinc = wave_incl_scan(jl);
+      const int64_t uinc = wave_incl_scan64(ul);
+      const int jtot = __shfl(jinc, 63, 64);
+      const int64_t utot = __shfl(uinc, 63, 64);
+      uint64_t prev = 0;
+      if (lane == 0) prev = add_agent(&C.hdr->map_ctr, ((uint64_t)jtot << kMapShift) | (uint64_t)utot);
+      prev = __shfl(prev, 0, 64);
+      uint32_t j = (uint32_t)(prev >> kMapShift) + (uint32_t)(jinc - jl);
+      uint64_t u = (prev & kMapUnitMask) + (uint64_t)(uinc - ul);
+#pragma unroll
+      for (int k = 0; k < IT; ++k) {
+        if (!want_map[k]) continue;
+        const TreeStatic *T = &C.ts[slot[k]];
+        if (j < (uint32_t)C.mj_cap) {
+          C.mj_lo[j] = x0[k]; C.mj_hi[j] = x1[k];
+          C.mj_src[j] = ((x2[k] + 1) & 1) ? (const uint32_t *)T->ptr1 : (const uint32_t *)T->ptr0;
+          C.mj_dst[j] = (x2[k] & 1) ? (uint32_t *)T->ptr1 : (uint32_t *)T->ptr0;
+          C.mj_off[j] = u;
+        } else {   // job list full: this lane merges by itself
+          ms_merge((uint32_t *)T->ptr0, (uint32_t *)T->ptr1, x0[k], x1[k], x2[k]);
+        }
+        ++j;
+        u += (uint64_t)(x1[k] - x0[k]);
+      }
+    }
+  }
+}
+
+// A forking task's children, from c (arena-relative, through the tree's
+// arena pointers), and its own entry e: join (the continuation at the same
+// epoch) or emit / finish.
+template <int K>
+__device__ __forceinline__ void write_task(int32_t *code, int32_t *a0, int32_t *a1, int32_t *a2, int32_t *a3, int64_t *r,
+                                           int op, int act, int nk, int32_t cb, int32_t e, int32_t nxt, int32_t own,
+                                           uint32_t tp, int64_t val, int32_t x0, int32_t x1, int32_t x2, int32_t x3) {
+  if (nk > 0 && cb >= 0) {
+    const int32_t c = cb;
+    if (op == OP_FIB32 || op == OP_FIB64) {
+      code[c] = nxt; a0[c] = x0 - 1;
+      code[c + 1] = nxt; a0[c + 1] = x0 - 2;
+    } else if (op == OP_Q) {
+      const int32_t n = (int32_t)(tp >> 8);
+      const uint32_t full = (1u << n) - 1u;
+      const uint32_t cols = (uint32_t)x1, ld = (uint32_t)x2, rd = (uint32_t)x3;
+      uint32_t avail = ~(cols | ld | rd) & full;
+      int32_t cc = c;
+      while (avail) {
+        const uint32_t bit = avail & (0u - avail);
+        avail ^= bit;
+        code[cc] = nxt;
+        a0[cc] = x0 + 1;
+        a1[cc] = (int32_t)(cols | bit);
+        a2[cc] = (int32_t)(((ld | bit) << 1) & full);
+        a3[cc] = (int32_t)((rd | bit) >> 1);
+        ++cc;
+      }
+    } else if (op == OP_MS) {
+      const int32_t mid = x0 + (x1 - x0) / 2;
+      code[c] = nxt; a0[c] = x0; a1[c] = mid; a2[c] = x2 + 1;
+      code[c + 1] = nxt; a0[c + 1] = mid; a1[c + 1] = x1; a2[c + 1] = x2 + 1;
+    } else if (op == OP_POST || op == OP_PRE) {
+      code[c] = nxt; a0[c] = x1;
+      code[c + 1] = nxt; a0[c + 1] = x2;
+    }
+  }
+  if (act == ACT_EMIT) {
+    r[e] = val;
+    code[e] = 0;
+  } else if (act == ACT_FINISH) {
+    code[e] = 0;
+  } else if (act == ACT_JOIN) {
+    code[e] = own;   // local type 2: SUM / QSUM / MERGE / visit, same epoch
+    if (op != OP_MS && op != OP_POST) {   // (their joins keep their own arguments)
+      a0[e] = cb;
+      if (op == OP_Q) a1[e] = nk;
+    }
+  }
+}
+
+// One step of a wavefront whose items [wa, wb) all belong to the tree of
+// cached entry s: the tree's values are uniform (scalar registers), entries
+// are addressed by 32-bit offsets from the tree's arena, and the wavefront
+// takes one allocation atomic for all its children.
+template <uint32_t OPS, int IT>
+__device__ void wave_step_tree(const DevCtx &C, WaveLds &W, const uint8_t *op_tab, int s, uint32_t wa, uint32_t wb) {
+  const int lane = lane_id();
+  const int slot = __builtin_amdgcn_readfirstlane(W.slot[s]);
+  const int32_t cen = __builtin_amdgcn_readfirstlane(W.cen[s]);
+  const uint32_t tp = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)W.tp[s]);
+  const uint32_t beg = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(s == 0 ? W.beg0 : W.end[s - 1]));
+  const int32_t b = __builtin_amdgcn_readfirstlane(W.b[s]);
+  const int64_t ab = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)W.tb[s]) << 6;
+  int32_t *code = C.code + ab, *pa0 = C.a0 + ab, *pa1 = C.a1 + ab, *pa2 = C.a2 + ab, *pa3 = C.a3 + ab;
+  int64_t *pr = C.r + ab;
+  const int32_t ntt = C.ntt;
+  const int t1 = (int)(tp & 0xFF);                 // the program's first type id
+  const int32_t lo_code = cen * ntt;               // this epoch's codes: lo_code + type
+  const int op1 = op_tab[t1], op2 = op_tab[min(t1 + 1, kMaxTypes)];
+  const int pop = op1;                             // the program, by its first operation
+  constexpr bool kWide = (OPS & (OPS_NQ | OPS_MS)) != 0;
+  int32_t *errf = &C.hot[slot].flags;
+
+  int32_t e[IT], a0v[IT], a1v[IT], a2v[IT], a3v[IT];
+  int op[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const uint32_t w = wa + (uint32_t)(k * 64 + lane);
+    e[k] = b + (int32_t)(w - beg);
+    op[k] = OP_NONE;
+    a0v[k] = a1v[k] = a2v[k] = a3v[k] = 0;
+    int32_t cd = 0;
+    if (w < wb) {
+      cd = code[e[k]];
+      a0v[k] = pa0[e[k]];
+      if (kWide) {
+        if (pop == OP_Q || pop == OP_MS) { a1v[k] = pa1[e[k]]; a2v[k] = pa2[e[k]]; }
+        if (pop == OP_Q) a3v[k] = pa3[e[k]];
+      }
+    }
+    if (cd != 0) {
+      const int32_t gt = cd - lo_code;
+      op[k] = gt == t1 ? op1 : (gt == t1 + 1 ? op2 : OP_NONE);
+      if (op[k] == OP_NONE || (opbit(op[k]) & OPS) == 0) {   // outside the epoch's window
+        op[k] = OP_NONE;
+        W.sink = or_agent(errf, (int32_t)TF_ENCODING);
+      }
+    }
+  }
+  int nk[IT], act[IT];
+  int64_t val[IT];
+  int32_t x0[IT], x1[IT], x2[IT], x3[IT];
+  bool want_map[IT], leaf[IT], fleaf[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k)
+    task_body<OPS>(C, op[k], a0v[k], a1v[k], a2v[k], a3v[k], ab, tp, slot, errf, W.sink, nk[k], act[k], val[k],
+                   x0[k], x1[k], x2[k], x3[k], want_map[k], leaf[k], fleaf[k]);
+  if constexpr ((OPS & (OPS_PO | OPS_MS)) != 0) {
+    int seg[IT], sl[IT];
+    uint32_t tpk[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) { seg[k] = s; sl[k] = slot; tpk[k] = tp; }
+    wave_cooperative<OPS, IT>(C, seg, sl, op, tpk, a0v, nk, leaf, want_map, x0, x1, x2);
+  }
+  // fork: the wavefront's children in one block of the tree's arena
+  int off[IT];
+  int run = 0, joins = 0, valid = 0;
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    int tot;
+    off[k] = run + wave_prefix_small<4>(nk[k], &tot);
+    run += tot;
+    joins += __popcll(ballot64(act[k] == ACT_JOIN));
+    valid += __popcll(ballot64(op[k] != OP_NONE));
+  }
+  int32_t base = 0;
+  if (run > 0) {
+    if (lane == 0) {
+      base = add_agent(&C.hot[slot].nfc, (int32_t)run);
+      if (base < 0 || (int64_t)base + run > (int64_t)C.ts[slot].cap) {
+        W.sink = or_agent(errf, (int32_t)TF_OVERFLOW);
+        base = -1;
+      }
+    }
+    base = __builtin_amdgcn_readfirstlane(base);
+  }
+  const int32_t nxt = (cen + 1) * ntt + t1;   // local type 1, next epoch
+  const int32_t own = lo_code + t1 + 1;       // local type 2, this epoch
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int32_t cb = nk[k] == 0 ? 0 : (base < 0 ? -1 : base + off[k]);
+    write_task<0>(code, pa0, pa1, pa2, pa3, pr, op[k], act[k], nk[k], cb, e[k], nxt, own, tp, val[k], x0[k], x1[k],
+                  x2[k], x3[k]);
+  }
+  // retirement: counted into the tree when the run moves on
+  if (lane == 0) {
+    W.ritems[s] += wb - wa;
+    W.rjoins[s] += (uint32_t)joins;
+    W.rvalid[s] += (uint32_t)valid;
+  }
+}
+
+// Items [wa, w1) of the current epoch's work list, by one wavefront: steps of
+// 64 * ITF items inside one tree take the scalar path above; steps that span
+// trees (64 * IT items) locate each item's tree in the cached entries and
+// take one allocation atomic per tree.  Retirements are counted once per
+// tree when the run leaves the cached entries or ends.
+template <uint32_t OPS, int IT, int ITF>
+__device__ void run_wave(const DevCtx &C, WaveLds &W, const uint8_t *op_tab, uint32_t wa, uint32_t w1, int32_t nL) {
+  const int lane = lane_id();
+  const int32_t ntt = C.ntt;
+  constexpr bool kWide = (OPS & (OPS_NQ | OPS_MS)) != 0;
+  while (wa < w1) {
+    // ---- the cached entries must hold item wa ------------------------------
+    if (!(W.kfirst >= 0 && W.beg0 <= wa && wa < W.end[kWSeg - 1])) {
+      wave_retire(C, W);
+      wave_locate(C, W, wa, nL);
+    }
+    const uint32_t beg0 = W.beg0;
+    const uint32_t end63 = W.end[kWSeg - 1];
+    {
+      const uint32_t wf = min(min(w1, wa + (uint32_t)(64 * ITF)), end63);
+      const int s0 = wave_seg(W, wa);
+      if (W.end[s0] >= wf) {   // one tree
+        wave_step_tree<OPS, ITF>(C, W, op_tab, s0, wa, wf);
+        wa = wf;
+        continue;
+      }
+    }
+    const uint32_t wb = min(min(w1, wa + (uint32_t)(64 * IT)), end63);   // this step's items
+    const int s_lo = wave_seg(W, wa), s_hi = wave_seg(W, wb - 1);
+
+    // ---- fetch and decode ------------------------------------------------------
+    int seg[IT], slot[IT], op[IT];
+    int32_t cen[IT];
+    int64_t idx[IT], tb[IT];
+    uint32_t tp[IT];
+    int32_t code[IT], a0v[IT], a1v[IT], a2v[IT], a3v[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const uint32_t w = wa + (uint32_t)(k * 64 + lane);
+      seg[k] = -1; slot[k] = 0; cen[k] = 0; idx[k] = 0; tb[k] = 0; tp[k] = 0; op[k] = OP_NONE;
+      code[k] = 0; a0v[k] = a1v[k] = a2v[k] = a3v[k] = 0;
+      if (w < wb) {
+        const int sg = wave_seg(W, w);
+        seg[k] = sg;
+        slot[k] = W.slot[sg];
+        cen[k] = W.cen[sg];
+        tb[k] = (int64_t)W.tb[sg] << 6;
+        tp[k] = W.tp[sg];
+        idx[k] = tb[k] + W.b[sg] + (int64_t)(w - (sg == 0 ? beg0 : W.end[sg - 1]));
+        code[k] = C.code[idx[k]];
+        a0v[k] = C.a0[idx[k]];
+        if (kWide) {
+          const int pop = op_tab[tp[k] & 0xFF];   // the program's first operation
+          if (pop == OP_Q || pop == OP_MS) { a1v[k] = C.a1[idx[k]]; a2v[k] = C.a2[idx[k]]; }
+          if (pop == OP_Q) a3v[k] = C.a3[idx[k]];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      if (code[k] != 0) {
+        const int32_t gtype = code[k] - cen[k] * ntt;
+        if (gtype >= 1 && gtype <= ntt) op[k] = op_tab[gtype];
+        if (op[k] == OP_NONE || (opbit(op[k]) & OPS) == 0) {   // outside the epoch's window
+          op[k] = OP_NONE;
+          W.sink = or_agent(&C.hot[slot[k]].flags, (int32_t)TF_ENCODING);
+        }
+      }
+    }
+
+    // ---- task bodies -------------------------------------------------------------
+    int nk[IT], act[IT];
+    int64_t val[IT];
+    int32_t x0[IT], x1[IT], x2[IT], x3[IT];
+    bool want_map[IT], leaf[IT], fleaf[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k)
+      task_body<OPS>(C, op[k], a0v[k], a1v[k], a2v[k], a3v[k], tb[k], tp[k], slot[k], &C.hot[slot[k]].flags,
+                     W.sink, nk[k], act[k], val[k], x0[k], x1[k], x2[k], x3[k], want_map[k], leaf[k], fleaf[k]);
+    wave_cooperative<OPS, IT>(C, seg, slot, op, tp, a0v, nk, leaf, want_map, x0, x1, x2);
+
+    // ---- fork: one device atomic per tree of this step -------------------------
+    int off[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      seg_add_pair(W.jv, seg[k], act[k] == ACT_JOIN, op[k] != OP_NONE);
+      off[k] = lds_reserve(W.cnt, seg[k], nk[k]);
+    }
+    wave_sync();
+    {
+      const int es = s_lo + lane;
+      if (es <= s_hi) {
+        const int c = W.cnt[es];
+        int bse = 0;
+        if (c > 0) {
+          W.cnt[es] = 0;
+          const int sl = W.slot[es];
+          bse = add_agent(&C.hot[sl].nfc, (int32_t)c);
+          if (bse < 0 || (int64_t)bse + c > (int64_t)C.ts[sl].cap) {
+            W.sink = or_agent(&C.hot[sl].flags, (int32_t)TF_OVERFLOW);
+            bse = -1;
+          }
+        }
+        W.base[es] = bse;
+        // the step's items, counted into the tree when the run moves on
+        const uint32_t bg = (es == 0) ? beg0 : W.end[es - 1];
+        W.ritems[es] += min(W.end[es], wb) - max(bg, wa);
+        const int32_t jv = W.jv[es];
+        W.jv[es] = 0;
+        W.rjoins[es] += (uint32_t)(jv & 0xFFFF);
+        W.rvalid[es] += (uint32_t)jv >> 16;
+      }
+    }
+    wave_sync();
+
+    // ---- children and own entries -----------------------------------------------
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      if (seg[k] < 0) continue;
+      const int32_t cb = child_base(W.base, seg[k], nk[k], off[k]);
+      const int64_t ab = tb[k];
+      write_task<0>(C.code + ab, C.a0 + ab, C.a1 + ab, C.a2 + ab, C.a3 + ab, C.r + ab, op[k], act[k], nk[k], cb,
+                    (int32_t)(idx[k] - ab), (cen[k] + 1) * ntt + (int32_t)(tp[k] & 0xFF),
+                    cen[k] * ntt + (int32_t)(tp[k] & 0xFF) + 1, tp[k], val[k], x0[k], x1[k], x2[k], x3[k]);
+    }
+    wa = wb;
+  }
+  wave_retire(C, W);   // the run's retirements
+}
+
+// ---------------------------------------------------------------------------
 // Admission of a tree on the device: its descriptor, state and counters, and
 // its root in entry 0 of its arena, to run in epoch 0 (Section 5.2.1).
 // ---------------------------------------------------------------------------
@@ -1160,7 +1675,7 @@ __device__ void admit_one(const DevCtx &C, const Admit &a) {
   ((TreeStatic *)C.ts)[s] = a.ts;
   TreeState T = {};
   T.cen = 0; T.b = 0; T.e = 1; T.old = 1; T.sp = 0; T.status = TS_LIVE; T.err = 0;
-  T.epochs = 0; T.tasks = 1; T.launched = 0; T.result = 0; T.done_gepoch = -1;
+  T.epochs = 0; T.tasks = 0; T.launched = 0; T.result = 0; T.done_gepoch = -1;
   T.start_gepoch = -1; T.peak = 1; T.ntrace = 0;
   C.st[s] = T;
   TreeHot Hh = {};
@@ -1186,8 +1701,8 @@ __device__ __forceinline__ bool needs_init(int kind) {
 // `*itot`); the ones whose buffers need initialising are listed for the init
 // phase that precedes the next epoch's chunks.  Every thread of the scanning
 // work-group calls it.
-template <int WG>
-__device__ void adopt(const DevCtx &C, Lds<WG> &L, int32_t *live, int *ctot, uint32_t *itot, int64_t g) {
+template <int WG, int NS>
+__device__ void adopt(const DevCtx &C, Lds<WG, NS> &L, int32_t *live, int *ctot, uint32_t *itot, int64_t g) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -1216,7 +1731,7 @@ __device__ void adopt(const DevCtx &C, Lds<WG> &L, int32_t *live, int *ctot, uin
     }
     TreeState *T = &C.st[s];
     T->cen = 0; T->b = 0; T->e = 1; T->old = 1; T->sp = 0; T->status = TS_LIVE; T->err = 0;
-    T->epochs = 0; T->tasks = 1; T->launched = 0; T->result = 0; T->done_gepoch = -1;
+    T->epochs = 0; T->tasks = 0; T->launched = 0; T->result = 0; T->done_gepoch = -1;
     T->start_gepoch = g; T->peak = 1; T->ntrace = 0;
     TreeHot *Hh = &C.hot[s];
     Hh->nfc = 1; Hh->flags = 0; Hh->done = 0; Hh->valid = 0;
@@ -1276,8 +1791,8 @@ __device__ void run_inits(const DevCtx &C, int n) {
 // Work-list construction (the serial part of Phase 1 over all trees): an
 // exclusive scan of the per-tree range lengths.  One work-group.
 // ---------------------------------------------------------------------------
-template <int WG>
-__device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
+template <int WG, int NS>
+__device__ void schedule_scan(const DevCtx &C, Lds<WG, NS> &L, bool after_epoch) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
   // an epoch that had no work list (an asynchronous run waiting for
@@ -1408,7 +1923,7 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
     }
     __syncthreads();
     for (;;) {
-      adopt<WG>(C, L, dst, &ctot, &itot, g);
+      adopt<WG, NS>(C, L, dst, &ctot, &itot, g);
       if (ctot > 0 || merges) break;
       // Nothing live: wait for a submission, the close request or an abort,
       // for at most one slice; then run an empty epoch (every work-group
@@ -1485,9 +2000,9 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG> &L, bool after_epoch) {
 // The work-list scan out of line, reading the context from its copy in
 // device memory: the epoch kernels' register budget (two work-groups per CU)
 // is then set by their chunk code alone, not by the scan's.
-template <int WG>
-__device__ __noinline__ void schedule_scan_ext(const DevCtx *C, Lds<WG> *L, int after_epoch) {
-  schedule_scan<WG>(*C, *L, after_epoch != 0);
+template <int WG, int NS>
+__device__ __noinline__ void schedule_scan_ext(const DevCtx *C, Lds<WG, NS> *L, int after_epoch) {
+  schedule_scan<WG, NS>(*C, *L, after_epoch != 0);
 }
 
 template <int WG, int NS>
@@ -1543,8 +2058,8 @@ __global__ __launch_bounds__(WG) void k_plain(DevCtx C, PlainArgs P) {
   // performed before it takes a ticket, so the last ticket sees every
   // work-group's counts (no cache writeback needed): the atomics whose result
   // a thread uses are waited for before the barrier; the one that returns
-  // nothing (the valid count, nonzero only when tracing) is waited for here.
-  if (C.trace_on) wait_vmem();
+  // nothing (the valid count) is waited for here.
+  wait_vmem();
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t t = add_agent(&C.plain->ticket, 1u);
@@ -1681,7 +2196,7 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
         const int32_t jv = sg[6 * kArcSegPool + q];
         const uint32_t joins = (uint32_t)(jv & 0xFFFF);
         const int32_t v = (int32_t)((uint32_t)jv >> 16);
-        if (C.trace_on && v) L.sink = add_agent(&C.hot[sl].valid, v);
+        if (v) L.sink = add_agent(&C.hot[sl].valid, v);
         const uint64_t prev = add_agent(&C.hot[sl].done, ((uint64_t)joins << 32) | items);
         if ((uint32_t)prev + items == range) tree_finish(C, sl, (uint32_t)(prev >> 32) + joins);
       }
@@ -1698,8 +2213,8 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
 // wait = false (graph form): the others return at once, the kernel
 // boundary is their barrier.  Returns false if this work-group gave up
 // waiting after the spin limit.
-template <int WG>
-__device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool wait) {
+template <int WG, int NS>
+__device__ bool grid_barrier(const DevCtx &C, Lds<WG, NS> &L, bool with_scan, bool wait) {
   SchedHdr *H = C.hdr;
   wait_vmem();
   __syncthreads();
@@ -1735,7 +2250,7 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG> &L, bool with_scan, bool w
       if (L.flag2) {
         if (threadIdx.x == 0) H->arc_phase = 1;
       } else {
-        schedule_scan_ext<WG>(C.self, &L, 1);
+        schedule_scan_ext<WG, NS>(C.self, &L, 1);
       }
     }
     wait_vmem();
@@ -1791,13 +2306,19 @@ __device__ __noinline__ void map_merge_call(const uint32_t *part_job, const int6
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
+  // programs without the co-operative expansion sweep one chunk per
+  // wavefront; the others one chunk per work-group
+  constexpr bool kWave = (OPS & OPS_EXPAND) == 0;
+  constexpr int NSL = kWave ? 1 : kChunk;   // segments the work-group's LDS caches
   using MapL = typename std::conditional<kMap, MapLds<kMapTile>, NoMapLds>::type;
   using VL = typename std::conditional<(OPS & OPS_EXPAND) != 0, VisitLds, NoVisitLds>::type;
-  __shared__ Lds<WG> L;
+  using WLT = typename std::conditional<kWave, WaveLds, NoWaveLds>::type;
+  __shared__ Lds<WG, NSL> L;
   __shared__ MapL M;
   __shared__ VL V;
+  __shared__ WLT WLs[kWave ? WG / 64 : 1];
   __shared__ uint32_t s_hdr[6];
-  lds_init<WG>(C, L);
+  lds_init(C, L);
   if (threadIdx.x == 0) L.tflag = 0;
   if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
   if (threadIdx.x == 0) L.tprof = realtime();
@@ -1825,12 +2346,12 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
         map_extent<kMapTile>(C, mapJ, &J, &U);
         map_partition<kMapTile>(C, J, U, (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6),
                       (int64_t)gridDim.x * (WG / 64));
-        if (!grid_barrier<WG>(C, L, false, true)) break;
+        if (!grid_barrier<WG, NSL>(C, L, false, true)) break;
         map_merge_call<WG>(C.part_job, C.part_ia, C.mj_off, C.mj_lo, C.mj_hi, C.mj_src, C.mj_dst, M, J, U);
       }
     }
     if (stop) break;
-    if ((mapJ || initN > 0) && !grid_barrier<WG>(C, L, false, true)) break;
+    if ((mapJ || initN > 0) && !grid_barrier<WG, NSL>(C, L, false, true)) break;
     // asynchronous run: trees that finished in the epoch whose merges just
     // ran are complete now
     if (C.async_mode && mapJ && blockIdx.x == 0 && threadIdx.x == 0) publish_completions(C);
@@ -1840,30 +2361,46 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     // shared counter, guided: a run is about a quarter of an even share, so
     // a work-group that drew expensive chunks takes fewer.  The others take
     // one even share each.
-    const uint32_t nchunks = (S + kChunk - 1) / kChunk;
-    constexpr bool kGuided = (OPS & OPS_EXPAND) != 0;
-    const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
-    PendingFinish pend;
-    Prefetch<kChunk / WG> pf;
-    for (uint32_t turn = 0;; ++turn) {
-      uint32_t c0;
-      if (kGuided) {
-        if (threadIdx.x == 0) s_hdr[4] = add_agent(&H->chunk_ctr, run);
-        __syncthreads();
-        c0 = s_hdr[4];
-        __syncthreads();
-      } else {
-        c0 = turn == 0 ? blockIdx.x * run : nchunks;
+    if constexpr (kWave) {
+      // every wavefront takes an even share of wavefront chunks (64 * ITW
+      // items), consecutive wavefronts consecutive shares
+      constexpr int ITW = 2;
+      constexpr uint32_t WCH = 64 * ITW;
+      const uint32_t nw = gridDim.x * (WG / 64);
+      const uint32_t wid = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+      WaveLds &W = WLs[threadIdx.x >> 6];
+      if (lane_id() == 0) W.kfirst = -1;   // (a new work list every epoch)
+      wave_sync();
+      const uint32_t nwc = (S + WCH - 1) / WCH;
+      const uint32_t run = (nwc + nw - 1) / nw;
+      const uint32_t c0 = wid * run, c1 = min(c0 + run, nwc);
+      if (c0 < c1) run_wave<OPS, ITW, 4>(C, W, L.op_tab, c0 * WCH, min(c1 * WCH, S), nL);
+    } else {
+      const uint32_t nchunks = (S + kChunk - 1) / kChunk;
+      constexpr bool kGuided = (OPS & OPS_EXPAND) != 0;
+      const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
+      PendingFinish pend;
+      Prefetch<kChunk / WG> pf;
+      for (uint32_t turn = 0;; ++turn) {
+        uint32_t c0;
+        if (kGuided) {
+          if (threadIdx.x == 0) s_hdr[4] = add_agent(&H->chunk_ctr, run);
+          __syncthreads();
+          c0 = s_hdr[4];
+          __syncthreads();
+        } else {
+          c0 = turn == 0 ? blockIdx.x * run : nchunks;
+        }
+        if (c0 >= nchunks) break;
+        const uint32_t c1 = min(c0 + run, nchunks);
+        pf.w0 = 0xFFFFFFFFu;
+        for (uint32_t c = c0; c < c1; ++c)
+          run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, pf, c1 * kChunk, c != c0);
       }
-      if (c0 >= nchunks) break;
-      const uint32_t c1 = min(c0 + run, nchunks);
-      pf.w0 = 0xFFFFFFFFu;
-      for (uint32_t c = c0; c < c1; ++c)
-        run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, pf, c1 * kChunk, c != c0);
+      settle(C, pend);
     }
-    settle(C, pend);
     phase_mark(C, L, 6);
-    bool ok = grid_barrier<WG>(C, L, true, persistent != 0);
+    bool ok = grid_barrier<WG, NSL>(C, L, true, persistent != 0);
     if constexpr ((OPS & OPS_EXPAND) != 0) {
       if (persistent && ok) {
         if (threadIdx.x == 0) s_hdr[4] = (uint32_t)H->arc_phase;
@@ -1872,7 +2409,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
         __syncthreads();
         if (arcs) {
           arc_phase<WG, OPS>(C, L, V);
-          ok = grid_barrier<WG>(C, L, true, true);
+          ok = grid_barrier<WG, kChunk>(C, L, true, true);
         }
       }
     }
@@ -1908,7 +2445,7 @@ __global__ __launch_bounds__(WG) void k_arcs(DevCtx C) {
   if (L.flag) {
     if (threadIdx.x == 0) { fence_acquire(); st_agent(&H->arc_arrive, 0u); }
     __syncthreads();
-    schedule_scan_ext<WG>(C.self, &L, 1);
+    schedule_scan_ext<WG, kChunk>(C.self, &L, 1);
   }
 }
 
@@ -1919,7 +2456,7 @@ __global__ __launch_bounds__(WG) void k_scan(DevCtx C) {
   if (threadIdx.x < 8) C.hdr->grp[threadIdx.x].n = 0;
   if (threadIdx.x == 0) { C.hdr->arrive = 0; C.hdr->done_count = 0; C.hdr->stop_reason = 0; C.hdr->stamp0 = realtime(); }
   __syncthreads();
-  schedule_scan<WG>(C, L, false);
+  schedule_scan<WG, kChunk>(C, L, false);
 }
 
 // Admission: make staged trees live (root in entry 0 of the arena, epoch 0).

@@ -388,7 +388,7 @@ trees_status flush_admissions(trees_ctx *c) {
       HostTree &t = c->trees[a.slot];
       t.hstatus = H_LIVE;
       memset(&t.st, 0, sizeof(t.st));
-      t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 1; t.st.peak = 1;
+      t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 0; t.st.peak = 1;
       t.st.done_gepoch = -1; t.st.start_gepoch = -1;
     }
     c->staged.clear();
@@ -527,7 +527,7 @@ trees_status run_plain_tree(trees_ctx *c, int slot, int64_t *budget, uint64_t *g
       recs.push_back(TraceRec{st.epochs, st.cen, st.b, st.e, st.e - st.b, valid, forks, joins, nfc});
     st.epochs += 1;
     st.launched += st.e - st.b;
-    st.tasks += (int64_t)forks + joins;
+    st.tasks += valid;   // tasks executed in this epoch
     if (nfc > st.peak) st.peak = nfc;
     ++*gepochs;
     if (*budget > 0) --*budget;
@@ -1318,7 +1318,7 @@ trees_status trees_submit(trees_ctx *c, int32_t prog, const int64_t *args, int32
     c->ring_tail++;
     t.hstatus = H_LIVE;
     memset(&t.st, 0, sizeof(t.st));
-    t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 1; t.st.peak = 1;
+    t.st.e = 1; t.st.old = 1; t.st.status = TS_LIVE; t.st.tasks = 0; t.st.peak = 1;
     t.st.done_gepoch = -1; t.st.start_gepoch = -1;
   } else {
     stage(c, a);

@@ -78,7 +78,7 @@ struct alignas(64) TreeHot {
   int32_t nfc;        // nextFreeCore, arena-relative
   int32_t flags;      // TF_* error bits
   uint64_t done;      // items finished this epoch (low 32) | joins (high 32)
-  int32_t valid;      // valid tasks this epoch (trace only)
+  int32_t valid;      // valid tasks executed this epoch
   int32_t pad[11];
 };
 
@@ -90,7 +90,7 @@ struct alignas(128) TreeState {
   int32_t status;            // TS_*
   int32_t err;               // 0 or a trees_status error code
   int32_t epochs;            // epochs executed
-  int64_t tasks;             // valid task executions (root counted at submit)
+  int64_t tasks;             // valid task executions, counted per epoch
   int64_t launched;          // lanes launched over all epochs
   int64_t result;            // r[root] once done
   int64_t done_gepoch;       // global epoch at completion
