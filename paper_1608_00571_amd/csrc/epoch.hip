@@ -208,9 +208,18 @@ __device__ __forceinline__ int32_t child_base(const int32_t *seg_base, int seg, 
 
 // ---------------------------------------------------------------------------
 // Phase 3 + Phase 1 of one tree (device form).  Run by one lane of the
-// work-group that retired the tree's last work item of the epoch.
+// wavefront or work-group that retired the tree's last work item of the
+// epoch.  Returns the tree's next range (len 0: the tree is complete), which
+// the caller appends to the next epoch's work list.
 // ---------------------------------------------------------------------------
-__device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
+struct NextRange {
+  int32_t len = 0, cen = 0, b = 0;
+  uint32_t tb = 0, tp = 0;
+  int32_t nxt = 0;   // the work-list buffer the range goes to
+};
+
+__device__ NextRange tree_phase3(const DevCtx &C, int slot, uint32_t joins) {
+  NextRange out;
   TreeState *T = &C.st[slot];
   TreeHot *H = &C.hot[slot];
   const int32_t nfc = ld_agent(&H->nfc);
@@ -220,6 +229,9 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
   const int32_t forks = nfc - old;
   const int32_t valid = ld_agent(&H->valid);   // tasks executed this epoch (its share of the work)
   const int32_t ep = T->epochs;
+  out.nxt = ld_agent(&C.hdr->wsel) ^ 1;
+  out.tb = (uint32_t)(C.ts[slot].base >> 6);
+  out.tp = C.ts[slot].tp;
   T->epochs = ep + 1;
   T->launched += e - b;
   T->tasks += valid;
@@ -255,7 +267,7 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
     C.t_len[slot] = 0;
     int j = add_agent(&C.hdr->done_count, 1);
     C.done_list[j] = slot;
-    return;
+    return out;
   }
   // Phase 1 of the tree's next epoch: nextFreeCore returns to the value it
   // had when the popped range was pushed.
@@ -266,6 +278,31 @@ __device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
   C.t_len[slot] = top.z - top.y;
   C.t_cen[slot] = top.x;
   C.t_b[slot] = top.y;
+  out.len = top.z - top.y;
+  out.cen = top.x;
+  out.b = top.y;
+  return out;
+}
+
+// Entry k of work-list buffer n.nxt: the range n of tree `slot`, its items
+// starting at `off`.
+__device__ __forceinline__ void wl_put(const DevCtx &C, const NextRange &n, int slot, int k, uint32_t off) {
+  const size_t i = (size_t)n.nxt * (size_t)(C.tmax + 1) + (size_t)k;
+  C.wl_tree[i] = slot;
+  C.wl_off[i] = off;
+  C.wl_b[i] = n.b;
+  C.wl_cen[i] = n.cen;
+  C.wl_tb[i] = n.tb;
+  C.wl_tp[i] = n.tp;
+}
+
+// Phase 3 of one tree from one lane, its next range appended on its own.
+__device__ void tree_finish(const DevCtx &C, int slot, uint32_t joins) {
+  const NextRange n = tree_phase3(C, slot, joins);
+  if (n.len > 0) {
+    const uint64_t prev = add_agent(&C.hdr->wl_next, ((uint64_t)1 << kWlShift) | (uint64_t)n.len);
+    wl_put(C, n, slot, (int)(prev >> kWlShift), (uint32_t)(prev & kWlItemMask));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -538,7 +575,7 @@ struct Prefetch {
 template <int WG, uint32_t OPS, bool MULTI, typename VL, int NS, int IT>
 __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, uint32_t S, int32_t nL,
                           const PlainArgs &P, PendingFinish &pend, Prefetch<IT> &pf, uint32_t run_end,
-                          bool follows = false) {
+                          bool follows = false, uint32_t wo = 0) {
   static_assert(IT == kChunk / WG, "items per lane");
   static_assert(MULTI ? NS == kChunk : NS >= 1, "a batched chunk can touch kChunk trees");
   // the previous chunk already loaded this chunk's entries (same tree, same
@@ -571,25 +608,25 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
       while (hi - lo > 1) {
         const int step = (hi - lo + 63) >> 6;
         const int p = lo + tid * step;
-        const bool ok = p < hi && C.wl_off[p] <= w0;
+        const bool ok = p < hi && C.wl_off[wo + p] <= w0;
         const int j = __popcll(ballot64(ok)) - 1;
         lo = lo + j * step;
         hi = min(lo + step, hi);
       }
-      if (tid == 0) { L.kfirst = lo; L.off0 = C.wl_off[lo]; }
+      if (tid == 0) { L.kfirst = lo; L.off0 = C.wl_off[wo + lo]; }
     }
     __syncthreads();
     const int kf = L.kfirst;
     const uint32_t wl = min(w0 + (uint32_t)kChunk, S) - 1;   // the chunk's last item
     if (tid < 64) {
       const int e = kf + tid;
-      const uint32_t end = (e + 1 <= nL) ? C.wl_off[e + 1] : 0xFFFFFFFFu;
+      const uint32_t end = (e + 1 <= nL) ? C.wl_off[wo + e + 1] : 0xFFFFFFFFu;
       if (e < nL) {
-        L.seg_slot[tid] = C.wl_tree[e];
-        L.seg_cen[tid] = C.wl_cen[e];
-        L.seg_b[tid] = C.wl_b[e];
-        L.seg_tb[tid] = C.wl_tb[e];
-        L.seg_tp[tid] = C.wl_tp[e];
+        L.seg_slot[tid] = C.wl_tree[wo + e];
+        L.seg_cen[tid] = C.wl_cen[wo + e];
+        L.seg_b[tid] = C.wl_b[wo + e];
+        L.seg_tb[tid] = C.wl_tb[wo + e];
+        L.seg_tp[tid] = C.wl_tp[wo + e];
       }
       L.win[tid] = end;
       const int ended = __popcll(ballot64(end <= wl));   // entries that end inside the chunk
@@ -602,13 +639,13 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
         const int t = k * WG + tid;
         const int e = kf + t;
         if (t < 64) continue;
-        L.win[t] = (e + 1 <= nL) ? C.wl_off[e + 1] : 0xFFFFFFFFu;
+        L.win[t] = (e + 1 <= nL) ? C.wl_off[wo + e + 1] : 0xFFFFFFFFu;
         if (e < nL) {
-          L.seg_slot[t] = C.wl_tree[e];
-          L.seg_cen[t] = C.wl_cen[e];
-          L.seg_b[t] = C.wl_b[e];
-          L.seg_tb[t] = C.wl_tb[e];
-          L.seg_tp[t] = C.wl_tp[e];
+          L.seg_slot[t] = C.wl_tree[wo + e];
+          L.seg_cen[t] = C.wl_cen[wo + e];
+          L.seg_b[t] = C.wl_b[wo + e];
+          L.seg_tb[t] = C.wl_tb[wo + e];
+          L.seg_tp[t] = C.wl_tp[wo + e];
         }
       }
       __syncthreads();
@@ -622,8 +659,8 @@ __device__ void run_chunk(const DevCtx &C, Lds<WG, NS> &L, VL &V, uint32_t w0, u
     L.kfirst = 0; L.nseg = 1; L.off0 = 0; L.win[0] = S;
     if (MULTI) {
       if (!follows) {   // one tree in the work list: its data stays for the whole run
-        L.seg_slot[0] = C.wl_tree[0]; L.seg_cen[0] = C.wl_cen[0]; L.seg_b[0] = C.wl_b[0];
-        L.seg_tb[0] = C.wl_tb[0]; L.seg_tp[0] = C.wl_tp[0];
+        L.seg_slot[0] = C.wl_tree[wo + 0]; L.seg_cen[0] = C.wl_cen[wo + 0]; L.seg_b[0] = C.wl_b[wo + 0];
+        L.seg_tb[0] = C.wl_tb[wo + 0]; L.seg_tp[0] = C.wl_tp[wo + 0];
       }
     } else {
       L.seg_slot[0] = P.slot; L.seg_cen[0] = P.cen; L.seg_b[0] = P.b;
@@ -1226,14 +1263,28 @@ __device__ __forceinline__ void wave_sync() {
 __device__ void wave_retire(const DevCtx &C, WaveLds &W) {
   const int lane = lane_id();
   const uint32_t it = W.ritems[lane];
+  NextRange n;
+  const int sl = W.slot[lane];
   if (W.kfirst >= 0 && it > 0) {
     const uint32_t j = W.rjoins[lane];
     const int32_t v = (int32_t)W.rvalid[lane];
-    const int sl = W.slot[lane];
     const uint32_t beg = (lane == 0) ? W.beg0 : W.end[lane - 1];
     if (v) W.sink = add_agent(&C.hot[sl].valid, v);
     const uint64_t prev = add_agent(&C.hot[sl].done, ((uint64_t)j << 32) | it);
-    if ((uint32_t)prev + it == W.end[lane] - beg) tree_finish(C, sl, (uint32_t)(prev >> 32) + j);
+    if ((uint32_t)prev + it == W.end[lane] - beg) n = tree_phase3(C, sl, (uint32_t)(prev >> 32) + j);
+  }
+  // the trees this wavefront completed the epoch of: one append for all
+  // their next ranges
+  const uint64_t m = ballot64(n.len > 0);
+  if (m) {
+    const int incl = wave_incl_scan(n.len);
+    const uint32_t tot = (uint32_t)__shfl(incl, 63, 64);   // (every lane takes part in the shuffle)
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint64_t prev = 0;
+    if (lane == leader) prev = add_agent(&C.hdr->wl_next, ((uint64_t)__popcll(m) << kWlShift) | (uint64_t)tot);
+    prev = __shfl(prev, leader, 64);
+    if (n.len > 0)
+      wl_put(C, n, sl, (int)(prev >> kWlShift) + mbcnt64(m), (uint32_t)(prev & kWlItemMask) + (uint32_t)(incl - n.len));
   }
   W.ritems[lane] = 0;
   W.rjoins[lane] = 0;
@@ -1244,33 +1295,59 @@ __device__ void wave_retire(const DevCtx &C, WaveLds &W) {
 
 // Caches the 64 work-list entries from the one holding item w (a 64-ary
 // search of the entries' start offsets, then one round trip for the rest).
-__device__ void wave_locate(const DevCtx &C, WaveLds &W, uint32_t w, int32_t nL) {
+// wo: the current work-list buffer's first entry.
+__device__ void wave_locate(const DevCtx &C, WaveLds &W, uint32_t w, int32_t nL, uint32_t wo) {
   const int lane = lane_id();
+  const uint32_t *off = C.wl_off + wo;
   int lo = 0, hi = nL;
-  while (hi - lo > 1) {   // last entry whose start is <= w
+  while (hi - lo > 64) {   // last entry whose start is <= w
     const int step = (hi - lo + 63) >> 6;
     const int p = lo + lane * step;
-    const bool ok = p < hi && C.wl_off[p] <= w;
+    const bool ok = p < hi && off[p] <= w;
     lo = lo + (__popcll(ballot64(ok)) - 1) * step;
     hi = min(lo + step, hi);
   }
-  const int e = lo + lane;
-  W.end[lane] = (e + 1 <= nL) ? C.wl_off[e + 1] : 0xFFFFFFFFu;
+  // at most 64 candidates left: their starts and the entries after them
+  // come in one round trip
+  int e = lo + lane;
+  uint32_t beg = e < nL ? off[e] : 0xFFFFFFFFu;
+  uint32_t end = (e + 1 <= nL) ? off[e + 1] : 0xFFFFFFFFu;
+  int32_t sl = 0, ce = 0, bb = 0;
+  uint32_t tb = 0, tp = 0;
   if (e < nL) {
-    W.slot[lane] = C.wl_tree[e];
-    W.cen[lane] = C.wl_cen[e];
-    W.b[lane] = C.wl_b[e];
-    W.tb[lane] = C.wl_tb[e];
-    W.tp[lane] = C.wl_tp[e];
+    sl = C.wl_tree[wo + e]; ce = C.wl_cen[wo + e]; bb = C.wl_b[wo + e];
+    tb = C.wl_tb[wo + e]; tp = C.wl_tp[wo + e];
+  }
+  const int sh = __popcll(ballot64(e < nL && beg <= w)) - 1;   // the entry holding w, from lo
+  if (sh > 0) {
+    // cache from that entry on; the slots past the entries loaded repeat
+    // the last end, so no item maps to them (the next locate loads on)
+    const uint32_t end_last = __shfl(end, 63, 64);
+    const int src = min(lane + sh, 63);
+    beg = __shfl(beg, src, 64); end = __shfl(end, src, 64);
+    sl = __shfl(sl, src, 64); ce = __shfl(ce, src, 64); bb = __shfl(bb, src, 64);
+    tb = __shfl(tb, src, 64); tp = __shfl(tp, src, 64);
+    if (lane + sh > 63) end = end_last;
+    lo += sh;
+    e = lo + lane;
+  }
+  W.end[lane] = end;
+  if (e < nL) {
+    W.slot[lane] = sl;
+    W.cen[lane] = ce;
+    W.b[lane] = bb;
+    W.tb[lane] = tb;
+    W.tp[lane] = tp;
   }
   W.cnt[lane] = 0;
   W.jv[lane] = 0;
   W.ritems[lane] = 0;
   W.rjoins[lane] = 0;
   W.rvalid[lane] = 0;
+  const uint32_t b0 = __shfl(beg, 0, 64);
   if (lane == 0) {
     W.kfirst = lo;
-    W.beg0 = C.wl_off[lo];
+    W.beg0 = b0;
   }
   wave_sync();
 }
@@ -1542,7 +1619,8 @@ __device__ void wave_step_tree(const DevCtx &C, WaveLds &W, const uint8_t *op_ta
 // take one allocation atomic per tree.  Retirements are counted once per
 // tree when the run leaves the cached entries or ends.
 template <uint32_t OPS, int IT, int ITF>
-__device__ void run_wave(const DevCtx &C, WaveLds &W, const uint8_t *op_tab, uint32_t wa, uint32_t w1, int32_t nL) {
+__device__ void run_wave(const DevCtx &C, WaveLds &W, const uint8_t *op_tab, uint32_t wa, uint32_t w1, int32_t nL,
+                         uint32_t wo) {
   const int lane = lane_id();
   const int32_t ntt = C.ntt;
   constexpr bool kWide = (OPS & (OPS_NQ | OPS_MS)) != 0;
@@ -1550,7 +1628,7 @@ __device__ void run_wave(const DevCtx &C, WaveLds &W, const uint8_t *op_tab, uin
     // ---- the cached entries must hold item wa ------------------------------
     if (!(W.kfirst >= 0 && W.beg0 <= wa && wa < W.end[kWSeg - 1])) {
       wave_retire(C, W);
-      wave_locate(C, W, wa, nL);
+      wave_locate(C, W, wa, nL, wo);
     }
     const uint32_t beg0 = W.beg0;
     const uint32_t end63 = W.end[kWSeg - 1];
@@ -1702,7 +1780,7 @@ __device__ __forceinline__ bool needs_init(int kind) {
 // phase that precedes the next epoch's chunks.  Every thread of the scanning
 // work-group calls it.
 template <int WG, int NS>
-__device__ void adopt(const DevCtx &C, Lds<WG, NS> &L, int32_t *live, int *ctot, uint32_t *itot, int64_t g) {
+__device__ void adopt(const DevCtx &C, Lds<WG, NS> &L, uint32_t wo, int *ctot, uint32_t *itot, int64_t g) {
   SchedHdr *H = C.hdr;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -1739,8 +1817,7 @@ __device__ void adopt(const DevCtx &C, Lds<WG, NS> &L, int32_t *live, int *ctot,
     C.code[base] = a->root_code;
     C.a0[base] = a->a0; C.a1[base] = a->a1; C.a2[base] = a->a2; C.a3[base] = a->a3;
     C.r[base] = 0;
-    const int k = k0 + j;
-    live[k] = s;
+    const uint32_t k = wo + (uint32_t)(k0 + j);
     C.wl_tree[k] = s;
     C.wl_off[k] = *itot + (uint32_t)j;
     C.wl_b[k] = 0;
@@ -1852,60 +1929,65 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG, NS> &L, bool after_epoch)
       if (tid == 0) H->ctail = ct + (uint32_t)nd;
     }
   }
-  // Candidates: after an epoch, the trees of the last work list (a live
-  // tree always has a non-empty range); at the start of a run, every slot.
-  // Rounds of WG x R candidates: every load of a round is issued before any
+  // The next work list.  After an epoch it is complete already: each tree's
+  // Phase 3 appended its next range to the other buffer, so only the totals
+  // are read.  At the start of a run it is built here from every slot's
+  // range: rounds of WG x R slots, every load of a round issued before any
   // of its values is used, then one work-group scan places the round.
-  const int sel = H->live_sel;
-  const int32_t *src = C.live + (size_t)sel * C.tmax;
-  int32_t *dst = C.live + (size_t)(after_epoch ? (sel ^ 1) : 0) * C.tmax;
-  const int n = after_epoch ? H->live : H->tslots;
+  const int nb = after_epoch ? (H->wsel ^ 1) : 0;
+  const uint32_t wo = (uint32_t)nb * (uint32_t)(C.tmax + 1);
   const int64_t g = H->gepoch + (real ? 1 : 0);
-  constexpr int R = WG >= 1024 ? 1 : 1024 / WG;   // (bounded: registers of the epoch kernel)
   int ctot = 0;
   uint32_t itot = 0;
-  for (int base = 0; base < n; base += WG * R) {
-    int slot[R], len[R], b[R], cen[R];
-    int64_t tbase[R], sg[R];
-    uint32_t tp[R];
+  if (after_epoch) {
+    const uint64_t pk = ld_agent(&H->wl_next);
+    ctot = (int)(pk >> kWlShift);
+    itot = (uint32_t)(pk & kWlItemMask);
+  } else {
+    const int n = H->tslots;
+    constexpr int R = WG >= 1024 ? 1 : 1024 / WG;
+    for (int base = 0; base < n; base += WG * R) {
+      int slot[R], len[R], b[R], cen[R];
+      int64_t tbase[R], sg[R];
+      uint32_t tp[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int t = base + r * WG + tid;
-      slot[r] = t < n ? (after_epoch ? src[t] : t) : -1;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
-      if (slot[r] >= 0) {
-        const int s = slot[r];
-        len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
-        tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
+      for (int r = 0; r < R; ++r) {
+        const int t = base + r * WG + tid;
+        slot[r] = t < n ? t : -1;
       }
-    }
-    int cnt = 0, items = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (len[r] > 0) { ++cnt; items += len[r]; }
-    int rc, ri;
-    int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
-    uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
+      for (int r = 0; r < R; ++r) {
+        len[r] = 0; b[r] = 0; cen[r] = 0; tbase[r] = 0; tp[r] = 0; sg[r] = 0;
+        if (slot[r] >= 0) {
+          const int s = slot[r];
+          len[r] = C.t_len[s]; b[r] = C.t_b[s]; cen[r] = C.t_cen[s];
+          tbase[r] = C.ts[s].base; tp[r] = C.ts[s].tp; sg[r] = C.st[s].start_gepoch;
+        }
+      }
+      int cnt = 0, items = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (len[r] <= 0) continue;
-      const int s = slot[r];
-      dst[k] = s;
-      C.wl_tree[k] = s;
-      C.wl_off[k] = off;
-      C.wl_b[k] = b[r];
-      C.wl_tb[k] = (uint32_t)(tbase[r] >> 6);
-      C.wl_tp[k] = tp[r];
-      C.wl_cen[k] = cen[r];
-      if (sg[r] < 0) C.st[s].start_gepoch = g;
-      ++k;
-      off += (uint32_t)len[r];
+      for (int r = 0; r < R; ++r)
+        if (len[r] > 0) { ++cnt; items += len[r]; }
+      int rc, ri;
+      int k = ctot + wg_excl_scan<WG>(cnt, L.scan_tmp, &rc);
+      uint32_t off = itot + (uint32_t)wg_excl_scan<WG>(items, L.scan_tmp, &ri);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (len[r] <= 0) continue;
+        const int s = slot[r];
+        C.wl_tree[wo + k] = s;
+        C.wl_off[wo + k] = off;
+        C.wl_b[wo + k] = b[r];
+        C.wl_tb[wo + k] = (uint32_t)(tbase[r] >> 6);
+        C.wl_tp[wo + k] = tp[r];
+        C.wl_cen[wo + k] = cen[r];
+        if (sg[r] < 0) C.st[s].start_gepoch = g;
+        ++k;
+        off += (uint32_t)len[r];
+      }
+      ctot += rc;
+      itot += (uint32_t)ri;
     }
-    ctot += rc;
-    itot += (uint32_t)ri;
   }
   // Asynchronous run.  The work list now holds only live trees, so the slots
   // of the trees that finished this epoch may be handed back: their
@@ -1923,7 +2005,7 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG, NS> &L, bool after_epoch)
     }
     __syncthreads();
     for (;;) {
-      adopt<WG, NS>(C, L, dst, &ctot, &itot, g);
+      adopt<WG, NS>(C, L, wo, &ctot, &itot, g);
       if (ctot > 0 || merges) break;
       // Nothing live: wait for a submission, the close request or an abort,
       // for at most one slice; then run an empty epoch (every work-group
@@ -1961,8 +2043,9 @@ __device__ void schedule_scan(const DevCtx &C, Lds<WG, NS> &L, bool after_epoch)
     st_agent(&H->arc_segs, 0u);
     st_agent(&H->arc_next, 0u);
     H->arc_phase = 0;
-    H->live_sel = after_epoch ? (sel ^ 1) : 0;
-    C.wl_off[ctot] = (uint32_t)itot;
+    H->wsel = nb;
+    st_agent(&H->wl_next, (uint64_t)0);   // the following epoch appends to the other buffer
+    C.wl_off[wo + ctot] = (uint32_t)itot;
     H->S = (uint32_t)itot;
     H->L = ctot;
     H->live = ctot;
@@ -2306,10 +2389,14 @@ __device__ __noinline__ void map_merge_call(const uint32_t *part_job, const int6
 template <int WG, uint32_t OPS>
 __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   constexpr bool kMap = (OPS & opbit(OP_MERGE)) != 0;
-  // programs without the co-operative expansion sweep one chunk per
-  // wavefront; the others one chunk per work-group
-  constexpr bool kWave = (OPS & OPS_EXPAND) == 0;
-  constexpr int NSL = kWave ? 1 : kChunk;   // segments the work-group's LDS caches
+  // programs without the co-operative expansion or merge sort can sweep one
+  // chunk per wavefront (chosen per epoch, see below); the others sweep one
+  // chunk per work-group (their leaf sorts and merges want the registers)
+  constexpr bool kWave = (OPS & (OPS_EXPAND | OPS_MS)) == 0;
+  // (256-lane work-groups sweep by wavefronts only: their work-group sweep
+  // holds four items per lane and would spill)
+  constexpr bool kGroupSweep = !kWave || WG >= 512;
+  constexpr int NSL = kGroupSweep ? kChunk : 1;   // segments the work-group's LDS caches
   using MapL = typename std::conditional<kMap, MapLds<kMapTile>, NoMapLds>::type;
   using VL = typename std::conditional<(OPS & OPS_EXPAND) != 0, VisitLds, NoVisitLds>::type;
   using WLT = typename std::conditional<kWave, WaveLds, NoWaveLds>::type;
@@ -2317,7 +2404,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   __shared__ MapL M;
   __shared__ VL V;
   __shared__ WLT WLs[kWave ? WG / 64 : 1];
-  __shared__ uint32_t s_hdr[6];
+  __shared__ uint32_t s_hdr[8];
   lds_init(C, L);
   if (threadIdx.x == 0) L.tflag = 0;
   if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
@@ -2328,10 +2415,12 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     if (threadIdx.x == 0) {
       s_hdr[0] = H->S; s_hdr[1] = (uint32_t)H->L; s_hdr[2] = (uint32_t)H->stop; s_hdr[3] = H->mapJ;
       s_hdr[5] = (uint32_t)H->initN;
+      s_hdr[6] = (uint32_t)H->wsel;
     }
     __syncthreads();
     const uint32_t S = s_hdr[0];
     const int32_t nL = (int32_t)s_hdr[1];
+    const uint32_t wo = s_hdr[6] * (uint32_t)(C.tmax + 1);   // the current work-list buffer
     const bool stop = s_hdr[2] != 0;
     const uint32_t mapJ = persistent ? s_hdr[3] : 0u;
     // trees adopted by an asynchronous run's last scan: their buffers are
@@ -2361,21 +2450,27 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     // shared counter, guided: a run is about a quarter of an even share, so
     // a work-group that drew expensive chunks takes fewer.  The others take
     // one even share each.
-    if constexpr (kWave) {
-      // every wavefront takes an even share of wavefront chunks (64 * ITW
-      // items), consecutive wavefronts consecutive shares
-      constexpr int ITW = 2;
-      constexpr uint32_t WCH = 64 * ITW;
-      const uint32_t nw = gridDim.x * (WG / 64);
-      const uint32_t wid = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
-      WaveLds &W = WLs[threadIdx.x >> 6];
-      if (lane_id() == 0) W.kfirst = -1;   // (a new work list every epoch)
-      wave_sync();
-      const uint32_t nwc = (S + WCH - 1) / WCH;
-      const uint32_t run = (nwc + nw - 1) / nw;
-      const uint32_t c0 = wid * run, c1 = min(c0 + run, nwc);
-      if (c0 < c1) run_wave<OPS, ITW, 4>(C, W, L.op_tab, c0 * WCH, min(c1 * WCH, S), nL);
-    } else {
+    // The wavefront sweep takes one allocation and one retirement atomic per
+    // wavefront and tree; when many wavefronts share a tree, those atomics
+    // on the tree's counters serialize, and the work-group sweep (one per
+    // 1024 items) is faster.  So: wavefronts while the wavefronts that get
+    // work number at most four per live tree, work-groups otherwise.
+    // (a wavefront's share: an even split of the items, at least 64)
+    const uint32_t nw = gridDim.x * (WG / 64);
+    const uint32_t share = max(64u, (S + nw - 1) / nw);
+    bool wave_sweep = false;
+    if constexpr (kWave) wave_sweep = !kGroupSweep || (S + share - 1) / share <= 4u * (uint32_t)nL;
+    if (wave_sweep) {
+      if constexpr (kWave) {
+        // consecutive wavefronts take consecutive shares
+        const uint32_t wid = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+        WaveLds &W = WLs[threadIdx.x >> 6];
+        if (lane_id() == 0) W.kfirst = -1;   // (a new work list every epoch)
+        wave_sync();
+        const uint64_t w0 = (uint64_t)wid * share, w1 = w0 + share < S ? w0 + share : S;
+        if (w0 < S) run_wave<OPS, 2, 4>(C, W, L.op_tab, (uint32_t)w0, (uint32_t)w1, nL, wo);
+      }
+    } else if constexpr (kGroupSweep) {
       const uint32_t nchunks = (S + kChunk - 1) / kChunk;
       constexpr bool kGuided = (OPS & OPS_EXPAND) != 0;
       const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
@@ -2395,7 +2490,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
         const uint32_t c1 = min(c0 + run, nchunks);
         pf.w0 = 0xFFFFFFFFu;
         for (uint32_t c = c0; c < c1; ++c)
-          run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, pf, c1 * kChunk, c != c0);
+          run_chunk<WG, OPS, true>(C, L, V, c * kChunk, S, nL, P, pend, pf, c1 * kChunk, c != c0, wo);
       }
       settle(C, pend);
     }
@@ -2489,13 +2584,15 @@ __global__ void k_release(DevCtx C, int32_t slot) {
   M(WG, OPS_NQ)                   \
   M(WG, OPS_FIB | OPS_NQ)         \
   M(WG, OPS_MS)                   \
+  M(WG, OPS_FIB | OPS_MS)         \
   M(WG, OPS_GRAPH)                \
   M(WG, OPS_FFT)                  \
   M(WG, OPS_PO)                   \
   M(WG, OPS_ALL)
 
 static uint32_t pick_ops(uint32_t need) {
-  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_GRAPH, OPS_FFT, OPS_PO, OPS_ALL};
+  const uint32_t sets[] = {OPS_FIB, OPS_NQ, OPS_FIB | OPS_NQ, OPS_MS, OPS_FIB | OPS_MS, OPS_GRAPH, OPS_FFT, OPS_PO,
+                          OPS_ALL};
   for (uint32_t s : sets)
     if ((need & ~s) == 0) return s;
   return OPS_ALL;

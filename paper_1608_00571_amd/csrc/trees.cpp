@@ -595,7 +595,8 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs, bool async = false) {
   c->hdr_host->tslots = c->tslots;
   c->hdr_host->arrive = 0;
   for (int g = 0; g < 8; ++g) c->hdr_host->grp[g].n = 0;
-  c->hdr_host->live_sel = 0;
+  c->hdr_host->wsel = 0;
+  c->hdr_host->wl_next = 0;
   c->hdr_host->mapJ = 0;
   c->hdr_host->map_ctr = 0;
   c->hdr_host->map_arrive = 0;
@@ -1001,10 +1002,10 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   const size_t o_ts = take(T * sizeof(TreeStatic)), o_st = take(T * sizeof(TreeState)),
                o_hot = take(T * sizeof(TreeHot)), o_len = take(T * 4), o_cen = take(T * 4),
                o_b = take(T * 4), o_stk = take(T * kStackMax * sizeof(int4)),
-               o_tr = trace ? take(T * kTraceMax * sizeof(TraceRec)) : 0, o_wt = take((T + 1) * 4),
-               o_wo = take((T + 1) * 4), o_ws = take((T + 1) * 4), o_wc = take((T + 1) * 4),
-               o_wtb = take((T + 1) * 4), o_wtp = take((T + 1) * 4),
-               o_dl = take(T * 4), o_lv = take(2 * T * 4), o_hdr = take(sizeof(SchedHdr)),
+               o_tr = trace ? take(T * kTraceMax * sizeof(TraceRec)) : 0, o_wt = take(2 * (T + 1) * 4),
+               o_wo = take(2 * (T + 1) * 4), o_ws = take(2 * (T + 1) * 4), o_wc = take(2 * (T + 1) * 4),
+               o_wtb = take(2 * (T + 1) * 4), o_wtp = take(2 * (T + 1) * 4),
+               o_dl = take(T * 4), o_hdr = take(sizeof(SchedHdr)),
                o_pl = take(sizeof(PlainCounters)),
                o_adm = take(T * sizeof(Admit)), o_init = take(T * 4), o_self = take(2 * sizeof(DevCtx));
   const bool nomap = (cfg->flags & TREES_F_NOMAP) != 0;
@@ -1034,7 +1035,6 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   c->dc.wl_tp = (uint32_t *)(b + o_wtp);
   c->dc.wl_cen = (int32_t *)(b + o_wc);
   c->dc.done_list = (int32_t *)(b + o_dl);
-  c->dc.live = (int32_t *)(b + o_lv);
   c->dc.tmax = (int32_t)T;
   c->dc.hdr = (SchedHdr *)(b + o_hdr);
   c->dc.plain = (PlainCounters *)(b + o_pl);

@@ -126,8 +126,13 @@ struct SchedHdr {
   alignas(128) uint32_t arrive;   // barrier arrivals of the last work-group of each group
   int32_t pad1[31];
   struct alignas(128) Grp { uint32_t n; int32_t pad[31]; } grp[8];   // per-group arrivals (blockIdx % 8)
-  int32_t live_sel;               // which half of the live-tree list is current
+  int32_t wsel;                   // which of the two work-list buffers is current
   int32_t pad4[31];
+  // Appends to the next epoch's work list: (entries << kWlShift) | items.
+  // A tree's Phase 3 appends its next range; the end-of-epoch scan reads
+  // the total and clears it.
+  alignas(128) uint64_t wl_next;
+  int32_t pad9[30];
   alignas(128) uint32_t gen;      // barrier generation
   int32_t pad2[31];
   alignas(128) uint64_t map_ctr;  // (jobs << 38) | units, appended during an epoch
@@ -154,6 +159,10 @@ constexpr int kEpochStamps = 256;
 // 38 bits) so one atomic add per work-group reserves both, and job indices
 // and unit offsets grow in the same order.
 constexpr int kMapShift = 38;
+// The work-list append counter: entries in the high 24 bits, items in the
+// low 40 (entry indices and item offsets grow in the same order).
+constexpr int kWlShift = 40;
+constexpr uint64_t kWlItemMask = (1ull << kWlShift) - 1;
 constexpr uint64_t kMapUnitMask = (1ull << kMapShift) - 1;
 
 // Counters used by the plain scheduler (double-buffered by epoch parity, so
@@ -248,6 +257,8 @@ struct DevCtx {
   int32_t *t_len, *t_cen, *t_b;   // next-epoch range per tree (finisher -> scan)
   int4 *stack;                    // [slot * kStackMax + k] = {cen, b, e, cend}
   TraceRec *trace;                // [slot * kTraceMax + k] or null
+  // Work list, two buffers of tmax + 1 entries each (hdr->wsel: the
+  // current one; the epoch's Phase 3 appends the next epoch's to the other)
   int32_t *wl_tree;               // work list: tree slot
   uint32_t *wl_off;               // exclusive prefix of range lengths (L+1 entries)
   int32_t *wl_b;                  // arena-relative range start
@@ -255,7 +266,6 @@ struct DevCtx {
   uint32_t *wl_tb;                // arena base / 64 (arenas are 64-entry aligned)
   uint32_t *wl_tp;                // the tree's first type id | program parameter << 8 (nqueens n)
   int32_t *done_list;             // trees finished in this epoch
-  int32_t *live;                  // 2 x tmax: live tree slots in work-list order (double buffer)
   int32_t tmax;
   int32_t pad3;
   SchedHdr *hdr;
