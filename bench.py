@@ -47,24 +47,24 @@ def log(msg: str):
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "6ac319ee73aa2102", "fetch_bytes": 68792867, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "2e2c90353acff024", "fetch_bytes": 2830514, "write_bytes": 3504698},
-    "k_plain<MS>": {"src": "2e2c90353acff024", "fetch_bytes": 2243764, "write_bytes": 2354595},
-    # one graph-form run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "2e2c90353acff024", "wg": 512, "fetch_bytes": 10429604027,
-                         "write_bytes": 12474202208},
+    "k_map_merge<1024,8192>": {"src": "1dd4525b884bc9b4", "fetch_bytes": 68794488, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "8b63fa4c5a3687c5", "fetch_bytes": 2817291, "write_bytes": 3510559},
+    "k_plain<MS>": {"src": "8b63fa4c5a3687c5", "fetch_bytes": 2245314, "write_bytes": 2355284},
+    # one persistent run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
+    "k_epochs<FIB|NQ>": {"src": "8b63fa4c5a3687c5", "wg": 512, "fetch_bytes": 10745043328,
+                         "write_bytes": 12770182048},
     # one graph-form run of the 64-graph BFS batch, k_epochs and k_arcs together
     # (profiles/batched_64rmat_bfs.md)
-    "k_epochs<GRAPH> bfs": {"src": "2e2c90353acff024", "wg": 512, "fetch_bytes": 19532886380 + 79275849928,
-                            "write_bytes": 463671200 + 2487117888},
+    "k_epochs<GRAPH> bfs": {"src": "8b63fa4c5a3687c5", "wg": 512, "fetch_bytes": 100305001344,
+                            "write_bytes": 2950777440},
     # one persistent run of the FFT batch (64 x 2^18), one k_epochs dispatch
     # (profiles/fft_64x2e18_and_2e20.md)
-    "k_epochs<FFT> batch": {"src": "2e2c90353acff024", "wg": 1024, "fetch_bytes": 1963832719,
-                            "write_bytes": 1764480576},
+    "k_epochs<FFT> batch": {"src": "8b63fa4c5a3687c5", "wg": 1024, "fetch_bytes": 1963848448,
+                            "write_bytes": 1764610816},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "2e2c90353acff024", "wg": 512, "fetch_bytes": 180044801134 + 141456997183,
-                             "write_bytes": 3365986048 + 4415063936},
+    "k_epochs<GRAPH> sssp": {"src": "8b63fa4c5a3687c5", "wg": 512, "fetch_bytes": 174030602496 + 144184864768,
+                             "write_bytes": 3282589056 + 4403164768},
 }
 
 
@@ -675,12 +675,18 @@ def bfs_block(ngraphs: int = 64, wg: int = 512, reps: int = 3, scheds=("graph", 
     b = forms[best]
     ach = (tv + payload) / (b["ms"] * 1e-3) / 1e9
     lines = (tv + payload + 60 * scanned) / (b["ms"] * 1e-3) / 1e9   # a depth probe moves a 64-B sector
+    m = MEASURED_TRAFFIC["k_epochs<GRAPH> bfs"]
+    traffic = traffic_for("k_epochs<GRAPH> bfs", 0) if (best == "graph" and wg == m["wg"]) else None
     out["roofline"] = {"bound": "hbm", "kernel": f"k_epochs<GRAPH> + k_arcs ({best}, wg {wg})",
                        "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(ach / HBM_PEAK_GBS, 4), "tv_bytes": tv, "payload_bytes": payload,
+                       "traffic": traffic,
+                       "traffic_from": "rocprofv3 FETCH_SIZE + WRITE_SIZE of k_epochs and k_arcs per graph-form "
+                                       "run, work-groups of 512 (profiles/batched_64rmat_bfs.md)",
                        "what": "algorithmic bytes (task-vector + graph payload) over the run's wall time",
                        "waste": {"note": "random 4-B depth probes move whole 64-B sectors",
-                                 "line_traffic_GBps": round(lines, 1)}}
+                                 "line_traffic_GBps": round(lines, 1),
+                                 "traffic_over_algorithmic": round(traffic / (tv + payload), 2) if traffic else None}}
     out["checked"] = "every depth against the oracle's queue BFS; tasks = reached, epochs = max depth + 1"
     return out
 
