@@ -59,6 +59,7 @@ struct Lds {
   int32_t sink;            // destination of atomics whose completion must be awaited
   int32_t tflag;
   int32_t sflag, scnt;     // work-list scan: broadcast and counter (adoption)
+  uint32_t hdr[6];         // header of the next epoch (S, L, stop, mapJ, initN, wsel), for a solo epoch
   uint32_t jbase;          // first map job reserved by this work-group
   uint64_t ubase;          // first map unit reserved by this work-group
   int64_t tprof;           // debug: clock at the last phase boundary
@@ -2294,10 +2295,40 @@ __device__ void arc_phase(const DevCtx &C, Lds<WG> &L, VisitLds &V) {
 // last arriver optionally runs the work-list scan and opens the barrier.
 // Leaving, one thread invalidates the CU's and XCD's caches (an acquire).
 // wait = false (graph form): the others return at once, the kernel
-// boundary is their barrier.  Returns false if this work-group gave up
-// waiting after the spin limit.
+// boundary is their barrier.  Returns 0 if this work-group gave up waiting
+// after the spin limit, 2 if it is the last arriver and keeps the barrier
+// closed to run the next epoch alone (SOLO: the largest such epoch, 0:
+// never), 1 otherwise.
+// Whether the next epoch (its work list just built) can run in this
+// work-group alone: at most `kMax` items, and nothing in it that needs the
+// grid (merges of the map phase, buffers of adopted trees to initialise).
+// Thread 0 decides; the answer is in L.flag2.
+template <uint32_t kMax, int WG, int NS>
+__device__ __forceinline__ void solo_decide(const DevCtx &C, Lds<WG, NS> &L) {
+  if (threadIdx.x == 0) {
+    const SchedHdr *H = C.hdr;
+    const uint32_t S = H->S, nL = (uint32_t)H->L, stop = (uint32_t)ld_agent(&H->stop), mapJ = H->mapJ,
+                   initN = (uint32_t)H->initN, wsel = (uint32_t)H->wsel;
+    L.hdr[0] = S; L.hdr[1] = nL; L.hdr[2] = stop; L.hdr[3] = mapJ; L.hdr[4] = initN; L.hdr[5] = wsel;
+    L.flag2 = (kMax > 0 && stop == 0 && mapJ == 0 && initN == 0 && S > 0 && S <= kMax) ? 1 : 0;
+  }
+  __syncthreads();
+}
+
+// The release that opens the barrier (its arrival counter cleared first).
 template <int WG, int NS>
-__device__ bool grid_barrier(const DevCtx &C, Lds<WG, NS> &L, bool with_scan, bool wait) {
+__device__ __forceinline__ void barrier_release(const DevCtx &C, Lds<WG, NS> &L) {
+  wait_vmem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st_agent(&C.hdr->arrive, 0u);
+    fence_release();
+    __hip_atomic_store(&C.hdr->gen, L.gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int WG, int NS, uint32_t SOLO = 0>
+__device__ int grid_barrier(const DevCtx &C, Lds<WG, NS> &L, bool with_scan, bool wait) {
   SchedHdr *H = C.hdr;
   wait_vmem();
   __syncthreads();
@@ -2334,15 +2365,15 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG, NS> &L, bool with_scan, bo
         if (threadIdx.x == 0) H->arc_phase = 1;
       } else {
         schedule_scan_ext<WG, NS>(C.self, &L, 1);
+        if constexpr (SOLO > 0) {
+          // a narrow next epoch: this work-group runs it alone and keeps the
+          // barrier closed meanwhile (k_epochs)
+          solo_decide<SOLO>(C, L);
+          if (L.flag2) return 2;
+        }
       }
     }
-    wait_vmem();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      st_agent(&H->arrive, 0u);
-      fence_release();
-      __hip_atomic_store(&H->gen, L.gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    barrier_release<WG, NS>(C, L);
   } else if (wait) {
     if (threadIdx.x == 0) {
       const int64_t t0 = realtime();
@@ -2358,11 +2389,11 @@ __device__ bool grid_barrier(const DevCtx &C, Lds<WG, NS> &L, bool with_scan, bo
       }
     }
     __syncthreads();
-    if (L.tflag) return false;
+    if (L.tflag) return 0;
   }
   if (threadIdx.x == 0) fence_acquire();
   __syncthreads();
-  return true;
+  return 1;
 }
 
 // Batched form.  persistent != 0: a co-resident grid loops over epochs with
@@ -2405,6 +2436,16 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   __shared__ VL V;
   __shared__ WLT WLs[kWave ? WG / 64 : 1];
   __shared__ uint32_t s_hdr[8];
+  // Narrow epochs run in one work-group: the last arriver at an epoch's
+  // barrier that finds the next epoch small (at most kSolo items; for a
+  // wavefront sweep one step of 256 items a wavefront) and free of merges,
+  // buffer initialisation and arc expansion runs it alone while the rest of
+  // the grid waits at the barrier (persistent) or has ended (graph), then the
+  // next one, and opens the barrier when an epoch needs the grid again.  Such
+  // an epoch costs one work-group's round trips instead of a grid barrier's.
+  constexpr uint32_t kSolo = (OPS & OPS_EXPAND) != 0 ? 0u
+                             : (OPS & OPS_MS) != 0 ? 2u * (uint32_t)kChunk : (uint32_t)WG * 4u;
+  bool solo = false;   // (uniform in the work-group)
   lds_init(C, L);
   if (threadIdx.x == 0) L.tflag = 0;
   if (threadIdx.x < 8) L.prof[threadIdx.x] = 0;
@@ -2413,9 +2454,14 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
   const PlainArgs P{};
   while (true) {
     if (threadIdx.x == 0) {
-      s_hdr[0] = H->S; s_hdr[1] = (uint32_t)H->L; s_hdr[2] = (uint32_t)H->stop; s_hdr[3] = H->mapJ;
-      s_hdr[5] = (uint32_t)H->initN;
-      s_hdr[6] = (uint32_t)H->wsel;
+      if (solo) {   // (the header this work-group's last scan wrote)
+        s_hdr[0] = L.hdr[0]; s_hdr[1] = L.hdr[1]; s_hdr[2] = L.hdr[2]; s_hdr[3] = L.hdr[3];
+        s_hdr[5] = L.hdr[4]; s_hdr[6] = L.hdr[5];
+      } else {
+        s_hdr[0] = H->S; s_hdr[1] = (uint32_t)H->L; s_hdr[2] = (uint32_t)H->stop; s_hdr[3] = H->mapJ;
+        s_hdr[5] = (uint32_t)H->initN;
+        s_hdr[6] = (uint32_t)H->wsel;
+      }
     }
     __syncthreads();
     const uint32_t S = s_hdr[0];
@@ -2456,14 +2502,16 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     // 1024 items) is faster.  So: wavefronts while the wavefronts that get
     // work number at most four per live tree, work-groups otherwise.
     // (a wavefront's share: an even split of the items, at least 64)
-    const uint32_t nw = gridDim.x * (WG / 64);
+    // (a work-group that runs the epoch alone is the only part)
+    const uint32_t nparts = solo ? 1u : gridDim.x, part = solo ? 0u : blockIdx.x;
+    const uint32_t nw = nparts * (WG / 64);
     const uint32_t share = max(64u, (S + nw - 1) / nw);
     bool wave_sweep = false;
     if constexpr (kWave) wave_sweep = !kGroupSweep || (S + share - 1) / share <= 4u * (uint32_t)nL;
     if (wave_sweep) {
       if constexpr (kWave) {
         // consecutive wavefronts take consecutive shares
-        const uint32_t wid = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+        const uint32_t wid = part * (WG / 64) + (threadIdx.x >> 6);
         WaveLds &W = WLs[threadIdx.x >> 6];
         if (lane_id() == 0) W.kfirst = -1;   // (a new work list every epoch)
         wave_sync();
@@ -2473,7 +2521,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
     } else if constexpr (kGroupSweep) {
       const uint32_t nchunks = (S + kChunk - 1) / kChunk;
       constexpr bool kGuided = (OPS & OPS_EXPAND) != 0;
-      const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + gridDim.x - 1) / gridDim.x;
+      const uint32_t run = kGuided ? max(1u, nchunks / (4u * gridDim.x)) : (nchunks + nparts - 1) / nparts;
       PendingFinish pend;
       Prefetch<kChunk / WG> pf;
       for (uint32_t turn = 0;; ++turn) {
@@ -2484,7 +2532,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
           c0 = s_hdr[4];
           __syncthreads();
         } else {
-          c0 = turn == 0 ? blockIdx.x * run : nchunks;
+          c0 = turn == 0 ? part * run : nchunks;
         }
         if (c0 >= nchunks) break;
         const uint32_t c1 = min(c0 + run, nchunks);
@@ -2495,7 +2543,21 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
       settle(C, pend);
     }
     phase_mark(C, L, 6);
-    bool ok = grid_barrier<WG, NSL>(C, L, true, persistent != 0);
+    bool ok = true;
+    if (solo) {
+      // this work-group ran the epoch alone: the next work list, then the
+      // next epoch alone too, or the barrier opened for the grid
+      wait_vmem();
+      __syncthreads();
+      schedule_scan_ext<WG, NSL>(C.self, &L, 1);
+      solo_decide<kSolo>(C, L);
+      solo = L.flag2 != 0;
+      if (!solo) barrier_release<WG, NSL>(C, L);
+    } else {
+      const int r = grid_barrier<WG, NSL, kSolo>(C, L, true, persistent != 0);
+      ok = r != 0;
+      solo = r == 2;
+    }
     if constexpr ((OPS & OPS_EXPAND) != 0) {
       if (persistent && ok) {
         if (threadIdx.x == 0) s_hdr[4] = (uint32_t)H->arc_phase;
@@ -2509,7 +2571,7 @@ __global__ __launch_bounds__(WG) void k_epochs(DevCtx C, int32_t persistent) {
       }
     }
     phase_mark(C, L, 7);
-    if (!persistent || !ok) break;
+    if (!ok || (!persistent && !solo)) break;
   }
   if (C.debug && threadIdx.x == 0)
     for (int ph = 0; ph < 8; ++ph) add_agent(&H->phase[ph], (uint64_t)L.prof[ph]);
