@@ -1866,8 +1866,11 @@ __device__ void run_inits(const DevCtx &C, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Work-list construction (the serial part of Phase 1 over all trees): an
-// exclusive scan of the per-tree range lengths.  One work-group.
+// End of an epoch (one work-group): the results of trees that finished, the
+// totals of the next work list (appended during the epoch by the trees'
+// Phase 3; at the start of a run, an exclusive scan of every slot's range
+// length builds it here), adoption of submitted trees in an asynchronous
+// run, and the header of the next epoch.
 // ---------------------------------------------------------------------------
 template <int WG, int NS>
 __device__ void schedule_scan(const DevCtx &C, Lds<WG, NS> &L, bool after_epoch) {
