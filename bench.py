@@ -985,7 +985,7 @@ class ServingCheck:
         return tasks
 
 
-def serving_block(n: int = 600, n_warm: int = 60, arena_gib: int = 16, wg: int = 512, loads=(0.5, 0.8),
+def serving_block(n: int = 600, n_warm: int = 60, arena_gib: int = 16, wg: int = 1024, loads=(0.5, 0.8),
                   modes=("async", "bursts"), burst: int = 4):
     """The serving configuration: Poisson arrivals of the 40/40/20 fib /
     msort / BFS mix (fib(12..30), msort of 2^10..2^22 keys, R-MAT BFS of
@@ -1169,8 +1169,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--sched", default="plain")
     ap.add_argument("--wg", type=int, default=0,
-                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler and the FFT "
-                         "configuration, 512 for BFS, SSSP, serving and the traversals, 256 otherwise)")
+                    help="epoch-kernel work-group size (default: 1024 for the plain scheduler, the FFT "
+                         "configuration and serving, 512 for BFS, SSSP and the traversals, 256 otherwise)")
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--log2tree", type=int, default=22, help="config 6: postorder tree of 2^k nodes")
     ap.add_argument("--sssp-deltas", type=lambda t: [int(x) for x in t.split(",") if x], default=[],
@@ -1194,8 +1194,9 @@ def main():
     ap.add_argument("--calib-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.wg == 0:
-        args.wg = (1024 if args.config in (1, 2, 8) and (args.sched == "plain" or args.config == 8)
-                   else 512 if args.config in (4, 5, 6, 7) else 256)
+        args.wg = (1024 if (args.config in (1, 2, 8) and (args.sched == "plain" or args.config == 8))
+                   or args.config == 5
+                   else 512 if args.config in (4, 6, 7) else 256)
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent trees would shard by tree, one context per GPU)", file=sys.stderr)
@@ -1230,7 +1231,7 @@ def main():
             log("batch block done")
             line["bfs"] = bfs_block(wg=512)
             log("bfs block done")
-            line["serving"] = serving_block(wg=512)
+            line["serving"] = serving_block(wg=1024)
             log("serving block done")
     else:
         print(f"bench.py: --config {args.config} is not wired", file=sys.stderr)

@@ -80,7 +80,7 @@ class Server:
     two modes)."""
 
     def __init__(self, arena_bytes: int, *, mode: str = "async", sched: str = "persistent", burst: int = 8,
-                 skip_ahead: int = 8, payload_budget: int = 16 << 30, wg: int = 512, max_trees: int = 4096,
+                 skip_ahead: int = 8, payload_budget: int = 16 << 30, wg: int = 1024, max_trees: int = 4096,
                  timeout_s: float = 60.0):
         import torch
         if mode not in ("async", "bursts"):

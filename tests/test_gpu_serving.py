@@ -92,7 +92,7 @@ def test_serving_stated_sizes(realtime):
     kinds = {j.kind for j in jobs}
     assert kinds == {"fib", "msort", "bfs"}
     assert max(j.args[0] for j in jobs if j.kind == "fib") >= 25
-    srv = Server(32 << 30, mode="async", payload_budget=32 << 30, wg=512, timeout_s=30.0)
+    srv = Server(32 << 30, mode="async", payload_budget=32 << 30, wg=1024, timeout_s=30.0)
     try:
         res = srv.serve(jobs, realtime=realtime)
     finally:
