@@ -47,23 +47,23 @@ def log(msg: str):
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "1dd4525b884bc9b4", "fetch_bytes": 68794581, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "4dc8a827326a2858", "fetch_bytes": 2817242, "write_bytes": 3510457},
-    "k_plain<MS>": {"src": "4dc8a827326a2858", "fetch_bytes": 2245312, "write_bytes": 2355262},
+    "k_map_merge<1024,8192>": {"src": "a3c1221125ea595c", "fetch_bytes": 68794581, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "01c3d1775ef2aa70", "fetch_bytes": 2817242, "write_bytes": 3510457},
+    "k_plain<MS>": {"src": "01c3d1775ef2aa70", "fetch_bytes": 2245312, "write_bytes": 2355262},
     # one persistent run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
-    "k_epochs<FIB|NQ>": {"src": "4dc8a827326a2858", "wg": 512, "fetch_bytes": 10744039680,
+    "k_epochs<FIB|NQ>": {"src": "01c3d1775ef2aa70", "wg": 512, "fetch_bytes": 10744039680,
                          "write_bytes": 12770263712},
     # one graph-form run of the 64-graph BFS batch, k_epochs and k_arcs together
     # (profiles/batched_64rmat_bfs.md)
-    "k_epochs<GRAPH> bfs": {"src": "4dc8a827326a2858", "wg": 512, "fetch_bytes": 19833428352 + 81570876928,
+    "k_epochs<GRAPH> bfs": {"src": "01c3d1775ef2aa70", "wg": 512, "fetch_bytes": 19833428352 + 81570876928,
                             "write_bytes": 464378624 + 2488418720},
     # one persistent run of the FFT batch (64 x 2^18), one k_epochs dispatch
     # (profiles/fft_64x2e18_and_2e20.md)
-    "k_epochs<FFT> batch": {"src": "4dc8a827326a2858", "wg": 1024, "fetch_bytes": 2022293248,
+    "k_epochs<FFT> batch": {"src": "01c3d1775ef2aa70", "wg": 1024, "fetch_bytes": 2022293248,
                             "write_bytes": 1764618272},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "4dc8a827326a2858", "wg": 512, "fetch_bytes": 175796320768 + 144625155840,
+    "k_epochs<GRAPH> sssp": {"src": "01c3d1775ef2aa70", "wg": 512, "fetch_bytes": 175796320768 + 144625155840,
                              "write_bytes": 3308267232 + 4360270912},
 }
 

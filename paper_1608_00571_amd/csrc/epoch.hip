@@ -2723,6 +2723,28 @@ hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int p
   return hipLaunchKernel(fn, dim3(grid), dim3(wg), args, 0, s);
 }
 
+// End of a captured chain of epochs: the header's first 64 bytes to the
+// host-mapped mirror, then the chain's number, written after the rest has
+// landed (one wavefront).
+// M: device address of the host-mapped mirror.
+__global__ __launch_bounds__(64) void k_publish_hdr(SchedHdr *H, HdrMirror *M) {
+  const int lane = threadIdx.x;
+  const uint32_t seq = ld_agent(&H->pub_seq) + 1u;
+  if (lane < 16)
+    __hip_atomic_store(&M->hdr[lane], ld_agent(&((const int32_t *)H)[lane]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  wait_vmem();
+  if (lane == 0) {
+    st_agent(&H->pub_seq, seq);
+    __hip_atomic_store(&M->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+hipError_t launch_publish_hdr(SchedHdr *hdr, HdrMirror *mirror_dev, hipStream_t s) {
+  void *args[] = {&hdr, &mirror_dev};
+  return hipLaunchKernel((const void *)&k_publish_hdr, dim3(1), dim3(64), args, 0, s);
+}
+
 hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s) {
   const void *fn = nullptr;
   switch (wg) {

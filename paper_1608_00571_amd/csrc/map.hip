@@ -19,10 +19,17 @@ __global__ __launch_bounds__(WG) void k_map_part(DevCtx C, uint32_t Jarg, int32_
   uint32_t J;
   uint64_t U;
   map_extent<TILE>(C, Jraw, &J, &U);
-  // Work-groups are dispatched round-robin over the 8 XCDs (block b on XCD
-  // b % 8).  Renumbered this way, each XCD searches a contiguous run of
-  // boundaries, whose shared upper probes then hit in its own L2.
-  const uint32_t G = gridDim.x;
+  // Only the work-groups that one boundary per wavefront needs take part
+  // (a captured chain launches a grid sized for the largest map).  Work-
+  // groups are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
+  // renumbered this way, each XCD searches a contiguous run of boundaries,
+  // whose shared upper probes then hit in its own L2, and every XCD gets
+  // an equal share.
+  const uint64_t nb = (U + TILE - 1) / TILE + 1;
+  const uint64_t need = (nb + WG / 64 - 1) / (WG / 64);
+  uint32_t G = gridDim.x;
+  if (G % 8 == 0 && need < G) G = (uint32_t)((need + 7) & ~(uint64_t)7);
+  if (blockIdx.x >= G) return;
   const uint32_t v = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
   map_partition<TILE>(C, J, U, (int64_t)v * (WG / 64) + (threadIdx.x >> 6), (int64_t)G * (WG / 64));
 }

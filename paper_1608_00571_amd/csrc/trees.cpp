@@ -28,6 +28,7 @@ hipError_t launch_epochs(const DevCtx &C, int wg, uint32_t need, int grid, int p
 hipError_t launch_map(const DevCtx &C, int wg, uint32_t jobs, int from_hdr, int grid_part, int grid_merge,
                       hipStream_t s, const hipEvent_t *ev);
 hipError_t launch_arcs(const DevCtx &C, int wg, uint32_t need, int grid, hipStream_t s);
+hipError_t launch_publish_hdr(SchedHdr *hdr, HdrMirror *mirror_dev, hipStream_t s);
 int coresident_blocks_per_cu(int wg, uint32_t need, int *scratch, int *own);
 hipError_t launch_scan(const DevCtx &C, hipStream_t s);
 hipError_t launch_admit(const DevCtx &C, const void *adm, int n, hipStream_t s);
@@ -48,6 +49,11 @@ constexpr int kBytesPerEntry = 28;   // code + a0..a3 (int32) + r (int64)
 constexpr int kMapJobs = 1 << 20;    // map jobs per epoch; merges beyond it run serially
 constexpr uint64_t kMapTileUnits = kMapLaunchTile;
 constexpr int kPartCap = 1 << 20;    // tile boundaries: 2^32 merged keys per epoch
+// Map grids of a captured chain, per CU (the job count is not known when the
+// chain is captured; both passes loop over their work, and a pass with no
+// jobs returns at once).
+constexpr int kGraphPartPerCU = 2;
+constexpr int kGraphMergePerCU = 4;
 
 std::string g_create_error;
 
@@ -216,6 +222,9 @@ struct trees_ctx {
   Admit *adm_host = nullptr;       // pinned staging
   Admit *adm_dev = nullptr;
   PlainMirror *mirror = nullptr;   // host-mapped, written after each plain epoch
+  HdrMirror *hmirror = nullptr;    // host-mapped, written after each captured chain
+  HdrMirror *hmirror_dev = nullptr;
+  uint32_t hseq = 0;               // captured chains launched (HdrMirror::seq of the last)
   uint32_t plain_seq = 0;
   DevCtx *self_dev = nullptr;      // device copies of dc (out-of-line device code reads them)
   DevCtx *self_host = nullptr;     // pinned staging for them
@@ -612,6 +621,7 @@ trees_status hdr_begin(trees_ctx *c, int64_t max_epochs, bool async = false) {
   c->hdr_host->ctail = 0;
   c->hdr_host->ctail_pub = 0;
   c->hdr_host->idle_t0 = 0;
+  c->hdr_host->pub_seq = c->hseq;   // the next chain publishes hseq + 1
   HIPCHK(c, hipMemcpyAsync(c->dc.hdr, c->hdr_host, sizeof(SchedHdr), hipMemcpyHostToDevice, c->stream));
   // the context's device copies (out-of-line device code reads them): as it
   // stands now (programs registered since the last run included), and its
@@ -673,7 +683,17 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
       hipError_t e = launch_epochs(c->dc, c->wg, need, grid, 0, c->stream);
       if (e == hipSuccess && (need & OPS_EXPAND)) e = launch_arcs(c->dc, c->wg, need, grid, c->stream);
       if (e == hipSuccess && c->dc.mj_cap > 0 && (need & OPS_MS))
-        e = launch_map(c->dc, kMapWG, 0, 1, c->ncu * 8, c->ncu * 8, c->stream, nullptr);
+        e = launch_map(c->dc, kMapWG, 0, 1, c->ncu * kGraphPartPerCU, c->ncu * kGraphMergePerCU, c->stream,
+                       nullptr);
+      if (e != hipSuccess) {
+        hipGraph_t g;
+        (void)hipStreamEndCapture(c->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, TREES_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+      }
+    }
+    {
+      const hipError_t e = launch_publish_hdr(c->dc.hdr, c->hmirror_dev, c->stream);
       if (e != hipSuccess) {
         hipGraph_t g;
         (void)hipStreamEndCapture(c->stream, &g);
@@ -691,10 +711,14 @@ trees_status run_graph(trees_ctx *c, int64_t max_epochs) {
     if (timed(c, 0)) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     if (timed(c, 0)) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-    s = read_hdr(c);
+    // the chain's last node publishes the header; poll for it
+    s = wait_seq(c, &c->hmirror->seq, ++c->hseq);
     if (s) return s;
+    for (int k = 0; k < 16; ++k)
+      ((int32_t *)c->hdr_host)[k] = __atomic_load_n(&c->hmirror->hdr[k], __ATOMIC_RELAXED);
     if (timed(c, 0)) {
       float ms = 0;
+      HIPCHK(c, hipEventSynchronize(c->ev1));
       HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
       c->ktime[0].ms += ms;
       c->ktime[0].launches += 1;
@@ -1071,6 +1095,8 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
       hipHostMalloc((void **)&c->abort_flag, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
       hipHostMalloc((void **)&c->wl_mirror, sizeof(WlMirror), hipHostMallocCoherent | hipHostMallocMapped) !=
           hipSuccess ||
+      hipHostMalloc((void **)&c->hmirror, sizeof(HdrMirror), hipHostMallocCoherent | hipHostMallocMapped) !=
+          hipSuccess ||
       hipHostMalloc((void **)&c->self_host, 2 * sizeof(DevCtx), hipHostMallocDefault) != hipSuccess)
     return bail(TREES_E_NOMEM, "hipHostMalloc failed");
   memset(c->wl_mirror, 0, sizeof(WlMirror));
@@ -1102,6 +1128,9 @@ trees_status trees_create(const trees_config *cfg, trees_ctx **out) {
   memset(c->mirror, 0, sizeof(PlainMirror));
   if (hipHostGetDevicePointer((void **)&c->dc.mirror, c->mirror, 0) != hipSuccess)
     return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
+  memset(c->hmirror, 0, sizeof(HdrMirror));
+  if (hipHostGetDevicePointer((void **)&c->hmirror_dev, c->hmirror, 0) != hipSuccess)
+    return bail(TREES_E_DEVICE, "hipHostGetDevicePointer failed");
   c->profile = (cfg->flags & TREES_F_PROFILE) != 0;
   if (c->profile && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess))
     return bail(TREES_E_DEVICE, "hipEventCreate failed");
@@ -1123,6 +1152,7 @@ void trees_destroy(trees_ctx *c) {
   if (c->ctl) (void)hipFree(c->ctl);
   if (c->adm_host) (void)hipHostFree(c->adm_host);
   if (c->mirror) (void)hipHostFree(c->mirror);
+  if (c->hmirror) (void)hipHostFree(c->hmirror);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   if (c->hdr_host) (void)hipHostFree(c->hdr_host);
   if (c->st_host) (void)hipHostFree(c->st_host);

@@ -8,6 +8,7 @@
 // Each tree owns a contiguous arena [base, base + cap) of the task vector;
 // all indices stored inside the task vector are arena-relative.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime.h>
 
@@ -122,7 +123,8 @@ struct SchedHdr {
   uint32_t ctail;       // asynchronous run: completion records written so far
   uint32_t ctail_pub;   // asynchronous run: completion records published to the host
   int64_t idle_t0;      // asynchronous run: device clock when no tree was left live (0: busy)
-  int32_t pad0[8];
+  uint32_t pub_seq;     // captured chains published to the host mirror (HdrMirror::seq)
+  int32_t pad0[7];
   alignas(128) uint32_t arrive;   // barrier arrivals of the last work-group of each group
   int32_t pad1[31];
   struct alignas(128) Grp { uint32_t n; int32_t pad[31]; } grp[8];   // per-group arrivals (blockIdx % 8)
@@ -217,6 +219,17 @@ struct PlainMirror {
   uint32_t seq;
   uint32_t pad;
 };
+
+// Host-visible copy of the header's first 64 bytes (S .. adm_head), written
+// at the end of each captured chain of epochs; `seq` is written last and
+// counts the chains, so the host polls it instead of copying the header back
+// and synchronising the stream.
+struct HdrMirror {
+  int32_t hdr[16];
+  uint32_t seq;
+  uint32_t pad[15];
+};
+static_assert(offsetof(SchedHdr, ctail) == sizeof(HdrMirror::hdr), "the mirrored part of the header");
 
 // ---------------------------------------------------------------------------
 // Asynchronous runs (TREES_RUN_ASYNC): trees submitted while a persistent
