@@ -1467,8 +1467,9 @@ __device__ __forceinline__ void wave_cooperative(const DevCtx &C, const int *seg
 template <int K>
 __device__ __forceinline__ void write_task(int32_t *code, int32_t *a0, int32_t *a1, int32_t *a2, int32_t *a3, int64_t *r,
                                            int op, int act, int nk, int32_t cb, int32_t e, int32_t nxt, int32_t own,
-                                           uint32_t tp, int64_t val, int32_t x0, int32_t x1, int32_t x2, int32_t x3) {
-  if (nk > 0 && cb >= 0) {
+                                           uint32_t tp, int64_t val, int32_t x0, int32_t x1, int32_t x2, int32_t x3,
+                                           bool kids = true) {
+  if (kids && nk > 0 && cb >= 0) {
     const int32_t c = cb;
     if (op == OP_FIB32 || op == OP_FIB64) {
       code[c] = nxt; a0[c] = x0 - 1;
@@ -1508,6 +1509,55 @@ __device__ __forceinline__ void write_task(int32_t *code, int32_t *a0, int32_t *
     if (op != OP_MS && op != OP_POST) {   // (their joins keep their own arguments)
       a0[e] = cb;
       if (op == OP_Q) a1[e] = nk;
+    }
+  }
+}
+
+// The N-queens children of a single-tree step, written with consecutive
+// lanes on consecutive entries: the step's children fill one block from
+// base (slot k's children from kb[k], lane by lane, each lane's nk[k] of
+// them from off[k]); each output position finds its parent lane by a
+// binary search over the lanes' running totals and takes the parent's
+// board from it, and the child's column is the parent's r-th free one
+// (r: the position's rank among the parent's children), as the lane-serial
+// writer takes them in increasing order.
+template <int IT>
+__device__ __forceinline__ void write_q_children(int32_t *code, int32_t *a0, int32_t *a1, int32_t *a2, int32_t *a3,
+                                                 int32_t base, const int *off, const int *nk, const int *kb,
+                                                 const int32_t *x0, const int32_t *x1, const int32_t *x2,
+                                                 const int32_t *x3, int32_t nxt, uint32_t tp) {
+  const int lane = lane_id();
+  const int32_t n = (int32_t)(tp >> 8);
+  const uint32_t full = (1u << n) - 1u;
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int incl = off[k] + nk[k];   // the end of this lane's children
+    for (int p0 = kb[k]; p0 < kb[k + 1]; p0 += 64) {
+      const int p = p0 + lane;
+      // the first lane whose children end after p (every lane searches, so
+      // that every lane's register is there to be read)
+      int lo = 0, hi = 63;
+#pragma unroll
+      for (int st = 0; st < 6; ++st) {
+        const int mid = (lo + hi) >> 1;
+        if (__shfl(incl, mid, 64) > p) hi = mid; else lo = mid + 1;
+      }
+      const int l = min(lo, 63);
+      const int r = p - __shfl(off[k], l, 64);
+      const int32_t row = __shfl(x0[k], l, 64);
+      const uint32_t cols = (uint32_t)__shfl(x1[k], l, 64);
+      const uint32_t ld = (uint32_t)__shfl(x2[k], l, 64), rd = (uint32_t)__shfl(x3[k], l, 64);
+      if (p < kb[k + 1]) {
+        uint32_t avail = ~(cols | ld | rd) & full;
+        for (int i = 0; i < r; ++i) avail &= avail - 1u;
+        const uint32_t bit = avail & (0u - avail);
+        const int32_t c = base + p;
+        code[c] = nxt;
+        a0[c] = row + 1;
+        a1[c] = (int32_t)(cols | bit);
+        a2[c] = (int32_t)(((ld | bit) << 1) & full);
+        a3[c] = (int32_t)((rd | bit) >> 1);
+      }
     }
   }
 }
@@ -1577,11 +1627,12 @@ __device__ void wave_step_tree(const DevCtx &C, WaveLds &W, const uint8_t *op_ta
     wave_cooperative<OPS, IT>(C, seg, sl, op, tpk, a0v, nk, leaf, want_map, x0, x1, x2);
   }
   // fork: the wavefront's children in one block of the tree's arena
-  int off[IT];
+  int off[IT], kb[IT + 1];
   int run = 0, joins = 0, valid = 0;
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     int tot;
+    kb[k] = run;
     off[k] = run + wave_prefix_small<4>(nk[k], &tot);
     run += tot;
     joins += __popcll(ballot64(act[k] == ACT_JOIN));
@@ -1598,13 +1649,20 @@ __device__ void wave_step_tree(const DevCtx &C, WaveLds &W, const uint8_t *op_ta
     }
     base = __builtin_amdgcn_readfirstlane(base);
   }
+  kb[IT] = run;
   const int32_t nxt = (cen + 1) * ntt + t1;   // local type 1, next epoch
   const int32_t own = lo_code + t1 + 1;       // local type 2, this epoch
+  // N-queens children go out coalesced; the others' with their own entries
+  const bool qkids = (OPS & opbit(OP_Q)) != 0 && pop == OP_Q;
+  if constexpr ((OPS & opbit(OP_Q)) != 0) {
+    if (qkids && base >= 0 && run > 0)
+      write_q_children<IT>(code, pa0, pa1, pa2, pa3, base, off, nk, kb, x0, x1, x2, x3, nxt, tp);
+  }
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     const int32_t cb = nk[k] == 0 ? 0 : (base < 0 ? -1 : base + off[k]);
     write_task<0>(code, pa0, pa1, pa2, pa3, pr, op[k], act[k], nk[k], cb, e[k], nxt, own, tp, val[k], x0[k], x1[k],
-                  x2[k], x3[k]);
+                  x2[k], x3[k], !qkids);
   }
   // retirement: counted into the tree when the run moves on
   if (lane == 0) {
