@@ -98,6 +98,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1608_00571_amd.build`")
+        # torch carries its own ROCm runtime beside the system one this
+        # library links; torch's must be loaded first (loaded the other way
+        # round, a context's hipSetDevice fails once torch has used the GPU)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         i32, i64, u64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
         L.trees_create.restype = i32

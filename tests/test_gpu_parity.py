@@ -43,6 +43,28 @@ def test_nqueens(sched):
         assert_matches_oracle(j)
 
 
+@pytest.mark.parametrize("sched", ["graph", "persistent"])
+@pytest.mark.parametrize("wg", [256, 512, 1024])
+def test_nqueens_wide_boards(sched, wg):
+    """Boards of 12 to 14 columns: up to 14 children per task, so a
+    wavefront step's children span many 64-entry rows of its block (the
+    single-tree step writes them with consecutive lanes on consecutive
+    entries); a fib tree beside them keeps the other program in the kernel."""
+    import paper_1608_00571_amd as T
+    jobs = [Job("nqueens", n) for n in (12, 13, 14)] + [Job("fib64", 20)]
+    arena = (sum(T.tv_bound(T.NQUEENS, [n]) for n in (12, 13, 14)) + T.tv_bound(T.FIB_I64, [20]) + 4096) \
+        * T.BYTES_PER_ENTRY
+    with T.Context(arena, sched=sched, wg=wg, timeout_s=20.0) as ctx:
+        register_all(ctx, jobs)
+        for j in jobs:
+            j.submit(ctx)
+        ctx.run()
+        for j in jobs:
+            j.collect(ctx)
+    for j in jobs:
+        assert_matches_oracle(j, check_trace=False)
+
+
 MSORT_SIZES = [0, 1, 2, 63, 64, 65, 129, 1000, 4096, (1 << 16) + 3]
 
 
