@@ -47,24 +47,24 @@ def log(msg: str):
 # `bench.py --calib-copy`), for the kernel sources with the given digest.  A
 # source change makes the figure stale, and it is then reported as null.
 MEASURED_TRAFFIC = {   # profiles/plain_fib32_msort2e24.md
-    "k_map_merge<1024,8192>": {"src": "a3c1221125ea595c", "fetch_bytes": 68794581, "write_bytes": 67108864},
-    "k_plain<FIB>": {"src": "1e02a739f0990e68", "fetch_bytes": 2817242, "write_bytes": 3510457},
-    "k_plain<MS>": {"src": "1e02a739f0990e68", "fetch_bytes": 2245312, "write_bytes": 2355262},
+    "k_map_merge<1024,8192>": {"src": "a3c1221125ea595c", "fetch_bytes": 68794794, "write_bytes": 67108864},
+    "k_plain<FIB>": {"src": "1e02a739f0990e68", "fetch_bytes": 2812957, "write_bytes": 3510431},
+    "k_plain<MS>": {"src": "1e02a739f0990e68", "fetch_bytes": 2243668, "write_bytes": 2355210},
     # one persistent run of the 4096-tree batch (profiles/batched_4096trees_fib_nqueens.md)
     "k_epochs<FIB|NQ>": {"src": "1e02a739f0990e68", "wg": 512, "fetch_bytes": 10741529088,
                          "write_bytes": 12627534720},
     # one graph-form run of the 64-graph BFS batch, k_epochs and k_arcs together
     # (profiles/batched_64rmat_bfs.md)
-    "k_epochs<GRAPH> bfs": {"src": "1e02a739f0990e68", "wg": 512, "fetch_bytes": 19833428352 + 81570876928,
-                            "write_bytes": 464378624 + 2488418720},
+    "k_epochs<GRAPH> bfs": {"src": "1e02a739f0990e68", "wg": 512, "fetch_bytes": 20028926720 + 81312432256,
+                            "write_bytes": 464622720 + 2482833728},
     # one persistent run of the FFT batch (64 x 2^18), one k_epochs dispatch
     # (profiles/fft_64x2e18_and_2e20.md)
-    "k_epochs<FFT> batch": {"src": "1e02a739f0990e68", "wg": 1024, "fetch_bytes": 2022293248,
-                            "write_bytes": 1764618272},
+    "k_epochs<FFT> batch": {"src": "1e02a739f0990e68", "wg": 1024, "fetch_bytes": 1903887872,
+                            "write_bytes": 1764621824},
     # one graph-form run of the 64-graph SSSP batch, k_epochs and k_arcs together
     # (profiles/sssp_64rmat_weighted.md)
-    "k_epochs<GRAPH> sssp": {"src": "1e02a739f0990e68", "wg": 512, "fetch_bytes": 175796320768 + 144625155840,
-                             "write_bytes": 3308267232 + 4360270912},
+    "k_epochs<GRAPH> sssp": {"src": "1e02a739f0990e68", "wg": 512, "fetch_bytes": 174533754368 + 140109007232,
+                             "write_bytes": 3394525792 + 4234848480},
 }
 
 
