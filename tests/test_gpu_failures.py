@@ -165,3 +165,30 @@ def test_traversal_log_cleared_after_pending_fill(kind):
         assert int(out[n]) == n
         assert sorted(out[:n].tolist()) == list(range(n))
         assert np.all(log2.cpu().numpy() == 5)
+
+
+def test_library_loaded_before_torch_uses_the_gpu():
+    """The library loaded before torch has touched the GPU (a host-only call
+    first), then torch allocates, then a context runs a tree: the binding
+    loads torch's runtime ahead of the library, so this order works too.
+    Run in a fresh process, where nothing has loaded either yet."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1608_00571_amd as T\n"
+        "need = T.tv_bound(T.FIB_I64, [15])\n"
+        "import torch\n"
+        "x = torch.zeros(16, device='cuda')\n"
+        "with T.Context((need + 4096) * T.BYTES_PER_ENTRY, sched='graph', timeout_s=20.0) as c:\n"
+        "    p = c.register(T.FIB_I64)\n"
+        "    t = c.submit(p, [15])\n"
+        "    c.run()\n"
+        "    v, st = c.results(t)\n"
+        "assert v == 610, v\n"
+        "print('ok', v)\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "ok 610" in r.stdout
